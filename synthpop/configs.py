@@ -1,0 +1,95 @@
+"""Parameter sets of the five workloads (plain small, plain at paper scale, plain at
+50M agents, batched ensemble, differentiable calibration).
+
+Every value is a model parameter, not code: the oracle and the GPU library each take
+this flat dict and compute on their own.  Readings of the paper that fix a value are
+noted beside it (section 3, eqs. 1-2; section 4; section 5).
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+from .population import make_population, replicate_population, N_AGE, N_OCC
+
+MODE_HARD, MODE_SOFT = 0, 1
+STRAT_STANDARD, STRAT_DELAYED, STRAT_DELAYED_EXCEPT_65 = 0, 1, 2
+
+BASE = dict(
+    seed=0,                     # Philox key = (seed & 0xffffffff, seed >> 32)
+    dt=1.0,                     # one step is one day
+    kappa=1.0 / 11.0,           # 1 / I-bar of eq. 1 (nominal mean daily in-degree)
+    gamma_shape=2.5, gamma_scale=2.0,    # infectiousness profile (mean 5 d, var 10 d^2)
+    A_stage=[0.0, 1.0, 1.0, 0.0, 0.0],   # per-stage factor for S, E, I, R, M infectors
+    w_household=1.0, w_occupation=0.2, w_random=0.2,   # network factor B_n
+    mu_random=[4.84] * N_AGE,            # mean daily random in-degree per age group
+    mu_occupation=[4.0] * N_OCC,         # mean daily workplace in-degree per occupation
+    p_death=[0.05 * a / 8.0 for a in range(N_AGE)],
+    e_days=5, i_days=10,
+    quarantine_days=0, test_delay=2, quarantine_dropout=0.0,
+    test_rate=0.0, test_sensitivity=0.95,
+    vacc_rate=0.0, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12,
+    strategy=STRAT_STANDARD,
+    mode=MODE_HARD, gumbel_tau=0.5, checkpoint_every=10,
+    n_steps=180,
+    edge_capacity=0,
+)
+
+INTERVENTIONS = dict(quarantine_days=14, test_delay=2, test_rate=0.05, test_sensitivity=0.95,
+                     vacc_rate=0.005, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12)
+
+WORKLOADS = {
+    0: dict(name="plain-1k", n=1000, workplaces=False, n_seeds=10, T=30,
+            params=dict(kappa=1.0 / 12.16, mu_random=[10.0] * N_AGE,
+                        mu_occupation=[0.0] * N_OCC, w_occupation=0.0)),
+    1: dict(name="plain-100k", n=100_000, workplaces=True, n_seeds=10, T=180,
+            params=dict(INTERVENTIONS, kappa=1.0 / 11.0)),
+    2: dict(name="plain-50M", n=50_000_000, workplaces=True, n_seeds=5000, T=180,
+            params=dict(INTERVENTIONS, kappa=1.0 / 20.0, mu_random=[13.84] * N_AGE)),
+    3: dict(name="batched-256", n=None, workplaces=True, n_seeds=10, T=180,
+            params=dict(INTERVENTIONS, kappa=1.0 / 11.0)),
+    4: dict(name="calib-100k", n=100_000, workplaces=True, n_seeds=10, T=180,
+            params=dict(kappa=1.0 / 11.0, mode=MODE_SOFT, gumbel_tau=0.5,
+                        checkpoint_every=10)),
+}
+
+
+def params_for(k: int, **overrides) -> dict:
+    p = copy.deepcopy(BASE)
+    p.update(copy.deepcopy(WORKLOADS[k]["params"]))
+    p["n_steps"] = WORKLOADS[k]["T"]
+    p.update(overrides)
+    return p
+
+
+def ensemble_draws(n_rep: int = 256, seed: int = 3000):
+    """Per-replicate sizes (log-uniform 1e4..5e5), R ~ U[3,7], dose-2 delay in
+    {21, 42, 84} for the batched ensemble."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 3])))
+    sizes = np.rint(np.exp(rng.uniform(np.log(1e4), np.log(5e5), size=n_rep))).astype(np.int64)
+    R = rng.uniform(3.0, 7.0, size=n_rep).astype(np.float32)
+    delay = rng.choice(np.array([21, 42, 84], np.int32), size=n_rep)
+    return sizes, R, delay
+
+
+def workload(k: int, n: int | None = None, n_rep: int | None = None, pop_seed: int | None = None,
+             **overrides):
+    """(params, population) of workload ``k``; ``n`` shrinks the population (tests)."""
+    w = WORKLOADS[k]
+    p = params_for(k, **overrides)
+    ps = 1000 + k if pop_seed is None else pop_seed
+    if k == 3:
+        nr = 256 if n_rep is None else n_rep
+        sizes, R, delay = ensemble_draws(nr)
+        if n is not None:      # shrink every replicate proportionally (tests)
+            sizes = np.maximum(64, (sizes * (n / sizes.sum())).astype(np.int64))
+        pop = make_population(sizes, workplaces=True, n_seeds=w["n_seeds"], pop_seed=ps,
+                              seed_seed=2000 + k, R=R, dose2_delay=delay)
+        return p, pop
+    N = w["n"] if n is None else n
+    pop = make_population([N], workplaces=w["workplaces"], n_seeds=w["n_seeds"],
+                          pop_seed=ps, seed_seed=2000 + k)
+    if n_rep:
+        pop = replicate_population(pop, n_rep)
+    return p, pop
