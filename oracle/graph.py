@@ -51,9 +51,12 @@ def static_maps(pop):
     wp_size = np.zeros(N, np.int64)
     wp_lo[has] = wps[wp_of[has]]
     wp_size[has] = wsz[wp_of[has]]
+    nrep = pop.agent_offset.size - 1
+    words = np.arange(nrep, dtype=np.int64) if getattr(pop, "stream", None) is None \
+        else np.asarray(pop.stream, np.int64)
     return dict(hh_lo=hs[hh_id], hh_hi=hs[hh_id + 1], wp_of=wp_of, wp_pos=wp_pos,
-                wp_lo=wp_lo, wp_size=wp_size,
-                rep=rep, local=np.arange(N) - np.asarray(pop.agent_offset)[rep])
+                wp_lo=wp_lo, wp_size=wp_size, rep=rep, stream=words[rep],
+                local=np.arange(N) - np.asarray(pop.agent_offset)[rep])
 
 
 def daily_draws(pop, params, t, maps=None, agents=None):
@@ -67,7 +70,7 @@ def daily_draws(pop, params, t, maps=None, agents=None):
     N = int(pop.agent_offset[-1])
     ids = np.arange(N) if agents is None else np.asarray(agents, np.int64)
     seed = int(params["seed"])
-    rep, loc = maps["rep"][ids], maps["local"][ids]
+    rep, loc, word = maps["rep"][ids], maps["local"][ids], maps["stream"][ids]
     nrep = np.diff(np.asarray(pop.agent_offset))[rep]
     off_rep = np.asarray(pop.agent_offset)[rep]
     mem = np.asarray(pop.wp_members, np.int64)
@@ -82,7 +85,7 @@ def daily_draws(pop, params, t, maps=None, agents=None):
             cls = np.asarray(pop.age, np.int64)[ids]
             m = nrep
         tabs = [poisson_thresholds(float(x) / 2.0) for x in mu]
-        w0 = philox.lane(seed, loc, t, rep, purpose, 0)
+        w0 = philox.lane(seed, loc, t, word, purpose, 0)
         k = np.zeros(ids.size, np.int64)
         for c in range(mu.size):
             sel = cls == c
@@ -92,7 +95,7 @@ def daily_draws(pop, params, t, maps=None, agents=None):
         inits, draws, partners = [], [], []
         for d in range(1, int(k.max(initial=0)) + 1):
             s = np.flatnonzero(k >= d)
-            x = philox.lane(seed, loc[s], t, rep[s], purpose, d).astype(np.uint64)
+            x = philox.lane(seed, loc[s], t, word[s], purpose, d).astype(np.uint64)
             mm = m[s].astype(np.uint64)
             off = ((x * (mm - np.uint64(1))) >> np.uint64(32)).astype(np.int64)
             if net == "occ":
@@ -176,6 +179,8 @@ def build_graph_naive(pop, params, t):
             h += 1
         rowsl[j][BLK_HH] = [i for i in range(hs[h], hs[h + 1]) if i != j]
     contacts = []          # (network, initiator, draw, partner)
+    words = list(range(len(off) - 1)) if getattr(pop, "stream", None) is None \
+        else [int(x) for x in pop.stream]
     for r in range(len(off) - 1):
         n = off[r + 1] - off[r]
         for loc in range(n):
@@ -184,14 +189,14 @@ def build_graph_naive(pop, params, t):
                 w, pos = where[i]
                 m = wps[w + 1] - wps[w]
                 tab = thr(float(params["mu_occupation"][int(pop.occupation[i])]) / 2.0)
-                k = count(word(loc, r, philox.PURPOSE_OCC, 0), tab) if m >= 2 else 0
+                k = count(word(loc, words[r], philox.PURPOSE_OCC, 0), tab) if m >= 2 else 0
                 for d in range(1, k + 1):
-                    o = (word(loc, r, philox.PURPOSE_OCC, d) * (m - 1)) >> 32
+                    o = (word(loc, words[r], philox.PURPOSE_OCC, d) * (m - 1)) >> 32
                     contacts.append((0, i, d, mem[wps[w] + (pos + 1 + o) % m]))
             tab = thr(float(params["mu_random"][int(pop.age[i])]) / 2.0)
-            k = count(word(loc, r, philox.PURPOSE_RAND, 0), tab) if n >= 2 else 0
+            k = count(word(loc, words[r], philox.PURPOSE_RAND, 0), tab) if n >= 2 else 0
             for d in range(1, k + 1):
-                o = (word(loc, r, philox.PURPOSE_RAND, d) * (n - 1)) >> 32
+                o = (word(loc, words[r], philox.PURPOSE_RAND, d) * (n - 1)) >> 32
                 contacts.append((1, i, d, off[r] + (loc + 1 + o) % n))
     for net, i, _d, p in sorted(contacts):
         own, recv = (BLK_OCC_OWN, BLK_OCC_RECV) if net == 0 else (BLK_RAND_OWN, BLK_RAND_RECV)

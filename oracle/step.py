@@ -74,6 +74,7 @@ class Model:
         self.N = int(pop.agent_offset[-1])
         self.rep = self.maps["rep"]
         self.loc = self.maps["local"]
+        self.word = self.maps["stream"]          # Philox stream word of each agent's replicate
         self.nrep = int(pop.agent_offset.size - 1)
         self.sizes = np.diff(np.asarray(pop.agent_offset))
         p = self.p
@@ -114,7 +115,7 @@ class Model:
     def uniforms(self, t, purpose, ids=None, day=None):
         ids = np.arange(self.N) if ids is None else ids
         d = t if day is None else day
-        w = philox.draw_words(int(self.p["seed"]), self.loc[ids], d, self.rep[ids], purpose, 0)
+        w = philox.draw_words(int(self.p["seed"]), self.loc[ids], d, self.word[ids], purpose, 0)
         return [philox.uniform(x) for x in w]
 
     def codes(self, st, t):
@@ -133,7 +134,7 @@ class Model:
         if not has1.any():
             return out
         ids = np.flatnonzero(has1)
-        w = philox.draw_words(int(p["seed"]), self.loc[ids], st["d1"][ids], self.rep[ids],
+        w = philox.draw_words(int(p["seed"]), self.loc[ids], st["d1"][ids], self.word[ids],
                               philox.PURPOSE_VACC, 0)
         u = philox.uniform(w[0])
         lag = int(p["dose_lag"])

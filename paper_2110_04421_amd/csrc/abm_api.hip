@@ -1,0 +1,751 @@
+// Host runtime and C ABI of libabm: parameter and population validation, workspace
+// layout, per-run tables (Gamma infectiousness integral of eq. 1, Poisson thresholds,
+// vaccination priority classes of Table 1), the HIP-graph day loop, and the adjoint
+// driver of the relaxed (soft) mode.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abm_internal.h"
+
+using namespace abm;
+
+namespace {
+
+// ---- tables --------------------------------------------------------------------------
+// Regularised lower incomplete gamma P(a, x) from its power series
+//   P(a, x) = x^a e^-x sum_n x^n / Gamma(a + n + 1).
+double gamma_lower_reg(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  double term = std::exp(a * std::log(x) - x - std::lgamma(a + 1.0));
+  double sum = term;
+  for (int n = 1; n < 100000; ++n) {
+    term *= x / (a + n);
+    sum += term;
+    if (term < 1e-18 * sum && n > x) break;
+  }
+  return std::min(sum, 1.0);
+}
+
+// Atab[tau] = A_{stage(tau)} * integral of the Gamma(shape, scale) density over the
+// day [tau - 1, tau] since exposure; exposed for tau <= e_days, infected until
+// e_days + i_days, nothing afterwards (eq. 1).
+void build_atab(const abm_params& p, float* out) {
+  for (int t = 0; t < ATAB; ++t) out[t] = 0.f;
+  for (int t = 1; t <= p.e_days + p.i_days; ++t) {
+    const double ph = gamma_lower_reg(p.gamma_shape, t / p.gamma_scale) -
+                      gamma_lower_reg(p.gamma_shape, (t - 1) / p.gamma_scale);
+    const double A = t <= p.e_days ? p.A_stage[ABM_STAGE_E] : p.A_stage[ABM_STAGE_I];
+    out[t] = (float)(A * ph);
+  }
+}
+
+// Poisson(m) inverse-CDF thresholds: T_k = min(floor(F_k 2^32), 2^32 - 1), with the CDF
+// accumulated left to right from pmf_0 = e^-m, pmf_k = pmf_{k-1} m / k.
+void build_poisson(double m, uint32_t* T) {
+  double pmf = std::exp(-m), F = pmf;
+  for (int k = 0; k < 64; ++k) {
+    if (k) {
+      pmf = pmf * m / k;
+      F = F + pmf;
+    }
+    const double v = std::floor(F * 4294967296.0);
+    T[k] = v >= 4294967295.0 ? 4294967295u : (uint32_t)v;
+  }
+}
+
+// Priority class (0 = first) of (dose, age group) under a strategy of Table 1.
+int priority_class(int strategy, int dose, int age) {
+  switch (strategy) {
+    case ABM_STRATEGY_STANDARD: return (dose == 2 ? 0 : 9) + (8 - age);
+    case ABM_STRATEGY_DELAYED: return (dose == 1 ? 0 : 9) + (8 - age);
+    default:
+      if (age >= 6) return 2 * (8 - age) + (dose == 1 ? 0 : 1);
+      return 6 + (dose == 1 ? 0 : 6) + (5 - age);
+  }
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t total = 0;
+  template <typename T>
+  size_t take(size_t n) {
+    const size_t off = total;
+    total = align_up(total + n * sizeof(T));
+    return off;
+  }
+};
+
+struct Offsets {
+  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, lambda, own, recv, row_ptr,
+      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, counts_day, prev_counts,
+      traj, day, flags, seeds;
+  size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
+      gtheta, gpart, dL;
+};
+
+struct Sizes {
+  int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
+  int64_t seg = 0, nckpt = 0;
+};
+
+}  // namespace
+
+struct abm_sim {
+  abm_params p{};
+  Sizes z;
+  Offsets o{};
+  Dev d{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int err = ABM_OK;
+  std::string msg;
+  int32_t host_day = 0;
+  bool soft_ready = false;
+  std::vector<RepInfo> reps;
+  char* ws = nullptr;
+  // profiling
+  static constexpr int NK = 9;
+  hipEvent_t ev[NK + 1] = {};
+  double ms[NK] = {};
+  int64_t launches[NK] = {};
+
+  int fail(int code, const char* fmt, ...) {
+    if (err == ABM_OK) {
+      char buf[512];
+      va_list ap;
+      va_start(ap, fmt);
+      vsnprintf(buf, sizeof buf, fmt, ap);
+      va_end(ap);
+      err = code;
+      msg = buf;
+    }
+    return err;
+  }
+};
+
+static const char* kKernelNames[abm_sim::NK] = {"pre",  "vplan",   "count", "scan",    "fill",
+                                                 "canon", "message", "fused", "finalize"};
+
+#define HIPCHK(s, x)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) return (s)->fail(ABM_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::string& why) {
+  auto bad = [&](const char* w) {
+    why = w;
+    return ABM_E_ARG;
+  };
+  if (!p || !pop) return bad("null params or population");
+  if (p->struct_size != sizeof(abm_params) || p->abi_version != ABM_ABI_VERSION) {
+    why = "abm_params struct_size/abi_version mismatch";
+    return ABM_E_ABI;
+  }
+  if (pop->n_replicates < 1) return bad("n_replicates < 1");
+  if (!pop->agent_offset || !pop->age || !pop->hh_start || !pop->occupation || !pop->R ||
+      !pop->susceptibility || !pop->dose2_delay || !pop->init_offset)
+    return bad("missing population array");
+  if (p->n_steps < 1 || p->n_steps > 32000) return bad("n_steps out of range [1, 32000]");
+  if (p->mode != ABM_HARD && p->mode != ABM_SOFT) return bad("mode");
+  if (!(p->dt > 0.f)) return bad("dt <= 0");
+  if (p->e_days < 1 || p->i_days < 1 || p->e_days + p->i_days > ATAB - 1 ||
+      p->e_days + p->i_days >= WIN)
+    return bad("e_days/i_days out of range (sum <= 15)");
+  if (!(p->gamma_shape > 0) || !(p->gamma_scale > 0)) return bad("gamma parameters");
+  for (int k = 0; k < ABM_N_AGE; ++k)
+    if (!(p->mu_random[k] >= 0 && p->mu_random[k] <= 40)) return bad("mu_random out of [0, 40]");
+  for (int k = 0; k < ABM_N_OCC; ++k)
+    if (!(p->mu_occupation[k] >= 0 && p->mu_occupation[k] <= 40)) return bad("mu_occupation out of [0, 40]");
+  if (p->test_rate > 0.f && p->test_delay < 1) return bad("test_delay must be >= 1");
+  if (p->quarantine_days < 0 || p->quarantine_days > 10000) return bad("quarantine_days");
+  if (p->dose_lag < 0 || p->dose_lag > 10000) return bad("dose_lag");
+  if (p->strategy < 0 || p->strategy > 2) return bad("strategy");
+  if (!(p->vacc_rate >= 0 && p->vacc_rate <= 1)) return bad("vacc_rate");
+  if (p->mode == ABM_SOFT) {
+    if (!(p->gumbel_tau > 0.f)) return bad("gumbel_tau <= 0");
+    if (p->checkpoint_every < 1) return bad("checkpoint_every < 1");
+  }
+  const int R = pop->n_replicates;
+  if (pop->agent_offset[0] != 0) return bad("agent_offset[0] != 0");
+  for (int r = 0; r < R; ++r)
+    if (pop->agent_offset[r + 1] <= pop->agent_offset[r]) return bad("empty or decreasing replicate");
+  const int64_t N = pop->agent_offset[R];
+  if (N >= (int64_t)1 << 31) return bad("more than 2^31 - 1 agents");
+  z.N = N;
+  z.R = R;
+  z.T = p->n_steps;
+  for (int64_t i = 0; i < N; ++i) {
+    if (pop->age[i] >= ABM_N_AGE) return bad("age group out of range");
+    if (pop->occupation[i] >= ABM_N_OCC) return bad("occupation out of range");
+  }
+  if (pop->n_households < 1 || pop->hh_start[0] != 0 || pop->hh_start[pop->n_households] != N)
+    return bad("hh_start must run from 0 to N");
+  {
+    int r = 0;
+    for (int h = 0; h < pop->n_households; ++h) {
+      const int64_t a = pop->hh_start[h], b = pop->hh_start[h + 1];
+      if (b <= a || b - a > 255) return bad("household size must be 1..255");
+      while (a >= pop->agent_offset[r + 1]) ++r;
+      if (b > pop->agent_offset[r + 1]) return bad("household crosses a replicate boundary");
+    }
+  }
+  if (pop->n_workplaces < 0) return bad("n_workplaces < 0");
+  if (pop->n_workplaces > 0) {
+    if (!pop->wp_start || !pop->wp_members) return bad("missing workplace arrays");
+    if (pop->wp_start[0] != 0) return bad("wp_start[0] != 0");
+    for (int w = 0; w < pop->n_workplaces; ++w) {
+      const int64_t m = (int64_t)pop->wp_start[w + 1] - pop->wp_start[w];
+      if (m < 1 || m > 65535) return bad("workplace size must be 1..65535");
+    }
+    z.M = pop->wp_start[pop->n_workplaces];
+  }
+  for (int r = 0; r < R; ++r) {
+    if (!(pop->R[r] >= 0.f) || !std::isfinite(pop->R[r])) return bad("R must be finite >= 0");
+    for (int a = 0; a < ABM_N_AGE; ++a)
+      if (!(pop->susceptibility[r * ABM_N_AGE + a] >= 0.f) ||
+          !std::isfinite(pop->susceptibility[r * ABM_N_AGE + a]))
+        return bad("susceptibility must be finite >= 0");
+    if (pop->dose2_delay[r] < 0 || pop->dose2_delay[r] > 10000) return bad("dose2_delay");
+    if (pop->init_offset[r + 1] < pop->init_offset[r]) return bad("init_offset decreasing");
+  }
+  if (pop->init_offset[0] != 0) return bad("init_offset[0] != 0");
+  z.nseeds = pop->init_offset[R];
+  if (z.nseeds > 0 && !pop->initial_infected) return bad("missing initial_infected");
+  for (int r = 0; r < R; ++r)
+    for (int64_t k = pop->init_offset[r]; k < pop->init_offset[r + 1]; ++k) {
+      const int64_t i = pop->initial_infected[k];
+      if (i < pop->agent_offset[r] || i >= pop->agent_offset[r + 1])
+        return bad("initial infection outside its replicate");
+    }
+  z.ntiles = 0;
+  for (int r = 0; r < R; ++r) z.ntiles += (pop->agent_offset[r + 1] - pop->agent_offset[r] + TILE - 1) / TILE;
+  z.nscan = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  // Edge room: mean directed edges + 8 standard deviations of the Poisson contact count.
+  double hh_edges = 0;
+  for (int h = 0; h < pop->n_households; ++h) {
+    const double s = (double)pop->hh_start[h + 1] - pop->hh_start[h];
+    hh_edges += s * (s - 1);
+  }
+  std::vector<uint16_t> wpn(N, 0);
+  for (int w = 0; w < pop->n_workplaces; ++w)
+    for (int64_t q = pop->wp_start[w]; q < pop->wp_start[w + 1]; ++q) {
+      const int64_t a = pop->wp_members[q];
+      if (a < 0 || a >= N) return bad("workplace member out of range");
+      wpn[a] = (uint16_t)(pop->wp_start[w + 1] - pop->wp_start[w]);
+    }
+  double cmean = 0;
+  for (int r = 0; r < R; ++r) {
+    const int64_t lo = pop->agent_offset[r], hi = pop->agent_offset[r + 1];
+    for (int64_t i = lo; i < hi; ++i) {
+      if (wpn[i] >= 2) cmean += p->mu_occupation[pop->occupation[i]] / 2.0;
+      if (hi - lo >= 2) cmean += p->mu_random[pop->age[i]] / 2.0;
+    }
+  }
+  const double emean = hh_edges + 2 * cmean;
+  const double ecap = p->edge_capacity > 0 ? (double)p->edge_capacity
+                                           : std::ceil(emean + 8.0 * 2.0 * std::sqrt(cmean) + 4096.0);
+  if (ecap >= 2147483000.0) {
+    why = "planned edge room exceeds int32 row pointers";
+    return ABM_E_CAPACITY;
+  }
+  z.ecap = (int64_t)ecap;
+  if (p->mode == ABM_SOFT) {
+    z.seg = p->checkpoint_every;
+    z.nckpt = (z.T + z.seg - 1) / z.seg + 1;
+  }
+  return ABM_OK;
+}
+
+void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
+  Layout L;
+  o.rep = L.take<RepInfo>(z.R);
+  o.tiles = L.take<int4>(z.ntiles);
+  o.srec = L.take<StaticRec>(z.N);
+  o.age = L.take<uint8_t>(z.N);
+  o.hhn = L.take<uint8_t>(z.N);
+  o.wpm = L.take<int32_t>(std::max<int64_t>(z.M, 1));
+  o.atab = L.take<float>(ATAB);
+  o.ptab = L.take<uint32_t>(NPT * 64);
+  o.state = L.take<AgentState>(z.N);
+  o.code = L.take<uint8_t>(z.N);
+  o.lambda = L.take<float>(z.N);
+  o.own = L.take<uint16_t>(z.N);
+  o.recv = L.take<uint32_t>(z.N);
+  o.row_ptr = L.take<int32_t>(z.N + 1);
+  o.cur_occ = L.take<int32_t>(z.N);
+  o.cur_rand = L.take<int32_t>(z.N);
+  o.col = L.take<int32_t>(z.ecap);
+  o.w = L.take<float>(z.ecap);
+  o.scan_part = L.take<int64_t>(z.nscan + 1);
+  o.vhist = L.take<int32_t>(z.ntiles * NBUCKET);
+  o.vplan = L.take<int32_t>(2 * z.R);
+  o.vtile = L.take<int32_t>(z.ntiles);
+  o.latch = L.take<uint8_t>(z.R);
+  o.counts_day = L.take<unsigned long long>(z.R * ABM_NC);
+  o.prev_counts = L.take<long long>(z.R * ABM_NC);
+  o.traj = L.take<long long>(z.T * z.R * ABM_NC);
+  o.day = L.take<int32_t>(1);
+  o.flags = L.take<int32_t>(1);
+  o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
+  if (p.mode == ABM_SOFT) {
+    o.s = L.take<float>(z.N);
+    o.ehist = L.take<float>(WIN * z.N);
+    o.inf = L.take<float>(z.N);
+    o.sigma = L.take<float>(z.N);
+    o.soft_inc = L.take<float>(z.R * z.T);
+    o.seg_sigma = L.take<float>(z.seg * z.N);
+    o.seg_y = L.take<float>(z.seg * z.N);
+    o.seg_s = L.take<float>(z.seg * z.N);
+    o.ckpt = L.take<float>(z.nckpt * (WIN + 1) * z.N);
+    o.s_bar = L.take<float>(z.N);
+    o.ibar = L.take<float>(WIN * z.N);
+    o.vtmp = L.take<float>(z.N);
+    o.lam_bar = L.take<float>(z.N);
+    o.gtheta = L.take<float>(z.R * ABM_N_THETA);
+    o.gpart = L.take<float>(z.ntiles * ABM_N_THETA);
+    o.dL = L.take<float>(z.R * z.T);
+  }
+  total = L.total;
+}
+
+void enqueue_day(abm_sim* s, hipStream_t st, bool timed) {
+  const Dev& d = s->d;
+  int k = 0;
+  auto mark = [&]() {
+    if (timed) (void)hipEventRecord(s->ev[k], st);
+    ++k;
+  };
+  mark();
+  launch_pre(d, st);
+  mark();
+  if (d.vacc_on) launch_vplan(d, st);
+  mark();
+  launch_count(d, st);
+  mark();
+  launch_scan(d, st);
+  mark();
+  launch_fill(d, st);
+  mark();
+  launch_canon(d, st);
+  mark();
+  launch_message(d, st);
+  mark();
+  launch_fused(d, st);
+  mark();
+  launch_finalize(d, st);
+  if (timed) (void)hipEventRecord(s->ev[abm_sim::NK], st);
+}
+
+int check_dev_flags(abm_sim* s) {
+  int32_t f = 0;
+  HIPCHK(s, hipMemcpyAsync(&f, s->d.flags, sizeof f, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (f & FLAG_CAPACITY)
+    return s->fail(ABM_E_CAPACITY, "a day's contact graph exceeded the edge room (%lld edges)",
+                   (long long)s->z.ecap);
+  if (f & FLAG_RECV_OVERFLOW) return s->fail(ABM_E_CAPACITY, "received-contact counter overflow");
+  return ABM_OK;
+}
+
+}  // namespace
+
+#include "soft_driver.inc"
+
+extern "C" {
+
+int abm_workspace_size(const abm_params* p, const abm_population* pop, size_t* bytes) {
+  if (!bytes) return ABM_E_ARG;
+  Sizes z;
+  std::string why;
+  const int rc = validate(p, pop, z, why);
+  if (rc) return rc;
+  Offsets o;
+  layout(z, *p, o, *bytes);
+  return ABM_OK;
+}
+
+int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace, size_t ws_bytes,
+               void* hip_stream, abm_sim** out) {
+  if (!out) return ABM_E_ARG;
+  *out = nullptr;
+  abm_sim* s = new abm_sim();
+  *out = s;
+  std::string why;
+  int rc = validate(p, pop, s->z, why);
+  if (rc) return s->fail(rc, "%s", why.c_str());
+  s->p = *p;
+  const Sizes& z = s->z;
+  size_t need = 0;
+  layout(z, *p, s->o, need);
+  if (!d_workspace || ws_bytes < need)
+    return s->fail(ABM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  s->ws = (char*)d_workspace;
+  s->stream = (hipStream_t)hip_stream;
+  const Offsets& o = s->o;
+  char* ws = s->ws;
+  Dev& d = s->d;
+  d.N = (int32_t)z.N;
+  d.R = (int32_t)z.R;
+  d.ntiles = (int32_t)z.ntiles;
+  d.T = (int32_t)z.T;
+  d.ecap = z.ecap;
+  d.nscan = (int32_t)z.nscan;
+  d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+  d.key1 = (uint32_t)(p->seed >> 32);
+  d.e_days = p->e_days;
+  d.i_days = p->i_days;
+  d.qdays = p->quarantine_days;
+  d.test_delay = p->test_delay;
+  d.dose_lag = p->dose_lag;
+  d.vacc_on = p->vacc_rate > 0 ? 1 : 0;
+  d.strategy = p->strategy;
+  d.mode = p->mode;
+  d.w_h = p->w_household;
+  d.w_o = p->w_occupation;
+  d.w_r = p->w_random;
+  d.dt = p->dt;
+  d.test_rate = p->test_rate;
+  d.sens = p->test_sensitivity;
+  d.dropout = p->quarantine_dropout;
+  d.eff1 = p->eff1;
+  d.eff2 = p->eff2;
+  d.gtau = p->gumbel_tau;
+  d.vacc_trigger = p->vacc_trigger;
+  for (int a = 0; a < ABM_N_AGE; ++a) {
+    d.p_death[a] = p->p_death[a];
+    d.vrank[0][a] = (int8_t)priority_class(p->strategy, 1, a);
+    d.vrank[1][a] = (int8_t)priority_class(p->strategy, 2, a);
+  }
+  d.rep = (const RepInfo*)(ws + o.rep);
+  d.tiles = (const int4*)(ws + o.tiles);
+  d.srec = (const StaticRec*)(ws + o.srec);
+  d.age = (const uint8_t*)(ws + o.age);
+  d.hhn = (const uint8_t*)(ws + o.hhn);
+  d.wp_members = (const int32_t*)(ws + o.wpm);
+  d.atab = (const float*)(ws + o.atab);
+  d.ptab = (const uint32_t*)(ws + o.ptab);
+  d.state = (AgentState*)(ws + o.state);
+  d.code = (uint8_t*)(ws + o.code);
+  d.lambda = (float*)(ws + o.lambda);
+  d.own = (uint16_t*)(ws + o.own);
+  d.recv = (uint32_t*)(ws + o.recv);
+  d.row_ptr = (int32_t*)(ws + o.row_ptr);
+  d.cur_occ = (int32_t*)(ws + o.cur_occ);
+  d.cur_rand = (int32_t*)(ws + o.cur_rand);
+  d.col = (int32_t*)(ws + o.col);
+  d.w = (float*)(ws + o.w);
+  d.scan_part = (int64_t*)(ws + o.scan_part);
+  d.vhist = (int32_t*)(ws + o.vhist);
+  d.vplan = (int32_t*)(ws + o.vplan);
+  d.vtile_base = (int32_t*)(ws + o.vtile);
+  d.latch = (uint8_t*)(ws + o.latch);
+  d.counts_day = (unsigned long long*)(ws + o.counts_day);
+  d.prev_counts = (long long*)(ws + o.prev_counts);
+  d.traj = (long long*)(ws + o.traj);
+  d.day = (int32_t*)(ws + o.day);
+  d.flags = (int32_t*)(ws + o.flags);
+  if (p->mode == ABM_SOFT) {
+    d.s = (float*)(ws + o.s);
+    d.ehist = (float*)(ws + o.ehist);
+    d.inf = (float*)(ws + o.inf);
+    d.sigma = (float*)(ws + o.sigma);
+    d.soft_inc = (float*)(ws + o.soft_inc);
+    d.seg_sigma = (float*)(ws + o.seg_sigma);
+    d.seg_y = (float*)(ws + o.seg_y);
+    d.seg_s = (float*)(ws + o.seg_s);
+    d.ckpt = (float*)(ws + o.ckpt);
+    d.s_bar = (float*)(ws + o.s_bar);
+    d.ibar = (float*)(ws + o.ibar);
+    d.vtmp = (float*)(ws + o.vtmp);
+    d.lam_bar = (float*)(ws + o.lam_bar);
+    d.gtheta = (float*)(ws + o.gtheta);
+    d.gpart = (float*)(ws + o.gpart);
+    d.dL = (const float*)(ws + o.dL);
+    d.seg = (int32_t)z.seg;
+  }
+
+  // host copies of the static data
+  const int64_t N = z.N;
+  const int R = (int)z.R;
+  std::vector<StaticRec> srec(N);
+  std::vector<uint8_t> hhn(N);
+  for (int h = 0; h < pop->n_households; ++h)
+    for (int64_t i = pop->hh_start[h]; i < pop->hh_start[h + 1]; ++i) {
+      srec[i].hh_lo = pop->hh_start[h];
+      srec[i].hh_n = (uint8_t)(pop->hh_start[h + 1] - pop->hh_start[h]);
+      hhn[i] = srec[i].hh_n;
+    }
+  std::vector<int32_t> agent_rep(N);
+  for (int r = 0; r < R; ++r)
+    for (int64_t i = pop->agent_offset[r]; i < pop->agent_offset[r + 1]; ++i) agent_rep[i] = r;
+  for (int64_t i = 0; i < N; ++i) {
+    srec[i].age = pop->age[i];
+    srec[i].occ = pop->occupation[i];
+    srec[i].pad = 0;
+    srec[i].wp_lo = 0;
+    srec[i].wp_pos = 0;
+    srec[i].wp_n = 0;
+  }
+  std::vector<uint8_t> seen(N, 0);
+  for (int w = 0; w < pop->n_workplaces; ++w) {
+    const int32_t lo = pop->wp_start[w], hi = pop->wp_start[w + 1];
+    const int r0 = agent_rep[pop->wp_members[lo]];
+    for (int32_t q = lo; q < hi; ++q) {
+      const int32_t a = pop->wp_members[q];
+      if (seen[a]) return s->fail(ABM_E_ARG, "agent %d belongs to two workplaces", a);
+      if (agent_rep[a] != r0) return s->fail(ABM_E_ARG, "workplace %d crosses replicates", w);
+      seen[a] = 1;
+      srec[a].wp_lo = lo;
+      srec[a].wp_pos = (uint16_t)(q - lo);
+      srec[a].wp_n = (uint16_t)(hi - lo);
+    }
+  }
+  s->reps.resize(R);
+  std::vector<int4> tiles;
+  tiles.reserve(z.ntiles);
+  const float kappa = p->kappa;
+  for (int r = 0; r < R; ++r) {
+    RepInfo& ri = s->reps[r];
+    memset(&ri, 0, sizeof ri);
+    ri.start = (int32_t)pop->agent_offset[r];
+    ri.n = (int32_t)(pop->agent_offset[r + 1] - pop->agent_offset[r]);
+    ri.stream = pop->stream ? pop->stream[r] : (uint32_t)r;
+    ri.delay = pop->dose2_delay[r];
+    ri.cap = (int64_t)std::floor(p->vacc_rate * (double)ri.n);
+    ri.tile0 = (int32_t)tiles.size();
+    for (int32_t a = ri.start; a < ri.start + ri.n; a += TILE) {
+      const int32_t b = std::min(a + TILE, ri.start + ri.n);
+      tiles.push_back(make_int4(r, a, b, (int)tiles.size()));
+    }
+    ri.ntiles = (int32_t)tiles.size() - ri.tile0;
+    ri.R = pop->R[r];
+    const float rk = ri.R * kappa;
+    ri.rk = rk;
+    for (int a = 0; a < ABM_N_AGE; ++a) {
+      ri.S[a] = pop->susceptibility[r * ABM_N_AGE + a];
+      ri.coef[a] = rk * ri.S[a];
+    }
+  }
+  float atab[ATAB];
+  build_atab(*p, atab);
+  std::vector<uint32_t> ptab(NPT * 64);
+  for (int k = 0; k < ABM_N_OCC; ++k) build_poisson(p->mu_occupation[k] / 2.0, &ptab[k * 64]);
+  for (int a = 0; a < ABM_N_AGE; ++a) build_poisson(p->mu_random[a] / 2.0, &ptab[(PT_AGE0 + a) * 64]);
+
+  hipStream_t st = s->stream;
+  HIPCHK(s, hipMemcpyAsync(ws + o.rep, s->reps.data(), R * sizeof(RepInfo), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.srec, srec.data(), N * sizeof(StaticRec), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.age, pop->age, N, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.hhn, hhn.data(), N, hipMemcpyHostToDevice, st));
+  if (z.M > 0)
+    HIPCHK(s, hipMemcpyAsync(ws + o.wpm, pop->wp_members, z.M * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.atab, atab, sizeof atab, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, st));
+  if (z.nseeds > 0)
+    HIPCHK(s, hipMemcpyAsync(ws + o.seeds, pop->initial_infected, z.nseeds * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 4, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.flags, 0, 4, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.vplan, 0, 8 * R, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.traj, 0, z.T * z.R * ABM_NC * 8, st));
+  launch_init_state(d, (const int32_t*)(ws + o.seeds), z.nseeds, st);
+  launch_recount(d, st);
+  if (p->mode == ABM_SOFT) {
+    rc = soft_create(s);
+    if (rc) return rc;
+  }
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipStreamSynchronize(st));
+  for (int k = 0; k <= abm_sim::NK; ++k) HIPCHK(s, hipEventCreate(&s->ev[k]));
+  const bool use_graph = !(p->flags & (ABM_FLAG_PROFILE | ABM_FLAG_NO_GRAPH)) && p->mode == ABM_HARD;
+  if (use_graph) {
+    HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_day(s, s->cap_stream, false);
+    HIPCHK(s, hipStreamEndCapture(s->cap_stream, &s->graph));
+    HIPCHK(s, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  }
+  return ABM_OK;
+}
+
+int abm_step(abm_sim* s, int32_t n_days) {
+  if (!s) return ABM_E_ARG;
+  if (s->err) return s->err;
+  if (n_days < 0) return s->fail(ABM_E_ARG, "n_days < 0");
+  if (s->p.mode != ABM_HARD) return s->fail(ABM_E_STATE, "abm_step is for hard mode; use abm_run");
+  if ((int64_t)s->host_day + n_days > s->z.T)
+    return s->fail(ABM_E_STATE, "stepping past n_steps (%d)", (int)s->z.T);
+  const bool timed = (s->p.flags & ABM_FLAG_PROFILE) != 0;
+  for (int k = 0; k < n_days; ++k) {
+    if (s->exec) {
+      HIPCHK(s, hipGraphLaunch(s->exec, s->stream));
+    } else {
+      enqueue_day(s, s->stream, timed);
+      HIPCHK(s, hipGetLastError());
+      if (timed) {
+        HIPCHK(s, hipEventSynchronize(s->ev[abm_sim::NK]));
+        for (int q = 0; q < abm_sim::NK; ++q) {
+          float ms = 0.f;
+          HIPCHK(s, hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]));
+          s->ms[q] += ms;
+          s->launches[q] += 1;
+        }
+      }
+    }
+    ++s->host_day;
+  }
+  return ABM_OK;
+}
+
+int abm_run(abm_sim* s, int32_t n_days, int64_t* h_counts, float* h_soft_incidence) {
+  if (!s) return ABM_E_ARG;
+  if (s->err) return s->err;
+  if (s->p.mode == ABM_SOFT) return soft_run(s, n_days, h_soft_incidence);
+  const int32_t t0 = s->host_day;
+  int rc = abm_step(s, n_days);
+  if (rc) return rc;
+  rc = check_dev_flags(s);
+  if (rc) return rc;
+  if (h_counts && n_days > 0) {
+    const size_t row = (size_t)s->z.R * ABM_NC;
+    HIPCHK(s, hipMemcpyAsync(h_counts, s->d.traj + (size_t)t0 * row, n_days * row * 8,
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  return ABM_OK;
+}
+
+int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
+  if (!s || !h_dst) return ABM_E_ARG;
+  if (s->err) return s->err;
+  const int rc = check_dev_flags(s);
+  if (rc) return rc;
+  const int64_t N = s->z.N;
+  const void* src = nullptr;
+  size_t n = 0;
+  int32_t E = 0;
+  if (what == ABM_GET_COL || what == ABM_GET_W) {
+    HIPCHK(s, hipMemcpy(&E, s->d.row_ptr + N, 4, hipMemcpyDeviceToHost));
+  }
+  switch (what) {
+    case ABM_GET_STATE: src = s->d.state; n = N * sizeof(AgentState); break;
+    case ABM_GET_LAMBDA: src = s->d.lambda; n = N * 4; break;
+    case ABM_GET_CODE: src = s->d.code; n = N; break;
+    case ABM_GET_ROWPTR: src = s->d.row_ptr; n = (N + 1) * 4; break;
+    case ABM_GET_COL: src = s->d.col; n = (size_t)E * 4; break;
+    case ABM_GET_W: src = s->d.w; n = (size_t)E * 4; break;
+    case ABM_GET_ATAB: src = s->d.atab; n = ATAB * 4; break;
+    case ABM_GET_POISSON: src = s->d.ptab; n = NPT * 64 * 4; break;
+    case ABM_GET_LATCH: src = s->d.latch; n = s->z.R; break;
+    case ABM_GET_SOFT_S:
+      if (s->p.mode != ABM_SOFT) return s->fail(ABM_E_STATE, "not a soft-mode simulation");
+      src = s->d.s; n = N * 4; break;
+    case ABM_GET_DAY:
+      if (h_bytes < 4) return s->fail(ABM_E_ARG, "buffer too small");
+      *(int32_t*)h_dst = s->host_day;
+      return ABM_OK;
+    case ABM_GET_COEF: {
+      if (h_bytes < (size_t)s->z.R * ABM_N_AGE * 4) return s->fail(ABM_E_ARG, "buffer too small");
+      float* f = (float*)h_dst;
+      for (int r = 0; r < s->z.R; ++r)
+        for (int a = 0; a < ABM_N_AGE; ++a) f[r * ABM_N_AGE + a] = s->reps[r].coef[a];
+      return ABM_OK;
+    }
+    default: return s->fail(ABM_E_ARG, "unknown abm_get item %d", what);
+  }
+  if (h_bytes < n) return s->fail(ABM_E_ARG, "buffer of %zu bytes, %zu needed", h_bytes, n);
+  if (n) {
+    HIPCHK(s, hipMemcpyAsync(h_dst, src, n, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  return ABM_OK;
+}
+
+int abm_set_state(abm_sim* s, int32_t day, const uint8_t* h_latch, const abm_agent_state* h_state,
+                  size_t n_agents) {
+  if (!s || !h_state || !h_latch) return ABM_E_ARG;
+  if (s->err) return s->err;
+  if (s->p.mode != ABM_HARD) return s->fail(ABM_E_STATE, "abm_set_state is for hard mode");
+  if ((int64_t)n_agents != s->z.N) return s->fail(ABM_E_ARG, "state of %zu agents, %lld expected",
+                                                 n_agents, (long long)s->z.N);
+  if (day < 0 || day > s->z.T) return s->fail(ABM_E_ARG, "day out of range");
+  HIPCHK(s, hipMemcpyAsync(s->d.state, h_state, n_agents * sizeof(AgentState), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->d.latch, h_latch, s->z.R, hipMemcpyHostToDevice, s->stream));
+  launch_set_day(s->d, day, s->stream);
+  launch_recount(s->d, s->stream);
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->host_day = day;
+  return ABM_OK;
+}
+
+int abm_sync(abm_sim* s) {
+  if (!s) return ABM_E_ARG;
+  if (s->err) return s->err;
+  return check_dev_flags(s);
+}
+
+void abm_destroy(abm_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  for (int k = 0; k <= abm_sim::NK; ++k)
+    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  delete s;
+}
+
+const char* abm_error_string(int code) {
+  switch (code) {
+    case ABM_OK: return "ok";
+    case ABM_E_ARG: return "invalid argument";
+    case ABM_E_ABI: return "ABI mismatch";
+    case ABM_E_WORKSPACE: return "workspace too small";
+    case ABM_E_CAPACITY: return "edge capacity exceeded";
+    case ABM_E_HIP: return "HIP runtime error";
+    case ABM_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char* abm_last_error(const abm_sim* s) { return s ? s->msg.c_str() : "null simulation"; }
+
+int abm_profile_kernels(void) { return abm_sim::NK; }
+const char* abm_profile_name(int32_t k) { return (k >= 0 && k < abm_sim::NK) ? kKernelNames[k] : ""; }
+int abm_profile_get(abm_sim* s, double* h_ms, int64_t* h_launches) {
+  if (!s) return ABM_E_ARG;
+  for (int k = 0; k < abm_sim::NK; ++k) {
+    if (h_ms) h_ms[k] = s->ms[k];
+    if (h_launches) h_launches[k] = s->launches[k];
+  }
+  return ABM_OK;
+}
+int abm_profile_reset(abm_sim* s) {
+  if (!s) return ABM_E_ARG;
+  for (int k = 0; k < abm_sim::NK; ++k) {
+    s->ms[k] = 0;
+    s->launches[k] = 0;
+  }
+  return ABM_OK;
+}
+
+int abm_philox(uint64_t seed, const uint32_t* d_ctr, int64_t n, uint32_t* d_out, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!d_ctr || !d_out))) return ABM_E_ARG;
+  launch_philox(seed, d_ctr, n, d_out, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? ABM_OK : ABM_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Internal definitions shared by the HIP kernels and the host runtime of libabm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/abm.h"
+
+namespace abm {
+
+constexpr int TILE = 256;          // agents per tile (one workgroup of 4 waves)
+constexpr int ATAB = 64;           // days-since-exposure table size
+constexpr int NPT = 32;            // Poisson tables: 23 occupations + 9 age groups
+constexpr int PT_AGE0 = ABM_N_OCC; // first age-group table
+constexpr int NBUCKET = 18;        // vaccination priority classes (dose x age group)
+constexpr int SCAN_ITEMS = 8;      // degrees per thread in the row-pointer scan
+constexpr int SCAN_BLOCK = TILE * SCAN_ITEMS;
+constexpr int MSG_CHUNK = 4096;    // edges staged in LDS per step of the message kernel
+constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
+
+enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };
+
+enum DevFlag : int32_t { FLAG_CAPACITY = 1, FLAG_RECV_OVERFLOW = 2 };
+
+// Per-agent static data, 16 bytes.
+struct StaticRec {
+  int32_t hh_lo;      // first member of the household
+  uint8_t hh_n;       // household size
+  uint8_t age;
+  uint8_t occ;
+  uint8_t pad;
+  int32_t wp_lo;      // offset of the workplace in wp_members (0 if none)
+  uint16_t wp_pos;    // position in the workplace
+  uint16_t wp_n;      // workplace size (0 if none)
+};
+static_assert(sizeof(StaticRec) == 16, "StaticRec is 16 bytes");
+
+struct AgentState {
+  uint8_t stage, flags, vacc, reserved;
+  int16_t t_exp, q_until, test_day, d1, d2, pad;
+};
+static_assert(sizeof(AgentState) == 16, "AgentState is 16 bytes");
+
+// Per-replicate data (device copy).
+struct RepInfo {
+  int32_t start, n;         // agents [start, start + n)
+  uint32_t stream;          // Philox stream word
+  int32_t delay;            // dose-2 delay
+  int64_t cap;              // daily doses
+  int32_t tile0, ntiles;    // tiles of this replicate
+  float coef[ABM_N_AGE];    // fl(fl(R * kappa) * S_a)
+  float R;
+  float S[ABM_N_AGE];
+  float rk;                 // fl(R * kappa)
+  int32_t pad[2];
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  int32_t N, R, ntiles, T;
+  int64_t ecap;
+  uint32_t key0, key1;
+  int32_t e_days, i_days, qdays, test_delay, dose_lag, vacc_on, strategy, mode;
+  float w_h, w_o, w_r, dt, test_rate, sens, dropout, eff1, eff2, gtau;
+  double vacc_trigger;
+  float p_death[ABM_N_AGE];
+  int8_t vrank[2][ABM_N_AGE];   // priority class of (dose 1|2, age group)
+
+  const RepInfo* rep;
+  const int4* tiles;            // {rep, start, end, tile index}
+  const StaticRec* srec;
+  const uint8_t* age;
+  const uint8_t* hhn;
+  const int32_t* wp_members;
+  const float* atab;            // [ATAB]
+  const uint32_t* ptab;         // [NPT][64]
+
+  AgentState* state;
+  uint8_t* code;
+  float* lambda;
+
+  uint16_t* own;                // k_occ | k_rand << 8 (drawn by the agent)
+  uint32_t* recv;               // received occ << 16 | received rand
+  int32_t* row_ptr;             // [N+1]
+  int32_t* cur_occ;             // claim cursors into the received blocks
+  int32_t* cur_rand;
+  int32_t* col;
+  float* w;
+  int64_t* scan_part;           // [nscan + 1]
+  int32_t nscan;
+
+  int32_t* vhist;               // [ntiles][NBUCKET]
+  int32_t* vplan;               // [R][2] partial class, quota in it
+  int32_t* vtile_base;          // [ntiles]
+  uint8_t* latch;               // [R]
+
+  unsigned long long* counts_day;   // [R][ABM_NC]
+  long long* prev_counts;           // [R][ABM_NC]
+  long long* traj;                  // [T][R][ABM_NC]
+  int32_t* day;
+  int32_t* flags;
+
+  // soft mode
+  float* s;            // susceptible mass [N]
+  float* ehist;        // exposure mass ring [WIN][N], slot = day mod WIN
+  float* inf;          // infectiousness [N]
+  float* sigma;        // sum_e w * inf[src] of the day [N]
+  float* soft_inc;     // [R][T] relaxed incidence
+  float* seg_sigma;    // [seg][N] recompute buffers of a checkpoint segment
+  float* seg_y;        // [seg][N]
+  float* seg_s;        // [seg][N]
+  float* ckpt;         // [nckpt][(WIN) + 1][N]
+  float* s_bar;        // [N]
+  float* ibar;         // [WIN][N] ring of adjoint of infectiousness, slot = day mod WIN
+  float* vtmp;         // [N] coef * lambda_bar (message input of the transpose pass)
+  float* lam_bar;      // [N]
+  float* gtheta;       // [R][ABM_N_THETA] accumulated in float (per-tile partials reduced)
+  float* gpart;        // [ntiles][ABM_N_THETA]
+  const float* dL;     // [R][T] device copy of dL/d(incidence)
+  int32_t seg;         // checkpoint interval
+};
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) ------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t lane4(const uint4& b, int l) {
+  return l == 0 ? b.x : (l == 1 ? b.y : (l == 2 ? b.z : b.w));
+}
+
+// (floor(x / 2^9) + 1/2) * 2^-23: odd multiples of 2^-24 in (0, 1), exact in FP32.
+__device__ __forceinline__ float u01(uint32_t x) {
+  return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+// Inverse-CDF Poisson count from a 32-bit word: #{k < 63 : T_k <= x}.
+__device__ __forceinline__ int poisson_k(const uint32_t* T, uint32_t x) {
+  int k = 0;
+  while (k < 63 && T[k] <= x) ++k;
+  return k;
+}
+
+// ---- kernel launchers (one per translation unit that owns the kernel) ---------------
+void launch_pre(const Dev& d, hipStream_t s);
+void launch_vplan(const Dev& d, hipStream_t s);
+void launch_count(const Dev& d, hipStream_t s);
+void launch_scan(const Dev& d, hipStream_t s);
+void launch_fill(const Dev& d, hipStream_t s);
+void launch_canon(const Dev& d, hipStream_t s);
+void launch_message(const Dev& d, hipStream_t s);
+void launch_fused(const Dev& d, hipStream_t s);
+void launch_finalize(const Dev& d, hipStream_t s);
+void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);
+void launch_recount(const Dev& d, hipStream_t s);
+void launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s);
+
+// soft mode
+void launch_soft_init(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);
+void launch_soft_inf(const Dev& d, hipStream_t s);
+void launch_soft_message(const Dev& d, const float* x, float* out, hipStream_t s);
+void launch_soft_update(const Dev& d, int32_t seg_slot, hipStream_t s);
+void launch_soft_finalize(const Dev& d, hipStream_t s);
+void launch_soft_ckpt_save(const Dev& d, int32_t k, hipStream_t s);
+void launch_soft_ckpt_load(const Dev& d, int32_t k, int32_t day, hipStream_t s);
+void launch_adj_zero(const Dev& d, hipStream_t s);
+void launch_adj_day(const Dev& d, int32_t t, int32_t seg_slot, hipStream_t s);
+void launch_adj_ibar(const Dev& d, int32_t t, hipStream_t s);
+void launch_adj_theta(const Dev& d, hipStream_t s);
+void launch_set_day(const Dev& d, int32_t day, hipStream_t s);
+
+}  // namespace abm

@@ -1,0 +1,242 @@
+// Daily contact-graph builder (section 3, "Interaction Networks"): fixed households,
+// workplace contacts and random contacts redrawn every day, laid out as a
+// destination-sorted CSR with a canonical order inside each row:
+//   [household members ascending]
+//   [workplace contacts the agent drew, draw order][workplace contacts others drew, by initiator]
+//   [random contacts the agent drew, draw order][random contacts others drew, by initiator]
+// Each drawn contact is seen from both ends (symmetric graph).
+//
+// Kernels: count (Poisson draws + atomic in-degree) -> scan (row pointers and claim
+// cursors) -> fill (own rows + claimed slots in partners' rows) -> canon (sort each
+// received block by initiator).  The Philox draws are recomputed in fill rather than
+// stored: ALU is cheaper than a round trip of the partner list through HBM.
+#include "abm_internal.h"
+
+namespace abm {
+
+// Walk the k contacts drawn by agent (loc) in network `purpose`; draw d uses flat lane
+// d of the purpose's stream, lane 0 being the count.  f(d, partner) for d = 1..k.
+template <typename F>
+__device__ __forceinline__ int walk_contacts(const Dev& d, uint32_t purpose, uint32_t loc,
+                                             uint32_t t, uint32_t stream, const uint32_t* T,
+                                             uint32_t m, F&& f, int partner_base, bool rnd,
+                                             int32_t wp_lo, uint32_t pos) {
+  if (m < 2) return 0;
+  uint4 blk = philox(loc, t, stream, purpose << 24, d.key0, d.key1);
+  const int k = poisson_k(T, blk.x);
+  for (int q = 1; q <= k; ++q) {
+    if ((q & 3) == 0) blk = philox(loc, t, stream, (purpose << 24) | (uint32_t)(q >> 2), d.key0, d.key1);
+    const uint32_t x = lane4(blk, q & 3);
+    const uint32_t off = (uint32_t)(((uint64_t)x * (uint64_t)(m - 1)) >> 32);
+    uint32_t slot = pos + 1 + off;
+    if (slot >= m) slot -= m;
+    const int p = rnd ? partner_base + (int)slot : d.wp_members[wp_lo + (int)slot];
+    f(q, p);
+  }
+  return k;
+}
+
+__global__ __launch_bounds__(TILE) void k_count(Dev d) {
+  __shared__ uint32_t T[NPT * 64];
+  for (int i = threadIdx.x; i < NPT * 64; i += TILE) T[i] = d.ptab[i];
+  __syncthreads();
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  if (i >= tl.z) return;
+  const RepInfo& ri = d.rep[tl.x];
+  const uint32_t t = (uint32_t)(*d.day);
+  const StaticRec sr = d.srec[i];
+  const uint32_t loc = (uint32_t)(i - ri.start);
+  const int ko = walk_contacts(
+      d, P_OCC, loc, t, ri.stream, T + sr.occ * 64, sr.wp_n,
+      [&](int, int p) { atomicAdd(&d.recv[p], 1u << 16); }, 0, false, sr.wp_lo, sr.wp_pos);
+  const int kr = walk_contacts(
+      d, P_RAND, loc, t, ri.stream, T + (PT_AGE0 + sr.age) * 64, (uint32_t)ri.n,
+      [&](int, int p) { atomicAdd(&d.recv[p], 1u); }, ri.start, true, 0, loc);
+  d.own[i] = (uint16_t)(ko | (kr << 8));
+}
+
+__device__ __forceinline__ uint32_t degree_of(const Dev& d, int i) {
+  const uint32_t o = d.own[i], r = d.recv[i];
+  return (uint32_t)d.hhn[i] - 1u + (o & 0xFFu) + (o >> 8) + (r >> 16) + (r & 0xFFFFu);
+}
+
+// Phase 1: per-block sums of the degrees.
+__global__ __launch_bounds__(TILE) void k_scan1(Dev d) {
+  __shared__ uint32_t red[TILE / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t i = base + k;
+    if (i < d.N) {
+      const uint32_t r = d.recv[i];
+      if ((r & 0xFFFFu) == 0xFFFFu || (r >> 16) == 0xFFFFu) atomicOr(d.flags, FLAG_RECV_OVERFLOW);
+      s += degree_of(d, (int)i);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < TILE / 64; ++k) t += red[k];
+    d.scan_part[blockIdx.x] = (int64_t)t;
+  }
+}
+
+// Phase 2: one workgroup turns the block sums into exclusive offsets; checks capacity.
+__global__ __launch_bounds__(1024) void k_scan2(Dev d) {
+  __shared__ int64_t buf[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < d.nscan; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    const int64_t v = b < d.nscan ? d.scan_part[b] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (b < d.nscan) d.scan_part[b] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.scan_part[d.nscan] = carry;
+    if (carry > d.ecap) atomicOr(d.flags, FLAG_CAPACITY);
+  }
+}
+
+// Phase 3: row pointers and the claim cursors of the two received blocks.
+__global__ __launch_bounds__(TILE) void k_scan3(Dev d) {
+  __shared__ uint32_t wsum[TILE / 64];
+  if (*d.flags) return;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t deg[SCAN_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t i = base + k;
+    deg[k] = i < d.N ? degree_of(d, (int)i) : 0u;
+    s += deg[k];
+  }
+  // inclusive scan of the thread sums across the wave, then across waves
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int k = 0; k < wv; ++k) wbase += wsum[k];
+  int64_t run = d.scan_part[blockIdx.x] + (int64_t)(wbase + inc - s);
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t i = base + k;
+    if (i < d.N) {
+      const int rp = (int)run;
+      const uint32_t o = d.own[i], r = d.recv[i];
+      d.row_ptr[i] = rp;
+      const int co = rp + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
+      d.cur_occ[i] = co;
+      d.cur_rand[i] = co + (int)(r >> 16) + (int)(o >> 8);
+      run += deg[k];
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) d.row_ptr[d.N] = (int)d.scan_part[d.nscan];
+}
+
+__global__ __launch_bounds__(TILE) void k_fill(Dev d) {
+  __shared__ uint32_t T[NPT * 64];
+  for (int i = threadIdx.x; i < NPT * 64; i += TILE) T[i] = d.ptab[i];
+  __syncthreads();
+  if (*d.flags) return;
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  if (i >= tl.z) return;
+  const RepInfo& ri = d.rep[tl.x];
+  const uint32_t t = (uint32_t)(*d.day);
+  const StaticRec sr = d.srec[i];
+  const uint32_t loc = (uint32_t)(i - ri.start);
+  int pos = d.row_ptr[i];
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;
+  for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m) {
+    if (m == i) continue;
+    d.col[pos] = m;
+    d.w[pos] = wh;
+    ++pos;
+  }
+  const int own_occ = pos;
+  const int ko = walk_contacts(
+      d, P_OCC, loc, t, ri.stream, T + sr.occ * 64, sr.wp_n,
+      [&](int q, int p) {
+        d.col[own_occ + q - 1] = p;
+        d.w[own_occ + q - 1] = wo;
+        const int slot = atomicAdd(&d.cur_occ[p], 1);
+        d.col[slot] = i;
+        d.w[slot] = wo;
+      },
+      0, false, sr.wp_lo, sr.wp_pos);
+  const int own_rand = own_occ + ko + (int)(d.recv[i] >> 16);
+  walk_contacts(
+      d, P_RAND, loc, t, ri.stream, T + (PT_AGE0 + sr.age) * 64, (uint32_t)ri.n,
+      [&](int q, int p) {
+        d.col[own_rand + q - 1] = p;
+        d.w[own_rand + q - 1] = wr;
+        const int slot = atomicAdd(&d.cur_rand[p], 1);
+        d.col[slot] = i;
+        d.w[slot] = wr;
+      },
+      ri.start, true, 0, loc);
+}
+
+// Insertion sort of a short received block by initiator id; weights are uniform
+// inside a block so only the ids move.
+__device__ __forceinline__ void sort_block(int32_t* c, int n) {
+  for (int a = 1; a < n; ++a) {
+    const int32_t v = c[a];
+    int b = a - 1;
+    while (b >= 0 && c[b] > v) {
+      c[b + 1] = c[b];
+      --b;
+    }
+    c[b + 1] = v;
+  }
+}
+
+__global__ __launch_bounds__(TILE) void k_canon(Dev d) {
+  if (*d.flags) return;
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (i >= d.N) return;
+  const uint32_t o = d.own[i], r = d.recv[i];
+  const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
+  const int a = d.row_ptr[i] + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
+  if (ro > 1) sort_block(d.col + a, ro);
+  const int b = a + ro + (int)(o >> 8);
+  if (rr > 1) sort_block(d.col + b, rr);
+}
+
+void launch_count(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_scan(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan1, dim3(d.nscan), dim3(TILE), 0, s, d);
+  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_scan3, dim3(d.nscan), dim3(TILE), 0, s, d);
+}
+void launch_fill(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_canon(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_canon, dim3((d.N + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+}
+
+}  // namespace abm

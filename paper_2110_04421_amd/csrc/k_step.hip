@@ -1,0 +1,394 @@
+// Per-day agent kernels: interventions before transmission, the edge-message force of
+// infection (eq. 1), the fused infection / progression / testing / vaccination step
+// (eq. 2; sections 3-5), and the end-of-day bookkeeping.
+#include "abm_internal.h"
+
+namespace abm {
+
+// ---- small block helpers (TILE = 256 threads = 4 waves of 64) -----------------------
+__device__ __forceinline__ uint32_t wave_count(bool p) {
+  return (uint32_t)__popcll(__ballot(p));
+}
+
+// Sum `nv` per-thread boolean counters over the workgroup and add them to dst[slot[k]].
+template <int NV>
+__device__ __forceinline__ void block_count_add(const bool (&v)[NV], const int (&slot)[NV],
+                                                unsigned long long* dst) {
+  __shared__ uint32_t part[TILE / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const uint32_t c = wave_count(v[k]);
+    if (lane == 0) part[wv][k] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    uint32_t s = 0;
+    for (int q = 0; q < TILE / 64; ++q) s += part[q][threadIdx.x];
+    if (s) atomicAdd(&dst[slot[threadIdx.x]], (unsigned long long)s);
+  }
+}
+
+__device__ __forceinline__ int vacc_bucket(const Dev& d, const AgentState& a, int t, int age,
+                                           int delay) {
+  if (a.stage == ABM_STAGE_M) return NBUCKET;
+  if (a.vacc == 0) return d.vrank[0][age];
+  if (a.vacc == 1 && t >= (int)a.d1 + delay) return d.vrank[1][age];
+  return NBUCKET;
+}
+
+// ---- pre: results due -> quarantine, dropout, infectiousness codes, vaccine classes --
+__global__ __launch_bounds__(TILE) void k_pre(Dev d) {
+  __shared__ int hist[NBUCKET + 1];
+  if (threadIdx.x <= NBUCKET) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  const bool live = i < tl.z;
+  const int t = *d.day;
+  bool pos_due = false;
+  if (live) {
+    const RepInfo& ri = d.rep[tl.x];
+    AgentState a = d.state[i];
+    const AgentState a0 = a;
+    if ((a.flags & 1) && t == (int)a.test_day + d.test_delay) {
+      if (a.flags & 2) {
+        pos_due = true;
+        if (d.qdays > 0) a.q_until = (int16_t)(t + d.qdays);
+      }
+      a.flags = 0;
+    }
+    if (d.dropout > 0.f && t < (int)a.q_until) {
+      const uint4 b = philox((uint32_t)(i - ri.start), (uint32_t)t, ri.stream, P_AGENT2 << 24,
+                             d.key0, d.key1);
+      if (u01(b.x) < d.dropout) a.q_until = (int16_t)t;
+    }
+    uint8_t c = 0;
+    if ((a.stage == ABM_STAGE_E || a.stage == ABM_STAGE_I) && t >= (int)a.q_until)
+      c = (uint8_t)(t - (int)a.t_exp);
+    d.code[i] = c;
+    d.recv[i] = 0u;
+    if (a.flags != a0.flags || a.q_until != a0.q_until) d.state[i] = a;
+    if (d.vacc_on) atomicAdd(&hist[vacc_bucket(d, a, t, d.age[i], ri.delay)], 1);
+  }
+  const bool v[1] = {pos_due};
+  const int sl[1] = {ABM_C_POS};
+  block_count_add<1>(v, sl, d.counts_day + (size_t)tl.x * ABM_NC);
+  if (d.vacc_on) {
+    __syncthreads();
+    if (threadIdx.x < NBUCKET) d.vhist[(size_t)blockIdx.x * NBUCKET + threadIdx.x] = hist[threadIdx.x];
+  }
+}
+
+// ---- vaccination plan: one workgroup per replicate ------------------------------------
+// Latch on prevalence, then give the day's capacity to the priority classes in order;
+// the first class that does not fit entirely gets a quota filled by ascending agent id
+// (exclusive prefix of its members over the replicate's tiles).
+__global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
+  __shared__ int tot[TILE / 64][NBUCKET];
+  __shared__ int plan[2];
+  __shared__ int wsum[TILE / 64];
+  __shared__ int carry;
+  const int r = blockIdx.x;
+  const RepInfo& ri = d.rep[r];
+  if (threadIdx.x == 0) {
+    int latched = d.latch[r];
+    if (!latched) {
+      const long long ei = d.prev_counts[(size_t)r * ABM_NC + ABM_C_E] +
+                           d.prev_counts[(size_t)r * ABM_NC + ABM_C_I];
+      if ((double)ei >= d.vacc_trigger * (double)ri.n) {
+        latched = 1;
+        d.latch[r] = 1;
+      }
+    }
+    plan[0] = latched ? 0 : -1;
+  }
+  __syncthreads();
+  if (plan[0] < 0) {
+    if (threadIdx.x == 0) {
+      d.vplan[2 * r] = -1;
+      d.vplan[2 * r + 1] = 0;
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int b = 0; b < NBUCKET; ++b) {
+    int s = 0;
+    for (int k = threadIdx.x; k < ri.ntiles; k += TILE) s += d.vhist[(size_t)(ri.tile0 + k) * NBUCKET + b];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) tot[wv][b] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long rem = ri.cap;
+    int bstar = NBUCKET, quota = 0;
+    for (int b = 0; b < NBUCKET; ++b) {
+      long long c = 0;
+      for (int q = 0; q < TILE / 64; ++q) c += tot[q][b];
+      if (c > rem) {
+        bstar = b;
+        quota = (int)rem;
+        break;
+      }
+      rem -= c;
+    }
+    plan[0] = bstar;
+    plan[1] = quota;
+    d.vplan[2 * r] = bstar;
+    d.vplan[2 * r + 1] = quota;
+    carry = 0;
+  }
+  __syncthreads();
+  const int bstar = plan[0];
+  if (bstar >= NBUCKET) return;
+  for (int k0 = 0; k0 < ri.ntiles; k0 += TILE) {
+    const int k = k0 + threadIdx.x;
+    const int v = k < ri.ntiles ? d.vhist[(size_t)(ri.tile0 + k) * NBUCKET + bstar] : 0;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    if (k < ri.ntiles) d.vtile_base[ri.tile0 + k] = carry + wb + inc - v;
+    __syncthreads();
+    if (threadIdx.x == TILE - 1) carry += wb + inc;
+    __syncthreads();
+  }
+}
+
+// ---- force of infection: lambda_j = coef[a_j] * sum_{e in row j} w_e * Atab[code[src_e]]
+// A tile of 256 rows streams its contiguous edge range through LDS in chunks: the
+// edge loads and the 1-byte code gathers are spread over all lanes, then each lane
+// sums its own row left to right (FP32, canonical order) from LDS.
+__global__ __launch_bounds__(TILE) void k_message(Dev d) {
+  __shared__ float atab[ATAB];
+  __shared__ float term[MSG_CHUNK];
+  if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
+  if (*d.flags) return;
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  const bool live = i < tl.z;
+  const int e0 = d.row_ptr[tl.y], e1 = d.row_ptr[tl.z];
+  const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
+  float sum = 0.f;
+  __syncthreads();
+  for (int c0 = e0; c0 < e1; c0 += MSG_CHUNK) {
+    const int cn = min(MSG_CHUNK, e1 - c0);
+    for (int k = threadIdx.x; k < cn; k += TILE) {
+      const int e = c0 + k;
+      const uint32_t src = (uint32_t)d.col[e];
+      term[k] = d.w[e] * atab[d.code[src < (uint32_t)d.N ? src : 0u]];
+    }
+    __syncthreads();
+    const int lo = max(rs, c0), hi = min(re, c0 + cn);
+    for (int e = lo; e < hi; ++e) sum += term[e - c0];
+    __syncthreads();
+  }
+  if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
+}
+
+// ---- fused day step ---------------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_fused(Dev d) {
+  __shared__ int wpre[TILE / 64];
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  const bool live = i < tl.z;
+  const RepInfo& ri = d.rep[tl.x];
+  const int t = *d.day;
+  AgentState a;
+  int age = 0;
+  if (live) {
+    a = d.state[i];
+    age = d.age[i];
+  }
+  bool dose1 = false, dose2 = false;
+  if (d.vacc_on) {
+    const int bstar = d.vplan[2 * tl.x];
+    const int quota = d.vplan[2 * tl.x + 1];
+    if (bstar >= 0) {
+      const int b = live ? vacc_bucket(d, a, t, age, ri.delay) : NBUCKET;
+      bool dose = b < bstar;
+      const bool inb = (b == bstar);
+      // rank among this tile's members of the partial class, in agent order
+      const unsigned long long m = __ballot(inb);
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+      if (lane == 0) wpre[wv] = __popcll(m);
+      __syncthreads();
+      int before = 0;
+      for (int q = 0; q < wv; ++q) before += wpre[q];
+      if (inb && bstar < NBUCKET) {
+        const int rank = d.vtile_base[blockIdx.x] + before + __popcll(m & lt);
+        dose = rank < quota;
+      }
+      if (dose) {
+        if (a.vacc == 0) {
+          a.vacc = 1;
+          a.d1 = (int16_t)t;
+          dose1 = true;
+        } else {
+          a.vacc = 2;
+          a.d2 = (int16_t)t;
+          dose2 = true;
+        }
+      }
+    }
+  }
+  bool is_new = false, near = false, tested = false;
+  if (live) {
+    const uint32_t loc = (uint32_t)(i - ri.start);
+    bool immune = false;
+    if (a.d1 != ABM_NEVER) {
+      const uint4 bv = philox(loc, (uint32_t)(int)a.d1, ri.stream, P_VACC << 24, d.key0, d.key1);
+      const float uv = u01(bv.x);
+      immune = (t >= (int)a.d1 + d.dose_lag && uv < d.eff1) ||
+               (a.d2 != ABM_NEVER && t >= (int)a.d2 + d.dose_lag && uv < d.eff2);
+    }
+    const uint4 b = philox(loc, (uint32_t)t, ri.stream, P_AGENT << 24, d.key0, d.key1);
+    const int st0 = a.stage;
+    const int tau = t - (int)a.t_exp;
+    if (st0 == ABM_STAGE_S) {
+      if (!immune) {
+        const double p = -expm1(-(double)d.lambda[i] * (double)d.dt);
+        const double u = (double)u01(b.x);
+        if (u < p) {
+          a.stage = ABM_STAGE_E;
+          a.t_exp = (int16_t)t;
+          is_new = true;
+        }
+        near = fabs(u - p) <= 1e-6;
+      }
+    } else if (st0 == ABM_STAGE_E) {
+      if (tau == d.e_days) a.stage = ABM_STAGE_I;
+    } else if (st0 == ABM_STAGE_I) {
+      if (tau == d.e_days + d.i_days) a.stage = u01(b.y) < d.p_death[age] ? ABM_STAGE_M : ABM_STAGE_R;
+    }
+    if (d.test_rate > 0.f && st0 != ABM_STAGE_M && t >= (int)a.q_until && !(a.flags & 1)) {
+      if (u01(b.z) < d.test_rate) {
+        tested = true;
+        const bool pos = (st0 == ABM_STAGE_E || st0 == ABM_STAGE_I) && u01(b.w) < d.sens;
+        a.flags = (uint8_t)(1 | (pos ? 2 : 0));
+        a.test_day = (int16_t)t;
+      }
+    }
+    d.state[i] = a;
+  }
+  const int st = live ? (int)a.stage : -1;
+  const bool v[10] = {st == 0, st == 1, st == 2, st == 3, st == 4, is_new, tested, dose1, dose2, near};
+  const int sl[10] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_NEW, ABM_C_TESTS,
+                      ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR};
+  block_count_add<10>(v, sl, d.counts_day + (size_t)tl.x * ABM_NC);
+}
+
+// ---- end of day: counts -> trajectory, edges per replicate, advance the day ---------
+__global__ __launch_bounds__(TILE) void k_finalize(Dev d) {
+  const int t = *d.day;
+  const bool ok = *d.flags == 0;
+  for (int k = threadIdx.x; k < d.R * ABM_NC; k += TILE) {
+    const int r = k / ABM_NC, c = k % ABM_NC;
+    long long v = (long long)d.counts_day[k];
+    if (c == ABM_C_EDGES)
+      v = ok ? (long long)d.row_ptr[d.rep[r].start + d.rep[r].n] - d.row_ptr[d.rep[r].start] : 0;
+    if (t < d.T) d.traj[(size_t)t * d.R * ABM_NC + k] = v;
+    d.prev_counts[k] = v;
+    d.counts_day[k] = 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *d.day = t + 1;
+}
+
+// ---- initial state: everyone susceptible, seeds exposed on day -1 --------------------
+__global__ __launch_bounds__(TILE) void k_init_state(Dev d) {
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (i >= d.N) return;
+  AgentState a;
+  a.stage = ABM_STAGE_S;
+  a.flags = 0;
+  a.vacc = 0;
+  a.reserved = 0;
+  a.t_exp = ABM_NEVER;
+  a.q_until = ABM_NEVER;
+  a.test_day = ABM_NEVER;
+  a.d1 = ABM_NEVER;
+  a.d2 = ABM_NEVER;
+  a.pad = 0;
+  d.state[i] = a;
+  d.code[i] = 0;
+  d.lambda[i] = 0.f;
+}
+
+__global__ void k_seed(Dev d, const int32_t* seeds, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = seeds[k];
+  d.state[i].stage = ABM_STAGE_E;
+  d.state[i].t_exp = -1;
+}
+
+__global__ void k_zero_counts(Dev d) {
+  for (int k = threadIdx.x; k < d.R * ABM_NC; k += blockDim.x) {
+    d.counts_day[k] = 0ull;
+    d.prev_counts[k] = 0;
+  }
+}
+
+// Stage counts of the current state into prev_counts (for the prevalence latch).
+__global__ __launch_bounds__(TILE) void k_recount(Dev d) {
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  const int st = i < tl.z ? (int)d.state[i].stage : -1;
+  const bool v[5] = {st == 0, st == 1, st == 2, st == 3, st == 4};
+  const int sl[5] = {0, 1, 2, 3, 4};
+  block_count_add<5>(v, sl, reinterpret_cast<unsigned long long*>(d.prev_counts) + (size_t)tl.x * ABM_NC);
+}
+
+__global__ void k_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint4 r = philox(ctr[4 * k], ctr[4 * k + 1], ctr[4 * k + 2], ctr[4 * k + 3],
+                         (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
+  out[4 * k] = r.x;
+  out[4 * k + 1] = r.y;
+  out[4 * k + 2] = r.z;
+  out[4 * k + 3] = r.w;
+}
+
+__global__ void k_set_day(Dev d, int32_t day) { *d.day = day; }
+
+void launch_pre(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_pre, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_vplan(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
+}
+void launch_message(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_message, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_fused(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_finalize(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TILE), 0, s, d);
+}
+void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3((d.N + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+  if (nseeds > 0)
+    hipLaunchKernelGGL(k_seed, dim3((unsigned)((nseeds + 255) / 256)), dim3(256), 0, s, d, seeds, nseeds);
+}
+void launch_recount(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_recount, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, ctr, n, out);
+}
+void launch_set_day(const Dev& d, int32_t day, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_day, dim3(1), dim3(1), 0, s, d, day);
+}
+
+}  // namespace abm

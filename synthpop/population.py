@@ -44,6 +44,7 @@ class Population:
     susceptibility: np.ndarray        # float32 [R, 9]
     dose2_delay: np.ndarray           # int32 [R]
     meta: dict = field(default_factory=dict)
+    stream: np.ndarray | None = None  # uint32 [R] Philox stream word per replicate (None: r)
 
     @property
     def n_agents(self) -> int:
@@ -189,3 +190,30 @@ def replicate_population(pop: Population, n: int, R=None, susceptibility=None,
     return Population(off, np.tile(pop.age, n), hh.astype(np.int32), np.tile(pop.occupation, n),
                       wps.astype(np.int32), wpm.astype(np.int32), ioff, init.astype(np.int32),
                       Rv, sus, dd, meta=dict(pop.meta, replicated=n))
+
+
+def extract_replicate(pop: Population, r: int) -> Population:
+    """Replicate r of a batch as a stand-alone population that keeps its Philox stream
+    word (so that a run of it alone reproduces its part of the batched run)."""
+    lo, hi = int(pop.agent_offset[r]), int(pop.agent_offset[r + 1])
+    hs = np.asarray(pop.hh_start, np.int64)
+    h0, h1 = int(np.searchsorted(hs, lo)), int(np.searchsorted(hs, hi))
+    wps = np.asarray(pop.wp_start, np.int64)
+    mem = np.asarray(pop.wp_members, np.int64)
+    sel_w = [w for w in range(wps.size - 1) if wps[w + 1] > wps[w] and lo <= mem[wps[w]] < hi]
+    if sel_w:
+        sizes = np.array([wps[w + 1] - wps[w] for w in sel_w])
+        wp_start = np.concatenate([[0], np.cumsum(sizes)])
+        wpm = np.concatenate([mem[wps[w]:wps[w + 1]] for w in sel_w]) - lo
+    else:
+        wp_start, wpm = np.zeros(1, np.int64), np.zeros(0, np.int64)
+    i0, i1 = int(pop.init_offset[r]), int(pop.init_offset[r + 1])
+    words = np.arange(pop.n_replicates) if pop.stream is None else np.asarray(pop.stream)
+    return Population(np.array([0, hi - lo], np.int64), pop.age[lo:hi].copy(),
+                      (hs[h0:h1 + 1] - lo).astype(np.int32), pop.occupation[lo:hi].copy(),
+                      wp_start.astype(np.int32), wpm.astype(np.int32),
+                      np.array([0, i1 - i0], np.int64),
+                      (np.asarray(pop.initial_infected[i0:i1], np.int64) - lo).astype(np.int32),
+                      pop.R[r:r + 1].copy(), pop.susceptibility[r:r + 1].copy(),
+                      pop.dose2_delay[r:r + 1].copy(), meta=dict(pop.meta, extracted=r),
+                      stream=np.array([words[r]], np.uint32))

@@ -1,0 +1,59 @@
+"""Shared test helpers: state conversion between the oracle and the library, skips."""
+import numpy as np
+import pytest
+
+from oracle import step as ostep
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def require_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def to_records(st, dtype):
+    """Oracle state dict -> array of the library's 16-byte agent records."""
+    N = st["stage"].size
+    rec = np.zeros(N, dtype)
+    rec["stage"] = st["stage"]
+    rec["flags"] = st["pending"].astype(np.uint8) | (st["positive"].astype(np.uint8) << 1)
+    rec["vacc"] = st["vacc"]
+    for k in ("t_exp", "q_until", "test_day", "d1", "d2"):
+        rec[k] = st[k]
+    return rec
+
+
+def from_records(rec, latch):
+    """Library records -> oracle state dict."""
+    st = dict(stage=rec["stage"].astype(np.int64), t_exp=rec["t_exp"].astype(np.int64),
+              q_until=rec["q_until"].astype(np.int64), test_day=rec["test_day"].astype(np.int64),
+              pending=(rec["flags"] & 1).astype(bool), positive=(rec["flags"] & 2).astype(bool),
+              vacc=rec["vacc"].astype(np.int64), d1=rec["d1"].astype(np.int64),
+              d2=rec["d2"].astype(np.int64), latch=np.asarray(latch, bool).copy())
+    return st
+
+
+FIELDS = ("stage", "t_exp", "q_until", "test_day", "pending", "positive", "vacc", "d1", "d2")
+
+
+def state_mismatch(a, b):
+    """Agents whose state differs between two oracle-format states."""
+    bad = np.zeros(a["stage"].size, bool)
+    for k in FIELDS:
+        bad |= a[k] != b[k]
+    return np.flatnonzero(bad)
+
+
+def lam_close(lam_gpu, lam_ora, rtol=1e-5):
+    lam_gpu = lam_gpu.astype(np.float64)
+    zero = lam_ora == 0
+    ok_zero = np.all(lam_gpu[zero] == 0)
+    err = np.abs(lam_gpu - lam_ora) / np.maximum(np.abs(lam_ora), 1e-300)
+    return ok_zero and bool(np.all(err[~zero] <= rtol)), float(err[~zero].max(initial=0.0))

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and exports every
+function include/abm.h declares, the ctypes structs have the C layout, and parameter,
+ABI and workspace errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2110_04421_amd import _lib as L
+from synthpop import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "abm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(abm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.lib()
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(L.exported_symbols()) == declared
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "abm.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(abm_params),'
+                   ' offsetof(abm_params, mu_random), offsetof(abm_params, vacc_rate),'
+                   ' offsetof(abm_params, edge_capacity), sizeof(abm_population));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals == [C.sizeof(L.AbmParams), L.AbmParams.mu_random.offset, L.AbmParams.vacc_rate.offset,
+                    L.AbmParams.edge_capacity.offset, C.sizeof(L.AbmPopulation)]
+
+
+def _ws(p, pop):
+    lib = L.lib()
+    P = L.make_params(p)
+    Q, keep = L.make_population(pop)
+    n = C.c_size_t(0)
+    rc = lib.abm_workspace_size(C.byref(P), C.byref(Q), C.byref(n))
+    return rc, n.value, P, Q, keep
+
+
+def test_workspace_size_and_errors():
+    p, pop = workload(0)
+    rc, n, *_ = _ws(p, pop)
+    assert rc == 0 and n > 1000 * 61
+    rc, *_ = _ws(dict(p, e_days=40, i_days=30), pop)
+    assert rc == -1
+    rc, *_ = _ws(dict(p, mu_random=[100.0] * 9), pop)
+    assert rc == -1
+    rc, *_ = _ws(dict(p, test_rate=0.1, test_delay=0), pop)
+    assert rc == -1
+    bad = workload(0)[1]
+    bad.hh_start = bad.hh_start.copy()
+    bad.hh_start[-1] -= 1
+    rc, *_ = _ws(p, bad)
+    assert rc == -1
+    rc, *_ = _ws(dict(p, edge_capacity=2**31), pop)
+    assert rc == -4
+
+
+def test_abi_mismatch_and_small_workspace_fail_before_device_work():
+    lib = L.lib()
+    p, pop = workload(0)
+    rc, n, P, Q, keep = _ws(p, pop)
+    P.struct_size = P.struct_size - 8
+    h = C.c_void_p()
+    assert lib.abm_workspace_size(C.byref(P), C.byref(Q), C.byref(C.c_size_t())) == -2
+    assert lib.abm_create(C.byref(P), C.byref(Q), C.c_void_p(16), n, None, C.byref(h)) == -2
+    assert b"mismatch" in lib.abm_last_error(h)
+    lib.abm_destroy(h)
+    P.struct_size = C.sizeof(L.AbmParams)
+    h = C.c_void_p()
+    assert lib.abm_create(C.byref(P), C.byref(Q), C.c_void_p(16), n - 1, None, C.byref(h)) == -3
+    assert lib.abm_step(h, 1) == -3          # sticky
+    lib.abm_destroy(h)
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        L.lib()
