@@ -1,0 +1,247 @@
+#!/usr/bin/env python
+"""Throughput of the DeepABM-COVID daily step on one MI355X.
+
+One step = one simulated day of the whole hot path (graph build, force of infection,
+fused infection/progression, testing, quarantine, vaccination) over the workload.
+Default workload: 50M agents, 20 contacts per agent per day (about 1e9 directed edges
+per day), interventions on.  W warm-up days, then K timed days (W + K = 180 by default:
+one full run).  value = edge-interactions per second over the timed days, where an
+edge-interaction is one directed edge of a day's contact graph.
+
+Extras on the same JSON line: the 100k-agent, 180-day run (the paper's 200M-interaction
+workload) with the paper's figure for context; the 256-replicate ensemble in one launch
+vs the same replicates run one by one; the per-kernel roofline of the dominant kernel;
+and the FP64 CPU oracle timed on a bounded sample of the 100k-agent workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge-interactions/s at 100k & 50M agents (HBM GB/s); batched replicates/s vs plain"
+HBM_PEAK_GBS = 8000.0
+PAPER_C1_RATE = 200e6 / 90.0      # 200M interactions in about 90 s (abstract, section 1)
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def household_edges(pop) -> int:
+    s = np.diff(np.asarray(pop.hh_start, np.int64))
+    return int((s * (s - 1)).sum())
+
+
+def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool) -> float:
+    """Algorithmic HBM bytes of one launch (one day) of a kernel.  E = directed edges of
+    the day, C = contacts drawn (each gives two edges), N = agents."""
+    if name == "message":      # col + w + 1-byte code gather per edge; row_ptr, age, lambda per row
+        return 9.0 * E + 9.0 * N
+    if name == "fill":         # write col + w per edge; claim RMW per received edge; per-agent reads
+        return 8.0 * E + 8.0 * C + 24.0 * N
+    if name == "count":        # static record, own counts; RMW per received edge
+        return 18.0 * N + 8.0 * C
+    if name == "canon":        # counts, row start, received blocks read + written
+        return 11.0 * N + 8.0 * C
+    if name == "scan":         # two passes over degree parts, row_ptr + 2 cursors written
+        return 26.0 * N
+    if name == "pre":          # state read, code + cleared counter written (+ age for classes)
+        return (22.0 if vacc else 21.0) * N
+    if name == "fused":        # state read + written, lambda, age
+        return 37.0 * N
+    return 0.0
+
+
+def time_days(sim, W: int, K: int):
+    import torch
+    if W:
+        sim.run(W)
+    sim.profile_reset() if sim_profiled(sim) else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counts = sim.run(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return counts, t1 - t0
+
+
+def sim_profiled(sim) -> bool:
+    return bool(sim._p.flags & 1)
+
+
+def cpu_baseline(budget_s: float = 15.0):
+    """The FP64 oracle, as it stands, on the first days of the 100k-agent workload."""
+    from synthpop import workload
+    from oracle import step as ostep
+    p, pop = workload(1)
+    m = ostep.Model(pop, p)
+    st = m.init_state()
+    prev = np.zeros((1, ostep.NC), np.int64)
+    prev[:, :5] = m.counts_of(st)
+    edges, days = 0, 0
+    t0 = time.perf_counter()
+    while days < 2 or (time.perf_counter() - t0 < budget_s and days < 180):
+        st, out = m.step(st, days, prev)
+        prev = out["counts"]
+        edges += int(out["counts"][0, ostep.C_EDGES])
+        days += 1
+    wall = time.perf_counter() - t0
+    return {"value": edges / wall, "unit": "edge-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"plain-100k (100,000 agents), days 0..{days - 1} of 180, FP64 numpy oracle, "
+                      f"one process; {edges} edge-interactions in {wall:.1f} s"}
+
+
+def c1_run(reps: int = 3):
+    """Full 180-day runs of the 100k-agent workload (HIP-graph day loop)."""
+    import torch
+    from paper_2110_04421_amd.sim import Simulator
+    from synthpop import workload
+    p, pop = workload(1)
+    walls, edges = [], 0
+    with Simulator(p, pop) as s:
+        init, latch = s.state(), np.zeros(1, np.uint8)
+        s.run(180)                                  # warm-up run
+        for _ in range(reps):
+            s.set_state(0, latch, init)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = s.run(180)
+            walls.append(time.perf_counter() - t0)
+            edges = int(c[:, 0, 10].sum())
+    wall = statistics.median(walls)
+    return {"workload": "plain-100k", "agents": 100_000, "days": 180,
+            "edge_interactions": edges, "seconds_per_run": wall,
+            "value": edges / wall, "unit": "edge-interactions/s",
+            "paper_context": {"value": PAPER_C1_RATE, "note": "200M interactions in about 90 s on an "
+                              "unnamed GPU (abstract, section 1); not the same hardware"},
+            "ratio_vs_paper_context": (edges / wall) / PAPER_C1_RATE}
+
+
+def batched_vs_plain(n_rep: int = 256):
+    """256 replicates (10k-500k agents each) in one launch vs one by one."""
+    import torch
+    from paper_2110_04421_amd.sim import Simulator
+    from synthpop import workload, split_replicates
+    p, pop = workload(3, n_rep=n_rep)
+    with Simulator(p, pop) as s:
+        s.run(1)
+        s.set_state(0, np.zeros(n_rep, np.uint8), _initial(s, pop))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cb = s.run(180)
+        tb = time.perf_counter() - t0
+    subs = split_replicates(pop)
+    ts, equal = 0.0, True
+    for r, sub in enumerate(subs):
+        with Simulator(p, sub) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cs = s.run(180)
+            ts += time.perf_counter() - t0
+        equal &= bool(np.array_equal(cs[:, 0, :], cb[:, r, :]))
+    return {"workload": "batched-256", "replicates": n_rep, "agents": int(pop.n_agents),
+            "batched_seconds": tb, "sequential_seconds": ts,
+            "batched_replicates_per_s": n_rep / tb, "sequential_replicates_per_s": n_rep / ts,
+            "speedup": ts / tb, "per_replicate_bit_equal": equal}
+
+
+def _initial(sim, pop):
+    rec = np.zeros(sim.N, sim.state().dtype)
+    rec["t_exp"] = rec["q_until"] = rec["test_day"] = rec["d1"] = rec["d2"] = -32768
+    seeds = np.asarray(pop.initial_infected, np.int64)
+    rec["stage"][seeds] = 1
+    rec["t_exp"][seeds] = -1
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=175, help="timed days")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed days before the timed ones")
+    ap.add_argument("--workload", default="plain-50M", choices=["plain-50M", "plain-100k"])
+    ap.add_argument("--n", type=int, default=None, help="override the agent count (testing)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 100k, batched and CPU legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(replicates and agent ranges would shard across GPUs; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.warmup + args.steps > 180:
+        sys.exit("warmup + steps must be <= 180 (one run)")
+    import torch
+    from paper_2110_04421_amd.sim import Simulator
+    from synthpop import workload
+    k = 2 if args.workload == "plain-50M" else 1
+    log(f"generating {args.workload}")
+    p, pop = workload(k, n=args.n)
+    N = pop.n_agents
+    log(f"{N} agents; creating the simulation")
+    ehh = household_edges(pop)
+    with Simulator(p, pop, profile=True) as sim:
+        log(f"warm-up {args.warmup} days, timing {args.steps} days")
+        counts, wall = time_days(sim, args.warmup, args.steps)
+        prof = sim.profile()
+    log(f"timed {args.steps} days in {wall:.3f} s")
+    E_days = counts[:, :, 10].sum(axis=1).astype(np.float64)
+    E_tot = float(E_days.sum())
+    E_mean = float(E_days.mean())
+    C_mean = (E_mean - ehh) / 2.0
+    vacc = p["vacc_rate"] > 0
+    kernels = {}
+    for name, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        b = kernel_bytes(name, N, E_mean, C_mean, vacc)
+        kernels[name] = {"ms_per_launch": avg, "launches": n,
+                         "algorithmic_GB": b / 1e9,
+                         "GB_per_s": (b / 1e9) / (avg / 1e3) if b and avg > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
+    dk = kernels[dom]
+    achieved = dk["GB_per_s"] or 0.0
+    step_bytes = sum(kernel_bytes(nm, N, E_mean, C_mean, vacc) for nm in kernels)
+    step_ms = sum(v["ms_per_launch"] for v in kernels.values())
+    line = {
+        "metric": METRIC,
+        "value": E_tot / wall,
+        "unit": "edge-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "agents": N, "days_timed": args.steps,
+                   "edges_per_day": E_mean, "contacts_per_agent_day": E_mean / N,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": dk["algorithmic_GB"] * 1e9,
+                     "step_kernels_GB_per_s": (step_bytes / 1e9) / (step_ms / 1e3),
+                     "step_kernels_frac": (step_bytes / 1e9) / (step_ms / 1e3) / HBM_PEAK_GBS},
+        "kernels": kernels,
+    }
+    if not args.no_extras:
+        log("100k-agent runs")
+        line["c1"] = c1_run()
+        log("batched ensemble vs one by one")
+        line["batched"] = batched_vs_plain()
+    if not args.no_extras and not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

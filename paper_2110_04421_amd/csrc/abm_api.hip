@@ -111,9 +111,10 @@ struct abm_sim {
   bool soft_ready = false;
   std::vector<RepInfo> reps;
   char* ws = nullptr;
-  // profiling
+  // profiling: one set of NK + 1 events per day enqueued since the last read-out
   static constexpr int NK = 9;
-  hipEvent_t ev[NK + 1] = {};
+  std::vector<std::vector<hipEvent_t>> prof_sets;
+  size_t prof_used = 0;
   double ms[NK] = {};
   int64_t launches[NK] = {};
 
@@ -319,11 +320,11 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   total = L.total;
 }
 
-void enqueue_day(abm_sim* s, hipStream_t st, bool timed) {
+void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) {
   const Dev& d = s->d;
   int k = 0;
   auto mark = [&]() {
-    if (timed) (void)hipEventRecord(s->ev[k], st);
+    if (ev) (void)hipEventRecord((*ev)[k], st);
     ++k;
   };
   mark();
@@ -344,7 +345,24 @@ void enqueue_day(abm_sim* s, hipStream_t st, bool timed) {
   launch_fused(d, st);
   mark();
   launch_finalize(d, st);
-  if (timed) (void)hipEventRecord(s->ev[abm_sim::NK], st);
+  if (ev) (void)hipEventRecord((*ev)[abm_sim::NK], st);
+}
+
+// Accumulate the per-kernel times of every profiled day enqueued so far.
+int drain_profile(abm_sim* s) {
+  if (s->prof_used == 0) return ABM_OK;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (size_t q = 0; q < s->prof_used; ++q) {
+    const std::vector<hipEvent_t>& ev = s->prof_sets[q];
+    for (int k = 0; k < abm_sim::NK; ++k) {
+      float ms = 0.f;
+      HIPCHK(s, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      s->ms[k] += ms;
+      s->launches[k] += 1;
+    }
+  }
+  s->prof_used = 0;
+  return ABM_OK;
 }
 
 int check_dev_flags(abm_sim* s) {
@@ -568,12 +586,11 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   }
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipStreamSynchronize(st));
-  for (int k = 0; k <= abm_sim::NK; ++k) HIPCHK(s, hipEventCreate(&s->ev[k]));
   const bool use_graph = !(p->flags & (ABM_FLAG_PROFILE | ABM_FLAG_NO_GRAPH)) && p->mode == ABM_HARD;
   if (use_graph) {
     HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_day(s, s->cap_stream, false);
+    enqueue_day(s, s->cap_stream, nullptr);
     HIPCHK(s, hipStreamEndCapture(s->cap_stream, &s->graph));
     HIPCHK(s, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
   }
@@ -591,18 +608,19 @@ int abm_step(abm_sim* s, int32_t n_days) {
   for (int k = 0; k < n_days; ++k) {
     if (s->exec) {
       HIPCHK(s, hipGraphLaunch(s->exec, s->stream));
-    } else {
-      enqueue_day(s, s->stream, timed);
-      HIPCHK(s, hipGetLastError());
-      if (timed) {
-        HIPCHK(s, hipEventSynchronize(s->ev[abm_sim::NK]));
-        for (int q = 0; q < abm_sim::NK; ++q) {
-          float ms = 0.f;
-          HIPCHK(s, hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]));
-          s->ms[q] += ms;
-          s->launches[q] += 1;
-        }
+    } else if (timed) {
+      if (s->prof_used == s->prof_sets.size()) {
+        std::vector<hipEvent_t> ev(abm_sim::NK + 1);
+        for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
+        s->prof_sets.push_back(ev);
       }
+      const std::vector<hipEvent_t>* ev = &s->prof_sets[s->prof_used];
+      ++s->prof_used;
+      enqueue_day(s, s->stream, ev);
+      HIPCHK(s, hipGetLastError());
+    } else {
+      enqueue_day(s, s->stream, nullptr);
+      HIPCHK(s, hipGetLastError());
     }
     ++s->host_day;
   }
@@ -703,8 +721,8 @@ void abm_destroy(abm_sim* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
-  for (int k = 0; k <= abm_sim::NK; ++k)
-    if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+  for (auto& ev : s->prof_sets)
+    for (auto e : ev) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -727,6 +745,9 @@ int abm_profile_kernels(void) { return abm_sim::NK; }
 const char* abm_profile_name(int32_t k) { return (k >= 0 && k < abm_sim::NK) ? kKernelNames[k] : ""; }
 int abm_profile_get(abm_sim* s, double* h_ms, int64_t* h_launches) {
   if (!s) return ABM_E_ARG;
+  if (s->err) return s->err;
+  const int rc = drain_profile(s);
+  if (rc) return rc;
   for (int k = 0; k < abm_sim::NK; ++k) {
     if (h_ms) h_ms[k] = s->ms[k];
     if (h_launches) h_launches[k] = s->launches[k];
@@ -735,6 +756,9 @@ int abm_profile_get(abm_sim* s, double* h_ms, int64_t* h_launches) {
 }
 int abm_profile_reset(abm_sim* s) {
   if (!s) return ABM_E_ARG;
+  if (s->err) return s->err;
+  const int rc = drain_profile(s);
+  if (rc) return rc;
   for (int k = 0; k < abm_sim::NK; ++k) {
     s->ms[k] = 0;
     s->launches[k] = 0;

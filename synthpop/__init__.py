@@ -5,5 +5,6 @@ populations (ages, households, occupations, workplaces, initial infections) and
 holds the parameter sets of the workloads.  Both sides receive these arrays as
 inputs; neither side's computation lives here.
 """
-from .population import Population, make_population, replicate_population, extract_replicate  # noqa: F401
+from .population import (Population, make_population, replicate_population,  # noqa: F401
+                         extract_replicate, split_replicates)
 from .configs import workload, WORKLOADS  # noqa: F401

@@ -200,11 +200,13 @@ def extract_replicate(pop: Population, r: int) -> Population:
     h0, h1 = int(np.searchsorted(hs, lo)), int(np.searchsorted(hs, hi))
     wps = np.asarray(pop.wp_start, np.int64)
     mem = np.asarray(pop.wp_members, np.int64)
-    sel_w = [w for w in range(wps.size - 1) if wps[w + 1] > wps[w] and lo <= mem[wps[w]] < hi]
-    if sel_w:
-        sizes = np.array([wps[w + 1] - wps[w] for w in sel_w])
-        wp_start = np.concatenate([[0], np.cumsum(sizes)])
-        wpm = np.concatenate([mem[wps[w]:wps[w + 1]] for w in sel_w]) - lo
+    sizes = np.diff(wps)
+    if sizes.size:
+        first = mem[np.minimum(wps[:-1], max(mem.size - 1, 0))]
+        keep = (sizes > 0) & (first >= lo) & (first < hi)
+        ks = sizes[keep]
+        wp_start = np.concatenate([[0], np.cumsum(ks)])
+        wpm = mem[np.repeat(keep, sizes)] - lo
     else:
         wp_start, wpm = np.zeros(1, np.int64), np.zeros(0, np.int64)
     i0, i1 = int(pop.init_offset[r]), int(pop.init_offset[r + 1])
@@ -217,3 +219,37 @@ def extract_replicate(pop: Population, r: int) -> Population:
                       pop.R[r:r + 1].copy(), pop.susceptibility[r:r + 1].copy(),
                       pop.dose2_delay[r:r + 1].copy(), meta=dict(pop.meta, extracted=r),
                       stream=np.array([words[r]], np.uint32))
+
+
+def split_replicates(pop: Population):
+    """All replicates of a batch as stand-alone populations (``extract_replicate`` for
+    every r, computed in one pass)."""
+    off = np.asarray(pop.agent_offset, np.int64)
+    hs = np.asarray(pop.hh_start, np.int64)
+    wps = np.asarray(pop.wp_start, np.int64)
+    mem = np.asarray(pop.wp_members, np.int64)
+    sizes = np.diff(wps)
+    wrep = np.searchsorted(off, mem[wps[:-1]], side="right") - 1 if sizes.size else np.zeros(0, np.int64)
+    order = np.argsort(wrep, kind="stable")
+    sizes_o = sizes[order]
+    mem_o = np.concatenate([mem[wps[w]:wps[w + 1]] for w in order]) if order.size else mem
+    wstart_o = np.concatenate([[0], np.cumsum(sizes_o)])
+    wr_bounds = np.searchsorted(wrep[order], np.arange(off.size))
+    words = np.arange(pop.n_replicates) if pop.stream is None else np.asarray(pop.stream)
+    out = []
+    for r in range(pop.n_replicates):
+        lo, hi = int(off[r]), int(off[r + 1])
+        h0, h1 = int(np.searchsorted(hs, lo)), int(np.searchsorted(hs, hi))
+        w0, w1 = int(wr_bounds[r]), int(wr_bounds[r + 1])
+        ws = wstart_o[w0:w1 + 1] - wstart_o[w0]
+        wm = mem_o[wstart_o[w0]:wstart_o[w1]] - lo
+        i0, i1 = int(pop.init_offset[r]), int(pop.init_offset[r + 1])
+        out.append(Population(
+            np.array([0, hi - lo], np.int64), pop.age[lo:hi].copy(),
+            (hs[h0:h1 + 1] - lo).astype(np.int32), pop.occupation[lo:hi].copy(),
+            ws.astype(np.int32), wm.astype(np.int32), np.array([0, i1 - i0], np.int64),
+            (np.asarray(pop.initial_infected[i0:i1], np.int64) - lo).astype(np.int32),
+            pop.R[r:r + 1].copy(), pop.susceptibility[r:r + 1].copy(),
+            pop.dose2_delay[r:r + 1].copy(), meta=dict(pop.meta, extracted=r),
+            stream=np.array([words[r]], np.uint32)))
+    return out
