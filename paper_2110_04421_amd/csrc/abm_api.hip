@@ -82,7 +82,7 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, lambda, own, recv, row_ptr,
+  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, counts_day, prev_counts,
       traj, day, flags, seeds;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
@@ -112,7 +112,7 @@ struct abm_sim {
   std::vector<RepInfo> reps;
   char* ws = nullptr;
   // profiling: one set of NK + 1 events per day enqueued since the last read-out
-  static constexpr int NK = 9;
+  static constexpr int NK = 10;
   std::vector<std::vector<hipEvent_t>> prof_sets;
   size_t prof_used = 0;
   double ms[NK] = {};
@@ -132,8 +132,8 @@ struct abm_sim {
   }
 };
 
-static const char* kKernelNames[abm_sim::NK] = {"pre",  "vplan",   "count", "scan",    "fill",
-                                                 "canon", "message", "fused", "finalize"};
+static const char* kKernelNames[abm_sim::NK] = {"pre",   "mask",    "vplan", "count",   "scan",
+                                                 "fill",  "canon",   "message", "fused", "finalize"};
 
 #define HIPCHK(s, x)                                                              \
   do {                                                                            \
@@ -279,7 +279,8 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.atab = L.take<float>(ATAB);
   o.ptab = L.take<uint32_t>(NPT * 64);
   o.state = L.take<AgentState>(z.N);
-  o.code = L.take<uint8_t>(z.N);
+  o.code = L.take<uint8_t>(z.N + 32);
+  o.imask = L.take<uint32_t>((z.N + 31) / 32 + 1);
   o.lambda = L.take<float>(z.N);
   o.own = L.take<uint16_t>(z.N);
   o.recv = L.take<uint32_t>(z.N);
@@ -329,6 +330,8 @@ void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) 
   };
   mark();
   launch_pre(d, st);
+  mark();
+  launch_mask(d, st);
   mark();
   if (d.vacc_on) launch_vplan(d, st);
   mark();
@@ -455,6 +458,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.ptab = (const uint32_t*)(ws + o.ptab);
   d.state = (AgentState*)(ws + o.state);
   d.code = (uint8_t*)(ws + o.code);
+  d.imask = (uint32_t*)(ws + o.imask);
   d.lambda = (float*)(ws + o.lambda);
   d.own = (uint16_t*)(ws + o.own);
   d.recv = (uint32_t*)(ws + o.recv);

@@ -77,6 +77,7 @@ struct Dev {
 
   AgentState* state;
   uint8_t* code;
+  uint32_t* imask;              // bit i: agent i infectious today (code != 0)
   float* lambda;
 
   uint16_t* own;                // k_occ | k_rand << 8 (drawn by the agent)
@@ -158,6 +159,7 @@ __device__ __forceinline__ int poisson_k(const uint32_t* T, uint32_t x) {
 
 // ---- kernel launchers (one per translation unit that owns the kernel) ---------------
 void launch_pre(const Dev& d, hipStream_t s);
+void launch_mask(const Dev& d, hipStream_t s);
 void launch_vplan(const Dev& d, hipStream_t s);
 void launch_count(const Dev& d, hipStream_t s);
 void launch_scan(const Dev& d, hipStream_t s);

@@ -8,30 +8,96 @@
 //
 // Kernels: count (Poisson draws + atomic in-degree) -> scan (row pointers and claim
 // cursors) -> fill (own rows + claimed slots in partners' rows) -> canon (sort each
-// received block by initiator).  The Philox draws are recomputed in fill rather than
+// received block by initiator, write its weights).  The Philox draws are recomputed in fill rather than
 // stored: ALU is cheaper than a round trip of the partner list through HBM.
 #include "abm_internal.h"
 
 namespace abm {
 
-// Walk the k contacts drawn by agent (loc) in network `purpose`; draw d uses flat lane
-// d of the purpose's stream, lane 0 being the count.  f(d, partner) for d = 1..k.
-template <typename F>
-__device__ __forceinline__ int walk_contacts(const Dev& d, uint32_t purpose, uint32_t loc,
-                                             uint32_t t, uint32_t stream, const uint32_t* T,
-                                             uint32_t m, F&& f, int partner_base, bool rnd,
-                                             int32_t wp_lo, uint32_t pos) {
-  if (m < 2) return 0;
-  uint4 blk = philox(loc, t, stream, purpose << 24, d.key0, d.key1);
-  const int k = poisson_k(T, blk.x);
-  for (int q = 1; q <= k; ++q) {
-    if ((q & 3) == 0) blk = philox(loc, t, stream, (purpose << 24) | (uint32_t)(q >> 2), d.key0, d.key1);
+// Contacts drawn by one agent in one network: draw q (1..k) uses flat lane q of the
+// network's Philox stream, lane 0 giving the Poisson count k.  Partners are uniform
+// over the other m - 1 members of the agent's workplace (or replicate):
+//   partner = member[(pos + 1 + floor(x (m - 1) / 2^32)) mod m].
+struct ContactGen {
+  uint32_t loc, t, stream, purpose, k0, k1, m, pos;
+  int base;              // first agent of the replicate (random network)
+  int wp_lo;             // offset of the workplace in the member list
+  bool rnd;
+  uint4 blk;
+  uint32_t blk_id;
+
+  __device__ __forceinline__ int count(const uint32_t* T) {
+    if (m < 2) return 0;
+    blk = philox(loc, t, stream, purpose << 24, k0, k1);
+    blk_id = 0;
+    return poisson_k(T, blk.x);
+  }
+  __device__ __forceinline__ int partner(const Dev& d, int q) {
+    const uint32_t b = (uint32_t)q >> 2;
+    if (b != blk_id) {
+      blk = philox(loc, t, stream, (purpose << 24) | b, k0, k1);
+      blk_id = b;
+    }
     const uint32_t x = lane4(blk, q & 3);
     const uint32_t off = (uint32_t)(((uint64_t)x * (uint64_t)(m - 1)) >> 32);
     uint32_t slot = pos + 1 + off;
     if (slot >= m) slot -= m;
-    const int p = rnd ? partner_base + (int)slot : d.wp_members[wp_lo + (int)slot];
-    f(q, p);
+    return rnd ? base + (int)slot : d.wp_members[wp_lo + (int)slot];
+  }
+};
+
+__device__ __forceinline__ ContactGen occ_gen(const Dev& d, const StaticRec& sr, uint32_t loc,
+                                              uint32_t t, uint32_t stream) {
+  ContactGen g;
+  g.loc = loc; g.t = t; g.stream = stream; g.purpose = P_OCC; g.k0 = d.key0; g.k1 = d.key1;
+  g.m = sr.wp_n; g.pos = sr.wp_pos; g.base = 0; g.wp_lo = sr.wp_lo; g.rnd = false;
+  return g;
+}
+
+__device__ __forceinline__ ContactGen rand_gen(const Dev& d, const RepInfo& ri, uint32_t loc,
+                                               uint32_t t) {
+  ContactGen g;
+  g.loc = loc; g.t = t; g.stream = ri.stream; g.purpose = P_RAND; g.k0 = d.key0; g.k1 = d.key1;
+  g.m = (uint32_t)ri.n; g.pos = loc; g.base = ri.start; g.wp_lo = 0; g.rnd = true;
+  return g;
+}
+
+constexpr int CLAIM_BATCH = 8;   // contacts whose memory operations are issued together
+
+// In-degree from the other ends: one atomic increment per contact at its partner.
+__device__ __forceinline__ int count_contacts(const Dev& d, ContactGen& g, const uint32_t* T,
+                                              uint32_t inc) {
+  const int k = g.count(T);
+  for (int q0 = 1; q0 <= k; q0 += CLAIM_BATCH) {
+    int p[CLAIM_BATCH];
+#pragma unroll
+    for (int b = 0; b < CLAIM_BATCH; ++b) p[b] = (q0 + b <= k) ? g.partner(d, q0 + b) : -1;
+#pragma unroll
+    for (int b = 0; b < CLAIM_BATCH; ++b)
+      if (p[b] >= 0) atomicAdd(&d.recv[p[b]], inc);
+  }
+  return k;
+}
+
+// Own block (partners in draw order) and one claimed slot in each partner's received
+// block.  The claims of a batch are independent, so they are all in flight at once.
+__device__ __forceinline__ int fill_contacts(const Dev& d, ContactGen& g, const uint32_t* T,
+                                             int32_t* cursor, int own, int self, float wv) {
+  const int k = g.count(T);
+  for (int q0 = 1; q0 <= k; q0 += CLAIM_BATCH) {
+    int p[CLAIM_BATCH], slot[CLAIM_BATCH];
+#pragma unroll
+    for (int b = 0; b < CLAIM_BATCH; ++b) p[b] = (q0 + b <= k) ? g.partner(d, q0 + b) : -1;
+#pragma unroll
+    for (int b = 0; b < CLAIM_BATCH; ++b)
+      if (p[b] >= 0) slot[b] = atomicAdd(&cursor[p[b]], 1);
+#pragma unroll
+    for (int b = 0; b < CLAIM_BATCH; ++b)
+      if (p[b] >= 0) {
+        d.col[own + q0 + b - 1] = p[b];
+        d.w[own + q0 + b - 1] = wv;
+        d.col[slot[b]] = self;
+      }
   }
   return k;
 }
@@ -47,12 +113,10 @@ __global__ __launch_bounds__(TILE) void k_count(Dev d) {
   const uint32_t t = (uint32_t)(*d.day);
   const StaticRec sr = d.srec[i];
   const uint32_t loc = (uint32_t)(i - ri.start);
-  const int ko = walk_contacts(
-      d, P_OCC, loc, t, ri.stream, T + sr.occ * 64, sr.wp_n,
-      [&](int, int p) { atomicAdd(&d.recv[p], 1u << 16); }, 0, false, sr.wp_lo, sr.wp_pos);
-  const int kr = walk_contacts(
-      d, P_RAND, loc, t, ri.stream, T + (PT_AGE0 + sr.age) * 64, (uint32_t)ri.n,
-      [&](int, int p) { atomicAdd(&d.recv[p], 1u); }, ri.start, true, 0, loc);
+  ContactGen go = occ_gen(d, sr, loc, t, ri.stream);
+  const int ko = count_contacts(d, go, T + sr.occ * 64, 1u << 16);
+  ContactGen gr = rand_gen(d, ri, loc, t);
+  const int kr = count_contacts(d, gr, T + (PT_AGE0 + sr.age) * 64, 1u);
   d.own[i] = (uint16_t)(ko | (kr << 8));
 }
 
@@ -167,7 +231,7 @@ __global__ __launch_bounds__(TILE) void k_fill(Dev d) {
   const StaticRec sr = d.srec[i];
   const uint32_t loc = (uint32_t)(i - ri.start);
   int pos = d.row_ptr[i];
-  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // received blocks' weights: canon
   for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m) {
     if (m == i) continue;
     d.col[pos] = m;
@@ -175,27 +239,11 @@ __global__ __launch_bounds__(TILE) void k_fill(Dev d) {
     ++pos;
   }
   const int own_occ = pos;
-  const int ko = walk_contacts(
-      d, P_OCC, loc, t, ri.stream, T + sr.occ * 64, sr.wp_n,
-      [&](int q, int p) {
-        d.col[own_occ + q - 1] = p;
-        d.w[own_occ + q - 1] = wo;
-        const int slot = atomicAdd(&d.cur_occ[p], 1);
-        d.col[slot] = i;
-        d.w[slot] = wo;
-      },
-      0, false, sr.wp_lo, sr.wp_pos);
+  ContactGen go = occ_gen(d, sr, loc, t, ri.stream);
+  const int ko = fill_contacts(d, go, T + sr.occ * 64, d.cur_occ, own_occ, i, wo);
   const int own_rand = own_occ + ko + (int)(d.recv[i] >> 16);
-  walk_contacts(
-      d, P_RAND, loc, t, ri.stream, T + (PT_AGE0 + sr.age) * 64, (uint32_t)ri.n,
-      [&](int q, int p) {
-        d.col[own_rand + q - 1] = p;
-        d.w[own_rand + q - 1] = wr;
-        const int slot = atomicAdd(&d.cur_rand[p], 1);
-        d.col[slot] = i;
-        d.w[slot] = wr;
-      },
-      ri.start, true, 0, loc);
+  ContactGen gr = rand_gen(d, ri, loc, t);
+  fill_contacts(d, gr, T + (PT_AGE0 + sr.age) * 64, d.cur_rand, own_rand, i, wr);
 }
 
 // Insertion sort of a short received block by initiator id; weights are uniform
@@ -212,6 +260,38 @@ __device__ __forceinline__ void sort_block(int32_t* c, int n) {
   }
 }
 
+// Blocks of up to 16 ids are sorted in registers by a bitonic network (all indices
+// compile-time constants); longer ones (rare: Poisson tail) fall back to insertion.
+__device__ __forceinline__ void sort_small(int32_t* c, int n) {
+  if (n <= 1) return;
+  if (n > 16) {
+    sort_block(c, n);
+    return;
+  }
+  int32_t v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = k < n ? c[k] : 0x7FFFFFFF;
+#pragma unroll
+  for (int size = 2; size <= 16; size <<= 1)
+#pragma unroll
+    for (int stride = size / 2; stride > 0; stride >>= 1)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int l = k ^ stride;
+        if (l > k) {
+          const bool up = (k & size) == 0;
+          const int32_t a = v[k], b = v[l];
+          if ((a > b) == up) {
+            v[k] = b;
+            v[l] = a;
+          }
+        }
+      }
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < n) c[k] = v[k];
+}
+
 __global__ __launch_bounds__(TILE) void k_canon(Dev d) {
   if (*d.flags) return;
   const int i = blockIdx.x * TILE + threadIdx.x;
@@ -219,9 +299,11 @@ __global__ __launch_bounds__(TILE) void k_canon(Dev d) {
   const uint32_t o = d.own[i], r = d.recv[i];
   const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
   const int a = d.row_ptr[i] + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
-  if (ro > 1) sort_block(d.col + a, ro);
+  sort_small(d.col + a, ro);
+  for (int e = a; e < a + ro; ++e) d.w[e] = d.w_o;
   const int b = a + ro + (int)(o >> 8);
-  if (rr > 1) sort_block(d.col + b, rr);
+  sort_small(d.col + b, rr);
+  for (int e = b; e < b + rr; ++e) d.w[e] = d.w_r;
 }
 
 void launch_count(const Dev& d, hipStream_t s) {

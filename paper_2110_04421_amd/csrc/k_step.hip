@@ -80,6 +80,31 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   }
 }
 
+// ---- infectious bit mask: one 32-bit word per 32 agents ----------------------------
+// Most edges come from non-infectious sources; the message kernel tests a bit from this
+// 1-bit-per-agent mask (cache resident) before gathering the source's code byte.
+__global__ __launch_bounds__(TILE) void k_mask(Dev d) {
+  const int w = blockIdx.x * TILE + threadIdx.x;
+  const int nw = (d.N + 31) >> 5;
+  if (w >= nw) return;
+  const int i0 = w << 5;
+  uint32_t m = 0;
+  if (i0 + 32 <= d.N) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
+    const uint4 a = c4[0], b = c4[1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
+  } else {
+    for (int k = 0; i0 + k < d.N; ++k)
+      if (d.code[i0 + k]) m |= 1u << k;
+  }
+  d.imask[w] = m;
+}
+
 // ---- vaccination plan: one workgroup per replicate ------------------------------------
 // Latch on prevalence, then give the day's capacity to the priority classes in order;
 // the first class that does not fit entirely gets a quota filled by ascending agent id
@@ -180,8 +205,11 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
     const int cn = min(MSG_CHUNK, e1 - c0);
     for (int k = threadIdx.x; k < cn; k += TILE) {
       const int e = c0 + k;
-      const uint32_t src = (uint32_t)d.col[e];
-      term[k] = d.w[e] * atab[d.code[src < (uint32_t)d.N ? src : 0u]];
+      uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
+      const float we = __builtin_nontemporal_load(d.w + e);
+      src = src < (uint32_t)d.N ? src : 0u;
+      const bool inf = (d.imask[src >> 5] >> (src & 31u)) & 1u;
+      term[k] = inf ? we * atab[d.code[src]] : 0.f;
     }
     __syncthreads();
     const int lo = max(rs, c0), hi = min(re, c0 + cn);
@@ -361,6 +389,10 @@ __global__ void k_set_day(Dev d, int32_t day) { *d.day = day; }
 
 void launch_pre(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pre, dim3(d.ntiles), dim3(TILE), 0, s, d);
+}
+void launch_mask(const Dev& d, hipStream_t s) {
+  const int nw = (d.N + 31) >> 5;
+  hipLaunchKernelGGL(k_mask, dim3((nw + TILE - 1) / TILE), dim3(TILE), 0, s, d);
 }
 void launch_vplan(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
