@@ -442,6 +442,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.eff1 = p->eff1;
   d.eff2 = p->eff2;
   d.gtau = p->gumbel_tau;
+  d.kappa = p->kappa;
   d.vacc_trigger = p->vacc_trigger;
   for (int a = 0; a < ABM_N_AGE; ++a) {
     d.p_death[a] = p->p_death[a];

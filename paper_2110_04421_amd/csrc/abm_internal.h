@@ -61,7 +61,7 @@ struct Dev {
   int64_t ecap;
   uint32_t key0, key1;
   int32_t e_days, i_days, qdays, test_delay, dose_lag, vacc_on, strategy, mode;
-  float w_h, w_o, w_r, dt, test_rate, sens, dropout, eff1, eff2, gtau;
+  float w_h, w_o, w_r, dt, test_rate, sens, dropout, eff1, eff2, gtau, kappa;
   double vacc_trigger;
   float p_death[ABM_N_AGE];
   int8_t vrank[2][ABM_N_AGE];   // priority class of (dose 1|2, age group)
@@ -162,6 +162,7 @@ void launch_pre(const Dev& d, hipStream_t s);
 void launch_mask(const Dev& d, hipStream_t s);
 void launch_vplan(const Dev& d, hipStream_t s);
 void launch_count(const Dev& d, hipStream_t s);
+void launch_clear_recv(const Dev& d, hipStream_t s);
 void launch_scan(const Dev& d, hipStream_t s);
 void launch_fill(const Dev& d, hipStream_t s);
 void launch_canon(const Dev& d, hipStream_t s);

@@ -306,6 +306,15 @@ __global__ __launch_bounds__(TILE) void k_canon(Dev d) {
   for (int e = b; e < b + rr; ++e) d.w[e] = d.w_r;
 }
 
+// In-degree counters start from zero each day (the hard step clears them in k_pre).
+__global__ __launch_bounds__(TILE) void k_clear_recv(Dev d) {
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (i < d.N) d.recv[i] = 0u;
+}
+
+void launch_clear_recv(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_recv, dim3((d.N + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+}
 void launch_count(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }

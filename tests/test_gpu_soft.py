@@ -1,0 +1,108 @@
+"""Relaxed (soft) mode on the GPU against the FP64 soft oracle: daily relaxed
+incidence, the hand-written adjoint against the oracle's forward-mode gradient and
+against GPU central differences, checkpoint-interval invariance, batched replicates."""
+import numpy as np
+import pytest
+
+from helpers import require_gpu
+from oracle.soft import SoftModel, gradient
+from synthpop import workload, replicate_population
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(p, pop, **kw):
+    require_gpu()
+    from paper_2110_04421_amd.sim import Simulator
+    return Simulator(p, pop, **kw)
+
+
+def _close(g, ref, rel):
+    scale = np.maximum(np.abs(ref), rel * np.abs(ref).max())
+    return np.all(np.abs(g - ref) <= rel * scale + 1e-12), float((np.abs(g - ref) / scale).max())
+
+
+def test_soft_forward_and_adjoint_match_oracle():
+    T = 40
+    p, pop = workload(4, n=20000, n_steps=T)
+    c_o, cd_o, _ = SoftModel(pop, p).run(T)
+    dL = np.random.default_rng(7).normal(size=(1, T))
+    g_o = gradient(cd_o, dL)
+    with _sim(p, pop) as s:
+        c_g = s.run(T)
+        ok, err = _close(c_g.astype(np.float64), c_o, 1e-4)
+        assert ok, f"relaxed incidence rel err {err}"
+        g_g = s.grad(dL.astype(np.float32))
+    ok, err = _close(g_g.astype(np.float64), g_o, 1e-3)
+    assert ok, f"adjoint rel err {err}: {g_g} vs {g_o}"
+
+
+def test_adjoint_matches_gpu_central_differences():
+    T = 30
+    p, pop = workload(4, n=10000, n_steps=T)
+    dL = np.random.default_rng(8).normal(size=(1, T)).astype(np.float32)
+    with _sim(p, pop) as s:
+        s.run(T)
+        g = s.grad(dL)[0]
+    h = 1e-3
+    th0 = np.concatenate([pop.R, pop.susceptibility[0]]).astype(np.float64)
+    for k in (0, 2, 6):
+        vals = []
+        for sgn in (1, -1):
+            th = th0.copy()
+            th[k] += sgn * h
+            q = replicate_population(pop, 1, R=th[0], susceptibility=th[1:])
+            with _sim(p, q) as s:
+                vals.append(float((dL.astype(np.float64) * s.run(T)).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(g[k] - fd) <= 1e-2 * max(abs(fd), 0.05 * np.abs(g).max()), (k, g[k], fd)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    T = 25
+    dL = np.random.default_rng(9).normal(size=(1, T)).astype(np.float32)
+    outs = []
+    for every in (1, 10, 25):
+        p, pop = workload(4, n=6000, n_steps=T, checkpoint_every=every)
+        with _sim(p, pop) as s:
+            c = s.run(T)
+            outs.append((c, s.grad(dL)))
+    for c, g in outs[1:]:
+        assert np.array_equal(c, outs[0][0]) and np.array_equal(g, outs[0][1])
+
+
+def test_batched_soft_replicates_match_oracle():
+    T = 20
+    p, pop1 = workload(4, n=5000, n_steps=T)
+    R = np.array([4.0, 5.18, 6.5], np.float32)
+    S = np.stack([np.linspace(0.35, 1.47, 9), np.full(9, 0.8), np.linspace(1.4, 0.4, 9)]).astype(np.float32)
+    pop = replicate_population(pop1, 3, R=R, susceptibility=S)
+    c_o, cd_o, _ = SoftModel(pop, p).run(T)
+    dL = np.random.default_rng(10).normal(size=(3, T))
+    g_o = gradient(cd_o, dL)
+    with _sim(p, pop) as s:
+        c_g = s.run(T)
+        g_g = s.grad(dL.astype(np.float32))
+    assert _close(c_g.astype(np.float64), c_o, 1e-4)[0]
+    for r in range(3):
+        ok, err = _close(g_g[r].astype(np.float64), g_o[r], 1e-3)
+        assert ok, (r, err)
+
+
+def test_zero_temperature_soft_equals_hard_incidence():
+    T = 30
+    p, pop = workload(4, n=8000, n_steps=T, gumbel_tau=1e-6)
+    with _sim(p, pop) as s:
+        c = s.run(T)
+    with _sim(dict(p, mode=0), pop) as s:
+        hard = s.run(T)[:, 0, 5]
+    assert np.array_equal(np.rint(c[0]).astype(np.int64), hard)
+
+
+def test_grad_before_run_is_an_error():
+    from paper_2110_04421_amd._lib import AbmError
+    p, pop = workload(4, n=2000, n_steps=10)
+    with _sim(p, pop) as s:
+        with pytest.raises(AbmError) as e:
+            s.grad(np.zeros((1, 10), np.float32))
+        assert e.value.code == -6
