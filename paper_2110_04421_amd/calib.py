@@ -1,0 +1,213 @@
+"""Learned calibration of (R, S_0..S_8) from a daily incidence curve, against grid search.
+
+The paper leaves calibration from aggregate data as the direction beyond grid search
+(section 1; section 6).  Here the plain simulator generates its own training data
+(batched runs with parameters drawn uniformly over R in [3, 7], S_a in [0.35, 1.47]);
+the BF16 matrix-core network learns the inverse map; a prediction is judged by
+re-simulating the plain simulator at the predicted parameters (independent Philox
+stream) and measuring the relative L2 distance to the target curve.  Grid search over
+R (S at its reference profile) is the fallback and the baseline.
+
+    python -m paper_2110_04421_amd.calib --train 50000 --heldout 1000 --agents 100000
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import _lib as L
+
+R_LO, R_HI, S_LO, S_HI = 3.0, 7.0, 0.35, 1.47
+NTHETA = 10
+
+
+def to_unit(theta):
+    t = np.asarray(theta, np.float64)
+    out = np.empty_like(t)
+    out[:, 0] = (t[:, 0] - R_LO) / (R_HI - R_LO)
+    out[:, 1:] = (t[:, 1:] - S_LO) / (S_HI - S_LO)
+    return out
+
+
+def from_unit(u):
+    u = np.clip(np.asarray(u, np.float64), 0.0, 1.0)
+    out = np.empty_like(u)
+    out[:, 0] = R_LO + u[:, 0] * (R_HI - R_LO)
+    out[:, 1:] = S_LO + u[:, 1:] * (S_HI - S_LO)
+    return out
+
+
+def sample_theta(n, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(R_LO, R_HI, (n, 1)), rng.uniform(S_LO, S_HI, (n, 9))], 1)
+
+
+def simulate_curves(params, base_pop, theta, seed, stream0=0, days=180, batch=256, log=None):
+    """Daily incidence [n, days] of plain runs of ``base_pop`` at each parameter row,
+    ``batch`` runs per launch (replicate r uses Philox stream stream0 + r)."""
+    from synthpop import replicate_population
+    from .sim import Simulator
+    theta = np.asarray(theta, np.float64)
+    n = theta.shape[0]
+    out = np.zeros((n, days), np.int64)
+    p = dict(params, seed=int(seed), n_steps=days, mode=L.HARD)
+    for b0 in range(0, n, batch):
+        b1 = min(n, b0 + batch)
+        pop = replicate_population(base_pop, b1 - b0, R=theta[b0:b1, 0].astype(np.float32),
+                                   susceptibility=theta[b0:b1, 1:].astype(np.float32))
+        pop.stream = (stream0 + np.arange(b0, b1)).astype(np.uint32)
+        with Simulator(p, pop) as s:
+            out[b0:b1] = s.run(days)[:, :, L.C_NEW].T
+        if log:
+            log(f"simulated {b1}/{n} runs")
+    return out
+
+
+class Features:
+    """log1p of the daily incidence, standardised per day, padded to 192 inputs."""
+
+    def fit(self, curves):
+        z = np.log1p(np.asarray(curves, np.float64))
+        self.mu = z.mean(0)
+        self.sd = z.std(0) + 1e-3
+        return self
+
+    def __call__(self, curves):
+        z = (np.log1p(np.asarray(curves, np.float64)) - self.mu) / self.sd
+        x = np.zeros((z.shape[0], L.MLP_IN), np.float32)
+        x[:, :z.shape[1]] = z
+        return x
+
+
+class Calibrator:
+    def __init__(self, seed=0, max_batch=1024):
+        from .mlp import MLP
+        self.net = MLP(max_batch, seed=seed)
+        self.feat = None
+
+    def train(self, curves, theta, epochs=30, batch=256, lr=1e-3, seed=0, log=None):
+        import torch
+        self.feat = Features().fit(curves)
+        x = torch.from_numpy(self.feat(curves)).cuda()
+        y = np.zeros((theta.shape[0], L.MLP_OUT), np.float32)
+        y[:, :NTHETA] = to_unit(theta)
+        y = torch.from_numpy(y).cuda()
+        rng = np.random.default_rng(seed)
+        n = x.shape[0]
+        hist = []
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(n)).cuda()
+            tot = 0.0
+            for b0 in range(0, n - batch + 1, batch):
+                idx = perm[b0:b0 + batch]
+                loss = self.net.train_step(x[idx].contiguous(), y[idx].contiguous(), NTHETA, lr=lr)
+                tot += float(loss.cpu())
+            hist.append(tot / max(1, n // batch))
+            if log:
+                log(f"epoch {ep}: loss {hist[-1]:.4f}")
+        return hist
+
+    def predict(self, curves):
+        import torch
+        x = torch.from_numpy(self.feat(curves)).cuda()
+        out = []
+        for b0 in range(0, x.shape[0], self.net.max_batch):
+            out.append(self.net.forward(x[b0:b0 + self.net.max_batch].contiguous()).cpu().numpy())
+        return from_unit(np.concatenate(out)[:, :NTHETA])
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1.0)
+
+
+def grid_thetas(n_r=41):
+    S0 = np.linspace(S_LO, S_HI, 9)
+    return np.concatenate([np.linspace(R_LO, R_HI, n_r)[:, None], np.tile(S0, (n_r, 1))], 1)
+
+
+def grid_fit(grid_curves, grid_theta, targets):
+    """Grid point whose curve is nearest (L2 of log1p) to each target."""
+    g = np.log1p(grid_curves.astype(np.float64))
+    t = np.log1p(np.asarray(targets, np.float64))
+    d = ((t[:, None, :] - g[None, :, :]) ** 2).sum(-1)
+    return grid_theta[np.argmin(d, 1)]
+
+
+def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, batch=256,
+        log=None, tol=None):
+    """The whole calibration study; returns a summary dict."""
+    from synthpop import workload
+    p, pop = workload(4, n=n_agents, mode=L.HARD, n_steps=days)
+    t0 = time.perf_counter()
+    th_tr = sample_theta(n_train, 11)
+    c_tr = simulate_curves(p, pop, th_tr, seed=1, days=days, batch=batch, log=log)
+    t_data = time.perf_counter() - t0
+    th_ho = sample_theta(n_heldout, 22)
+    c_ho = simulate_curves(p, pop, th_ho, seed=2, days=days, batch=batch, log=log)
+    t0 = time.perf_counter()
+    cal = Calibrator()
+    hist = cal.train(c_tr, th_tr, epochs=epochs, log=log)
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    th_mlp = cal.predict(c_ho)
+    t_pred = time.perf_counter() - t0
+    gt = grid_thetas()
+    t0 = time.perf_counter()
+    c_grid = simulate_curves(p, pop, gt, seed=4, days=days, batch=batch)
+    th_grid = grid_fit(c_grid, gt, c_ho)
+    t_grid = time.perf_counter() - t0
+    # re-simulation on an independent stream (seed 3), same stream word per held-out curve
+    e_mlp = rel_l2(simulate_curves(p, pop, th_mlp, seed=3, days=days, batch=batch), c_ho)
+    e_grid = rel_l2(simulate_curves(p, pop, th_grid, seed=3, days=days, batch=batch), c_ho)
+    e_true = rel_l2(simulate_curves(p, pop, th_ho, seed=3, days=days, batch=batch), c_ho)
+    mean_th = np.tile(th_tr.mean(0), (n_heldout, 1))
+    e_mean = rel_l2(simulate_curves(p, pop, mean_th, seed=3, days=days, batch=batch), c_ho)
+    summary = dict(
+        agents=n_agents, days=days, train_runs=n_train, heldout=n_heldout, epochs=epochs,
+        train_loss_first=hist[0], train_loss_last=hist[-1],
+        resim_rel_l2=dict(mlp=float(e_mlp.mean()), grid=float(e_grid.mean()),
+                          true_params=float(e_true.mean()), training_mean_params=float(e_mean.mean())),
+        resim_rel_l2_median=dict(mlp=float(np.median(e_mlp)), grid=float(np.median(e_grid)),
+                                 true_params=float(np.median(e_true))),
+        param_rmse_unit=dict(mlp=float(np.sqrt(((to_unit(th_mlp) - to_unit(th_ho)) ** 2).mean(0)).mean()),
+                             grid=float(np.sqrt(((to_unit(th_grid) - to_unit(th_ho)) ** 2).mean(0)).mean())),
+        R_rmse=dict(mlp=float(np.sqrt(((th_mlp[:, 0] - th_ho[:, 0]) ** 2).mean())),
+                    grid=float(np.sqrt(((th_grid[:, 0] - th_ho[:, 0]) ** 2).mean()))),
+        seconds=dict(training_data=t_data, training=t_train, mlp_predict=t_pred,
+                     grid_search=t_grid))
+    if tol is not None:
+        # fallback: grid search where the network's re-simulation misses by more than tol
+        fb = e_mlp > tol
+        e_comb = np.where(fb, e_grid, e_mlp)
+        summary["with_fallback"] = dict(tol=tol, fallback_share=float(fb.mean()),
+                                        resim_rel_l2=float(e_comb.mean()))
+    return summary
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=50000)
+    ap.add_argument("--heldout", type=int, default=1000)
+    ap.add_argument("--agents", type=int, default=100_000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--days", type=int, default=180)
+    ap.add_argument("--tol", type=float, default=0.5)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    log = lambda m: print(f"[calib {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
+    s = run(a.train, a.heldout, a.agents, a.epochs, a.days, log=log, tol=a.tol)
+    txt = json.dumps(s, indent=1)
+    print(txt)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt + "\n")
+
+
+if __name__ == "__main__":
+    main()
