@@ -83,6 +83,8 @@ enum {
 /* params.flags */
 #define ABM_FLAG_PROFILE 1  /* time every kernel with HIP events (eager launches) */
 #define ABM_FLAG_NO_GRAPH 2 /* launch day kernels eagerly instead of a HIP graph  */
+#define ABM_FLAG_CLAIM_BUILDER 4 /* build the daily graph with per-edge atomic slot claims
+                                    (the default partitions contacts by destination)     */
 
 /* Model parameters; copied at create.  Section 3 eq. 1: lambda = R * S_a * A_s * B_n /
  * Ibar * integral of the Gamma infectiousness density over the day. */
@@ -205,10 +207,11 @@ void abm_destroy(abm_sim* s);
 const char* abm_error_string(int code);
 const char* abm_last_error(const abm_sim* s);
 
-/* Per-kernel timing (params.flags & ABM_FLAG_PROFILE): number of timed kernels, their
- * names, accumulated milliseconds and launch counts since create or reset. */
-int abm_profile_kernels(void);
-const char* abm_profile_name(int32_t k);
+/* Per-kernel timing (params.flags & ABM_FLAG_PROFILE): number of timed steps of the day
+ * (one or a few kernels each), their names, accumulated milliseconds and launch counts
+ * since create or reset. */
+int abm_profile_kernels(const abm_sim* s);
+const char* abm_profile_name(const abm_sim* s, int32_t k);
 int abm_profile_get(abm_sim* s, double* h_ms, int64_t* h_launches);
 int abm_profile_reset(abm_sim* s);
 

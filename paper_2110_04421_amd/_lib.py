@@ -14,7 +14,7 @@ HARD, SOFT = 0, 1
 NC = 12
 N_AGE, N_OCC, N_THETA = 9, 23, 10
 NEVER = -32768
-FLAG_PROFILE, FLAG_NO_GRAPH = 1, 2
+FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER = 1, 2, 4
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR) = range(NC)
 (GET_STATE, GET_LAMBDA, GET_CODE, GET_ROWPTR, GET_COL, GET_W, GET_ATAB, GET_POISSON, GET_DAY,
  GET_LATCH, GET_SOFT_S, GET_COEF) = range(12)
@@ -86,8 +86,8 @@ def lib():
         "abm_destroy": (None, [vp]),
         "abm_error_string": (C.c_char_p, [C.c_int]),
         "abm_last_error": (C.c_char_p, [vp]),
-        "abm_profile_kernels": (C.c_int, []),
-        "abm_profile_name": (C.c_char_p, [i32]),
+        "abm_profile_kernels": (C.c_int, [vp]),
+        "abm_profile_name": (C.c_char_p, [vp, i32]),
         "abm_profile_get": (C.c_int, [vp, vp, vp]),
         "abm_profile_reset": (C.c_int, [vp]),
         "abm_philox": (C.c_int, [u64, vp, i64, vp, vp]),

@@ -85,6 +85,8 @@ struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, counts_day, prev_counts,
       traj, day, flags, seeds;
+  size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
+      pb_buf2, pb_rsrc, pb_rstart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
       gtheta, gpart, dL;
 };
@@ -92,6 +94,8 @@ struct Offsets {
 struct Sizes {
   int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
   int64_t seg = 0, nckpt = 0;
+  // partitioned builder
+  int64_t pb_on = 0, lb = 0, nb1 = 0, nst = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
 };
 
 }  // namespace
@@ -111,12 +115,13 @@ struct abm_sim {
   bool soft_ready = false;
   std::vector<RepInfo> reps;
   char* ws = nullptr;
-  // profiling: one set of NK + 1 events per day enqueued since the last read-out
-  static constexpr int NK = 10;
+  // profiling: one set of nk + 1 events per day enqueued since the last read-out
+  int nk = 0;
+  std::vector<std::string> names;
   std::vector<std::vector<hipEvent_t>> prof_sets;
   size_t prof_used = 0;
-  double ms[NK] = {};
-  int64_t launches[NK] = {};
+  std::vector<double> ms;
+  std::vector<int64_t> launches;
 
   int fail(int code, const char* fmt, ...) {
     if (err == ABM_OK) {
@@ -132,8 +137,6 @@ struct abm_sim {
   }
 };
 
-static const char* kKernelNames[abm_sim::NK] = {"pre",   "mask",    "vplan", "count",   "scan",
-                                                 "fill",  "canon",   "message", "fused", "finalize"};
 
 #define HIPCHK(s, x)                                                              \
   do {                                                                            \
@@ -261,6 +264,22 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
     return ABM_E_CAPACITY;
   }
   z.ecap = (int64_t)ecap;
+  // partitioned builder geometry: leaves of 2^lb destinations holding a few thousand
+  // received entries, at most 1024 level-1 buckets of 256 leaves
+  z.ccap = (int64_t)std::ceil(cmean + 8.0 * std::sqrt(cmean) + 4096.0);
+  const double rbar = cmean / (double)N;
+  int lb = (int)std::floor(std::log2(6000.0 / std::max(rbar, 0.5)));
+  lb = std::min(11, std::max(6, lb));
+  auto nb1_of = [&](int b) { return (N + ((int64_t)1 << (b + 8)) - 1) >> (b + 8); };
+  while (lb < 11 && nb1_of(lb) > 1024) ++lb;
+  z.lb = lb;
+  z.nb1 = nb1_of(lb);
+  z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
+            rbar * (double)((int64_t)1 << lb) * 2.0 < 24576.0 && z.ccap < ((int64_t)1 << 31);
+  z.nst = (z.ntiles + 15) / 16;
+  z.s1_nparts = (z.nb1 * z.nst + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  z.maxch = (z.ccap + 16383) / 16384 + z.nb1;
+  z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;
   if (p->mode == ABM_SOFT) {
     z.seg = p->checkpoint_every;
     z.nckpt = (z.T + z.seg - 1) / z.seg + 1;
@@ -300,6 +319,20 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.day = L.take<int32_t>(1);
   o.flags = L.take<int32_t>(1);
   o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
+  if (z.pb_on) {
+    o.pb_hist1 = L.take<int32_t>(z.nst * z.nb1);
+    o.pb_part = L.take<int64_t>(z.s1_nparts + 1);
+    o.pb_bstart = L.take<int32_t>(z.nb1 + 1);
+    o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
+    o.pb_nchunks = L.take<int32_t>(1);
+    o.pb_chunks = L.take<int4>(z.maxch);
+    o.pb_hist2 = L.take<int32_t>(z.maxch * 256);
+    o.pb_leaf = L.take<int32_t>(z.nb1 * 256 + 1);
+    o.pb_buf1 = L.take<uint2>(z.ccap);
+    o.pb_buf2 = L.take<uint2>(z.ccap);
+    o.pb_rsrc = L.take<uint32_t>(z.ccap);
+    o.pb_rstart = L.take<int32_t>(z.N);
+  }
   if (p.mode == ABM_SOFT) {
     o.s = L.take<float>(z.N);
     o.ehist = L.take<float>(WIN * z.N);
@@ -321,6 +354,9 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   total = L.total;
 }
 
+// The day's kernel chain: interventions, graph build (named steps), force of
+// infection, fused step, bookkeeping.  With `ev`, an event is recorded before every
+// named step and after the last one.
 void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) {
   const Dev& d = s->d;
   int k = 0;
@@ -334,21 +370,26 @@ void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) 
   launch_mask(d, st);
   mark();
   if (d.vacc_on) launch_vplan(d, st);
-  mark();
-  launch_count(d, st);
-  mark();
-  launch_scan(d, st);
-  mark();
-  launch_fill(d, st);
-  mark();
-  launch_canon(d, st);
+  for (int b = 0; b < build_steps(d); ++b) {
+    mark();
+    launch_build_step(d, b, st);
+  }
   mark();
   launch_message(d, st);
   mark();
   launch_fused(d, st);
   mark();
   launch_finalize(d, st);
-  if (ev) (void)hipEventRecord((*ev)[abm_sim::NK], st);
+  if (ev) (void)hipEventRecord((*ev)[k], st);
+}
+
+void name_kernels(abm_sim* s) {
+  s->names = {"pre", "mask", "vplan"};
+  for (int b = 0; b < build_steps(s->d); ++b) s->names.push_back(build_step_name(s->d, b));
+  for (const char* n : {"message", "fused", "finalize"}) s->names.push_back(n);
+  s->nk = (int)s->names.size();
+  s->ms.assign(s->nk, 0.0);
+  s->launches.assign(s->nk, 0);
 }
 
 // Accumulate the per-kernel times of every profiled day enqueued so far.
@@ -357,7 +398,7 @@ int drain_profile(abm_sim* s) {
   HIPCHK(s, hipStreamSynchronize(s->stream));
   for (size_t q = 0; q < s->prof_used; ++q) {
     const std::vector<hipEvent_t>& ev = s->prof_sets[q];
-    for (int k = 0; k < abm_sim::NK; ++k) {
+    for (int k = 0; k < s->nk; ++k) {
       float ms = 0.f;
       HIPCHK(s, hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
       s->ms[k] += ms;
@@ -497,6 +538,29 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.dL = (const float*)(ws + o.dL);
     d.seg = (int32_t)z.seg;
   }
+  d.pb_on = (int32_t)z.pb_on;
+  if (z.pb_on) {
+    d.pb_lb = (int32_t)z.lb;
+    d.pb_nb1 = (int32_t)z.nb1;
+    d.pb_nst = (int32_t)z.nst;
+    d.pb_s1_nparts = (int32_t)z.s1_nparts;
+    d.pb_maxch = (int32_t)z.maxch;
+    d.pb_nleaf = (int32_t)z.nleaf;
+    d.pb_ccap = z.ccap;
+    d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
+    d.pb_part = (int64_t*)(ws + o.pb_part);
+    d.pb_bstart = (int32_t*)(ws + o.pb_bstart);
+    d.pb_bchunk = (int32_t*)(ws + o.pb_bchunk);
+    d.pb_nchunks = (int32_t*)(ws + o.pb_nchunks);
+    d.pb_chunks = (int4*)(ws + o.pb_chunks);
+    d.pb_hist2 = (int32_t*)(ws + o.pb_hist2);
+    d.pb_leaf = (int32_t*)(ws + o.pb_leaf);
+    d.pb_buf1 = (uint2*)(ws + o.pb_buf1);
+    d.pb_buf2 = (uint2*)(ws + o.pb_buf2);
+    d.pb_rsrc = (uint32_t*)(ws + o.pb_rsrc);
+    d.pb_rstart = (int32_t*)(ws + o.pb_rstart);
+  }
+  name_kernels(s);
 
   // host copies of the static data
   const int64_t N = z.N;
@@ -589,6 +653,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     rc = soft_create(s);
     if (rc) return rc;
   }
+  HIPCHK(s, prepare_build(d));
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipStreamSynchronize(st));
   const bool use_graph = !(p->flags & (ABM_FLAG_PROFILE | ABM_FLAG_NO_GRAPH)) && p->mode == ABM_HARD;
@@ -615,7 +680,7 @@ int abm_step(abm_sim* s, int32_t n_days) {
       HIPCHK(s, hipGraphLaunch(s->exec, s->stream));
     } else if (timed) {
       if (s->prof_used == s->prof_sets.size()) {
-        std::vector<hipEvent_t> ev(abm_sim::NK + 1);
+        std::vector<hipEvent_t> ev(s->nk + 1);
         for (auto& e : ev) HIPCHK(s, hipEventCreate(&e));
         s->prof_sets.push_back(ev);
       }
@@ -746,14 +811,16 @@ const char* abm_error_string(int code) {
 
 const char* abm_last_error(const abm_sim* s) { return s ? s->msg.c_str() : "null simulation"; }
 
-int abm_profile_kernels(void) { return abm_sim::NK; }
-const char* abm_profile_name(int32_t k) { return (k >= 0 && k < abm_sim::NK) ? kKernelNames[k] : ""; }
+int abm_profile_kernels(const abm_sim* s) { return s ? s->nk : 0; }
+const char* abm_profile_name(const abm_sim* s, int32_t k) {
+  return (s && k >= 0 && k < s->nk) ? s->names[k].c_str() : "";
+}
 int abm_profile_get(abm_sim* s, double* h_ms, int64_t* h_launches) {
   if (!s) return ABM_E_ARG;
   if (s->err) return s->err;
   const int rc = drain_profile(s);
   if (rc) return rc;
-  for (int k = 0; k < abm_sim::NK; ++k) {
+  for (int k = 0; k < s->nk; ++k) {
     if (h_ms) h_ms[k] = s->ms[k];
     if (h_launches) h_launches[k] = s->launches[k];
   }
@@ -764,7 +831,7 @@ int abm_profile_reset(abm_sim* s) {
   if (s->err) return s->err;
   const int rc = drain_profile(s);
   if (rc) return rc;
-  for (int k = 0; k < abm_sim::NK; ++k) {
+  for (int k = 0; k < s->nk; ++k) {
     s->ms[k] = 0;
     s->launches[k] = 0;
   }

@@ -101,6 +101,22 @@ struct Dev {
   int32_t* day;
   int32_t* flags;
 
+  // partitioned graph builder (k_build.hip)
+  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf;
+  int64_t pb_ccap;          // room for received entries (contacts) per day
+  int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
+  int64_t* pb_part;         // [s1_nparts + 1]
+  int32_t* pb_bstart;       // [nb1 + 1]
+  int32_t* pb_bchunk;       // [nb1 + 1] first chunk of each bucket
+  int32_t* pb_nchunks;      // [1]
+  int4* pb_chunks;          // [maxch] {bucket, begin, end, 0}
+  int32_t* pb_hist2;        // [maxch][256] histogram, then run offsets
+  int32_t* pb_leaf;         // [nb1 * 256 + 1] leaf starts
+  uint2* pb_buf1;           // [ccap] (destination, initiator | network << 31)
+  uint2* pb_buf2;           // [ccap]
+  uint32_t* pb_rsrc;        // [ccap] received initiators, sorted by (dest, network, initiator)
+  int32_t* pb_rstart;       // [N] first received entry of each destination
+
   // soft mode
   float* s;            // susceptible mass [N]
   float* ehist;        // exposure mass ring [WIN][N], slot = day mod WIN
@@ -172,6 +188,12 @@ void launch_finalize(const Dev& d, hipStream_t s);
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);
 void launch_recount(const Dev& d, hipStream_t s);
 void launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s);
+
+// partitioned builder: named steps (for per-kernel timing) and one-time setup
+int build_steps(const Dev& d);
+const char* build_step_name(const Dev& d, int k);
+void launch_build_step(const Dev& d, int k, hipStream_t s);
+hipError_t prepare_build(const Dev& d);
 
 // soft mode
 void launch_soft_init(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);

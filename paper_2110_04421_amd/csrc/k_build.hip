@@ -1,0 +1,508 @@
+// Daily contact graph, partitioned builder.  Same CSR, same canonical order as the
+// claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
+// global atomics and without random 4-byte scatters:
+//
+//   P1  gen/hist    per 16-tile super-tile: draw every agent's contacts, keep its own
+//                   counts, histogram the partners by level-1 digit (dest >> (LB + 8)).
+//   S1  scan        digit-major exclusive scan of the histograms -> each (super-tile,
+//                   digit) run's offset; level-1 bucket bounds; chunk table.
+//   P2  scatter-1   draw the contacts again, write (dest, src | net) into the runs.
+//   P3  hist-2      per chunk of a level-1 bucket: histogram by level-2 digit.
+//   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
+//   P4  scatter-2   entries into leaves of 2^LB destinations.
+//   P5  leaf sort   per leaf, in LDS: counting sort by (destination, network), then each
+//                   (destination, network) run sorted by initiator; received counts and
+//                   the received-list start of every destination.
+//   row pointers    the prefix scan of k_graph.hip (scan1-3).
+//   P6  assemble    each row: household, own occupation draws, received occupation
+//                   (copied), own random draws, received random (copied).
+// Every run written in P2/P4 is a contiguous block of a few hundred bytes, and every
+// random access of the old builder becomes an LDS access.
+#include "abm_internal.h"
+
+namespace abm {
+
+constexpr int PB_ST = 16;              // tiles per super-tile in P1/P2
+constexpr int PB_CHUNK = 16384;        // entries per level-2 chunk
+constexpr int PB_LEAF_CAP = 24576;     // entries a leaf may hold in LDS
+constexpr int PB_NB1_MAX = 1024;       // level-1 digits
+
+// Contact generation shared with k_graph.hip (same draws, same order).
+struct Gen {
+  uint32_t loc, t, stream, purpose, k0, k1, m, pos;
+  int base, wp_lo;
+  bool rnd;
+  uint4 blk;
+  uint32_t blk_id;
+  __device__ __forceinline__ int count(const uint32_t* T) {
+    if (m < 2) return 0;
+    blk = philox(loc, t, stream, purpose << 24, k0, k1);
+    blk_id = 0;
+    return poisson_k(T, blk.x);
+  }
+  __device__ __forceinline__ int partner(const Dev& d, int q) {
+    const uint32_t b = (uint32_t)q >> 2;
+    if (b != blk_id) {
+      blk = philox(loc, t, stream, (purpose << 24) | b, k0, k1);
+      blk_id = b;
+    }
+    const uint32_t x = lane4(blk, q & 3);
+    const uint32_t off = (uint32_t)(((uint64_t)x * (uint64_t)(m - 1)) >> 32);
+    uint32_t slot = pos + 1 + off;
+    if (slot >= m) slot -= m;
+    return rnd ? base + (int)slot : d.wp_members[wp_lo + (int)slot];
+  }
+};
+
+__device__ __forceinline__ Gen gen_occ(const Dev& d, const StaticRec& sr, uint32_t loc, uint32_t t,
+                                       uint32_t stream) {
+  Gen g;
+  g.loc = loc; g.t = t; g.stream = stream; g.purpose = P_OCC; g.k0 = d.key0; g.k1 = d.key1;
+  g.m = sr.wp_n; g.pos = sr.wp_pos; g.base = 0; g.wp_lo = sr.wp_lo; g.rnd = false;
+  return g;
+}
+__device__ __forceinline__ Gen gen_rand(const Dev& d, const RepInfo& ri, uint32_t loc, uint32_t t) {
+  Gen g;
+  g.loc = loc; g.t = t; g.stream = ri.stream; g.purpose = P_RAND; g.k0 = d.key0; g.k1 = d.key1;
+  g.m = (uint32_t)ri.n; g.pos = loc; g.base = ri.start; g.wp_lo = 0; g.rnd = true;
+  return g;
+}
+
+__device__ __forceinline__ void load_ptab(const Dev& d, uint32_t* T) {
+  for (int i = threadIdx.x; i < NPT * 64; i += TILE) T[i] = d.ptab[i];
+}
+
+// ---- P1: own counts and level-1 histogram per super-tile -----------------------------
+__global__ __launch_bounds__(TILE) void k_pb_hist1(Dev d) {
+  __shared__ uint32_t T[NPT * 64];
+  __shared__ int hist[PB_NB1_MAX];
+  load_ptab(d, T);
+  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) hist[k] = 0;
+  __syncthreads();
+  const uint32_t t = (uint32_t)(*d.day);
+  const int s1 = d.pb_lb + 8;
+  const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
+  for (int tix = blockIdx.x * PB_ST; tix < tile_end; ++tix) {
+    const int4 tl = d.tiles[tix];
+    const int i = tl.y + threadIdx.x;
+    if (i < tl.z) {
+      const RepInfo& ri = d.rep[tl.x];
+      const StaticRec sr = d.srec[i];
+      const uint32_t loc = (uint32_t)(i - ri.start);
+      Gen go = gen_occ(d, sr, loc, t, ri.stream);
+      const int ko = go.count(T + sr.occ * 64);
+      for (int q = 1; q <= ko; ++q) atomicAdd(&hist[go.partner(d, q) >> s1], 1);
+      Gen gr = gen_rand(d, ri, loc, t);
+      const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+      for (int q = 1; q <= kr; ++q) atomicAdd(&hist[gr.partner(d, q) >> s1], 1);
+      d.own[i] = (uint16_t)(ko | (kr << 8));
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[k];
+}
+
+// ---- generic three-phase exclusive scan over a virtual index ----------------------------
+// Level-1 order: q = digit * nst + super-tile, element hist1[super-tile][digit].
+__device__ __forceinline__ int* h1_at(const Dev& d, int64_t q) {
+  const int64_t b = q / d.pb_nst, s = q % d.pb_nst;
+  return d.pb_hist1 + s * d.pb_nb1 + b;
+}
+
+__global__ __launch_bounds__(TILE) void k_pb_s1a(Dev d) {
+  __shared__ int red[TILE / 64];
+  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nst;
+  const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    if (q0 + k < n) s += *h1_at(d, q0 + k);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) d.pb_part[blockIdx.x] = (int64_t)(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Exclusive scan of nparts block sums in place (one workgroup); total to parts[nparts].
+__global__ __launch_bounds__(1024) void k_pb_parts(int64_t* parts, int nparts) {
+  __shared__ int64_t buf[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nparts; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    const int64_t v = b < nparts ? parts[b] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (b < nparts) parts[b] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[nparts] = carry;
+}
+
+__global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
+  __shared__ int wsum[TILE / 64];
+  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nst;
+  const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = q0 + k < n ? *h1_at(d, q0 + k) : 0;
+    s += v[k];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int k = 0; k < wv; ++k) wb += wsum[k];
+  int64_t run = d.pb_part[blockIdx.x] + wb + inc - s;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (q0 + k < n) *h1_at(d, q0 + k) = (int)run;
+    run += v[k];
+  }
+}
+
+// Bucket bounds and the level-2 chunk table (one workgroup; nb1 <= 1024).
+__global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
+  __shared__ int nch[PB_NB1_MAX + 1];
+  __shared__ int ok;
+  const int64_t total = d.pb_part[d.pb_s1_nparts];
+  const int b = threadIdx.x;
+  int start = 0, size = 0;
+  if (b < d.pb_nb1) {
+    start = d.pb_hist1[b];      // q = b * nst + 0 lives at hist1[0][b]
+    const int64_t end = b + 1 < d.pb_nb1 ? (int64_t)d.pb_hist1[b + 1] : total;
+    size = (int)(end - start);
+    d.pb_bstart[b] = start;
+    nch[b] = (size + PB_CHUNK - 1) / PB_CHUNK;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int k = 0; k < d.pb_nb1; ++k) {
+      const int n = nch[k];
+      nch[k] = c;
+      c += n;
+    }
+    nch[d.pb_nb1] = c;
+    *d.pb_nchunks = c;
+    d.pb_bstart[d.pb_nb1] = (int)total;
+    ok = total <= d.pb_ccap && c <= d.pb_maxch;
+    if (!ok) atomicOr(d.flags, FLAG_CAPACITY);
+  }
+  __syncthreads();
+  if (b < d.pb_nb1 && ok) {
+    for (int k = 0; k < nch[b + 1] - nch[b]; ++k) {
+      const int c = nch[b] + k;
+      const int lo = start + k * PB_CHUNK;
+      d.pb_chunks[c] = make_int4(b, lo, min(lo + PB_CHUNK, start + size), 0);
+    }
+    d.pb_bchunk[b] = nch[b];
+  }
+  if (b == 0) d.pb_bchunk[d.pb_nb1] = nch[d.pb_nb1];
+}
+
+// ---- P2: scatter into level-1 runs ---------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_pb_scatter1(Dev d) {
+  __shared__ uint32_t T[NPT * 64];
+  __shared__ int cur[PB_NB1_MAX];
+  if (*d.flags) return;
+  load_ptab(d, T);
+  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) cur[k] = d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k];
+  __syncthreads();
+  const uint32_t t = (uint32_t)(*d.day);
+  const int s1 = d.pb_lb + 8;
+  const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
+  for (int tix = blockIdx.x * PB_ST; tix < tile_end; ++tix) {
+    const int4 tl = d.tiles[tix];
+    const int i = tl.y + threadIdx.x;
+    if (i < tl.z) {
+      const RepInfo& ri = d.rep[tl.x];
+      const StaticRec sr = d.srec[i];
+      const uint32_t loc = (uint32_t)(i - ri.start);
+      Gen go = gen_occ(d, sr, loc, t, ri.stream);
+      const int ko = go.count(T + sr.occ * 64);
+      for (int q = 1; q <= ko; ++q) {
+        const int p = go.partner(d, q);
+        const int pos = atomicAdd(&cur[p >> s1], 1);
+        d.pb_buf1[pos] = make_uint2((uint32_t)p, (uint32_t)i);
+      }
+      Gen gr = gen_rand(d, ri, loc, t);
+      const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+      for (int q = 1; q <= kr; ++q) {
+        const int p = gr.partner(d, q);
+        const int pos = atomicAdd(&cur[p >> s1], 1);
+        d.pb_buf1[pos] = make_uint2((uint32_t)p, (uint32_t)i | 0x80000000u);
+      }
+    }
+  }
+}
+
+// ---- P3: level-2 histograms per chunk -----------------------------------------------
+__global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
+  __shared__ int hist[256];
+  if (*d.flags) return;
+  const int c = blockIdx.x;
+  if (c >= *d.pb_nchunks) return;
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int4 ch = d.pb_chunks[c];
+  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE)
+    atomicAdd(&hist[(d.pb_buf1[e].x >> d.pb_lb) & 255u], 1);
+  __syncthreads();
+  d.pb_hist2[(size_t)c * 256 + threadIdx.x] = hist[threadIdx.x];
+}
+
+// ---- S2: per bucket, digit-major exclusive scan of its chunks' histograms ------------
+__global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
+  __shared__ int wsum[TILE / 64];
+  __shared__ int carry;
+  if (*d.flags) return;
+  const int b = blockIdx.x;
+  const int c0 = d.pb_bchunk[b], nc = d.pb_bchunk[b + 1] - c0;
+  const int base = d.pb_bstart[b];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int n = 256 * nc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q0 = 0; q0 < n; q0 += TILE) {
+    const int q = q0 + threadIdx.x;
+    const int dg = nc ? q / nc : 0, cc = nc ? q % nc : 0;
+    const int v = q < n ? d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] : 0;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int k = 0; k < wv; ++k) wb += wsum[k];
+    const int ex = carry + wb + inc - v;
+    if (q < n) {
+      d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] = base + ex;
+      if (cc == 0) d.pb_leaf[(size_t)b * 256 + dg] = base + ex;
+    }
+    __syncthreads();
+    if (threadIdx.x == TILE - 1) carry += wb + inc;
+    __syncthreads();
+  }
+  if (nc == 0)
+    for (int dg = threadIdx.x; dg < 256; dg += TILE) d.pb_leaf[(size_t)b * 256 + dg] = base;
+  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 * 256] = d.pb_bstart[d.pb_nb1];
+}
+
+// ---- P4: scatter into leaves ---------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_pb_scatter2(Dev d) {
+  __shared__ int cur[256];
+  if (*d.flags) return;
+  const int c = blockIdx.x;
+  if (c >= *d.pb_nchunks) return;
+  cur[threadIdx.x] = d.pb_hist2[(size_t)c * 256 + threadIdx.x];
+  __syncthreads();
+  const int4 ch = d.pb_chunks[c];
+  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE) {
+    const uint2 v = d.pb_buf1[e];
+    const int pos = atomicAdd(&cur[(v.x >> d.pb_lb) & 255u], 1);
+    d.pb_buf2[pos] = v;
+  }
+}
+
+// ---- P5: per leaf, sort by (destination, network, initiator) in LDS ------------------
+__global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
+  extern __shared__ uint32_t lds[];
+  if (*d.flags) return;
+  const int L = blockIdx.x;
+  const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
+  const int n = hi - lo;
+  if (n > PB_LEAF_CAP) {
+    if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
+    return;
+  }
+  const int nkeys = 2 << d.pb_lb;             // (destination offset, network)
+  uint32_t* sorted = lds;                     // [PB_LEAF_CAP]
+  int* cnt = (int*)(lds + PB_LEAF_CAP);       // [nkeys + 1]
+  __shared__ int wsum[TILE / 64];
+  __shared__ int carry;
+  for (int k = threadIdx.x; k <= nkeys; k += TILE) cnt[k] = 0;
+  __syncthreads();
+  const uint32_t dmask = (1u << d.pb_lb) - 1u;
+  for (int e = lo + threadIdx.x; e < hi; e += TILE) {
+    const uint2 v = d.pb_buf2[e];
+    atomicAdd(&cnt[((v.x & dmask) << 1) | (v.y >> 31)], 1);
+  }
+  __syncthreads();
+  // per-destination received counts (before the counts become offsets)
+  const int dest0 = L << d.pb_lb;
+  for (int k = threadIdx.x; k <= (int)dmask; k += TILE) {
+    const int dest = dest0 + k;
+    if (dest < d.N) {
+      const int co = cnt[2 * k], cr = cnt[2 * k + 1];
+      if (co > 0xFFFE || cr > 0xFFFE) atomicOr(d.flags, FLAG_RECV_OVERFLOW);
+      d.recv[dest] = ((uint32_t)co << 16) | (uint32_t)cr;
+    }
+  }
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < nkeys; k0 += TILE) {
+    const int k = k0 + threadIdx.x;
+    const int v = k < nkeys ? cnt[k] : 0;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    if (k < nkeys) {
+      cnt[k] = carry + wb + inc - v;
+      if ((k & 1) == 0 && dest0 + (k >> 1) < d.N) d.pb_rstart[dest0 + (k >> 1)] = lo + carry + wb + inc - v;
+    }
+    __syncthreads();
+    if (threadIdx.x == TILE - 1) carry += wb + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[nkeys] = n;
+  __syncthreads();
+  // key runs are [cnt[k], cnt[k+1]); place with a cursor copy kept in the key's slot
+  // of a second pass: use atomics on a shifted copy, then restore starts from the runs.
+  for (int e = lo + threadIdx.x; e < hi; e += TILE) {
+    const uint2 v = d.pb_buf2[e];
+    const int k = ((v.x & dmask) << 1) | (v.y >> 31);
+    const int pos = atomicAdd(&cnt[k], 1);
+    sorted[pos] = v.y & 0x7FFFFFFFu;
+  }
+  __syncthreads();
+  // after placement cnt[k] = end of run k = start of run k+1; run k is [cnt[k-1], cnt[k])
+  for (int k = threadIdx.x; k < nkeys; k += TILE) {
+    const int a = k ? cnt[k - 1] : 0, b = cnt[k];
+    for (int x = a + 1; x < b; ++x) {
+      const uint32_t v = sorted[x];
+      int y = x - 1;
+      while (y >= a && sorted[y] > v) {
+        sorted[y + 1] = sorted[y];
+        --y;
+      }
+      sorted[y + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += TILE) d.pb_rsrc[lo + k] = sorted[k];
+}
+
+// ---- P6: assemble each row --------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
+  __shared__ uint32_t T[NPT * 64];
+  load_ptab(d, T);
+  __syncthreads();
+  if (*d.flags) return;
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  if (i >= tl.z) return;
+  const RepInfo& ri = d.rep[tl.x];
+  const uint32_t t = (uint32_t)(*d.day);
+  const StaticRec sr = d.srec[i];
+  const uint32_t loc = (uint32_t)(i - ri.start);
+  const uint32_t r = d.recv[i];
+  const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
+  int pos = d.row_ptr[i];
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;
+  for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m) {
+    if (m == i) continue;
+    d.col[pos] = m;
+    d.w[pos] = wh;
+    ++pos;
+  }
+  Gen go = gen_occ(d, sr, loc, t, ri.stream);
+  const int ko = go.count(T + sr.occ * 64);
+  for (int q = 1; q <= ko; ++q) {
+    d.col[pos] = go.partner(d, q);
+    d.w[pos] = wo;
+    ++pos;
+  }
+  const int rs = d.pb_rstart[i];
+  for (int q = 0; q < ro; ++q) {
+    d.col[pos] = (int)d.pb_rsrc[rs + q];
+    d.w[pos] = wo;
+    ++pos;
+  }
+  Gen gr = gen_rand(d, ri, loc, t);
+  const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+  for (int q = 1; q <= kr; ++q) {
+    d.col[pos] = gr.partner(d, q);
+    d.w[pos] = wr;
+    ++pos;
+  }
+  for (int q = 0; q < rr; ++q) {
+    d.col[pos] = (int)d.pb_rsrc[rs + ro + q];
+    d.w[pos] = wr;
+    ++pos;
+  }
+}
+
+// Named steps of a day's graph build.  With the partitioned builder off (populations
+// too large for 1024 level-1 digits) the claim-based builder of k_graph.hip runs.
+int build_steps(const Dev& d) { return d.pb_on ? 8 : 5; }
+
+const char* build_step_name(const Dev& d, int k) {
+  static const char* pb[8] = {"pb_hist1", "pb_scan1", "pb_scatter1", "pb_hist2",
+                              "pb_scatter2", "pb_leaf", "rowptr", "pb_assemble"};
+  static const char* cl[5] = {"clear", "count", "scan", "fill", "canon"};
+  return d.pb_on ? pb[k] : cl[k];
+}
+
+static size_t leaf_lds(const Dev& d) { return (size_t)(PB_LEAF_CAP + (2u << d.pb_lb) + 1) * 4; }
+
+hipError_t prepare_build(const Dev& d) {
+  if (!d.pb_on) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)leaf_lds(d));
+}
+
+void launch_build_step(const Dev& d, int k, hipStream_t s) {
+  if (!d.pb_on) {
+    switch (k) {
+      case 0: launch_clear_recv(d, s); break;
+      case 1: launch_count(d, s); break;
+      case 2: launch_scan(d, s); break;
+      case 3: launch_fill(d, s); break;
+      default: launch_canon(d, s); break;
+    }
+    return;
+  }
+  switch (k) {
+    case 0: hipLaunchKernelGGL(k_pb_hist1, dim3(d.pb_nst), dim3(TILE), 0, s, d); break;
+    case 1:
+      hipLaunchKernelGGL(k_pb_s1a, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_part, d.pb_s1_nparts);
+      hipLaunchKernelGGL(k_pb_s1c, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_buckets, dim3(1), dim3(1024), 0, s, d);
+      break;
+    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(TILE), 0, s, d); break;
+    case 3:
+      hipLaunchKernelGGL(k_pb_hist2, dim3(d.pb_maxch), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
+      break;
+    case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(TILE), 0, s, d); break;
+    case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(TILE), leaf_lds(d), s, d); break;
+    case 6: launch_scan(d, s); break;
+    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), 0, s, d); break;
+  }
+}
+
+}  // namespace abm

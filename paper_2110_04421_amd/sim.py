@@ -24,14 +24,16 @@ class Simulator:
 
     ``params``: flat parameter dict (see synthpop.configs); ``pop``: population object with
     the arrays of abm_population.  ``profile`` times every kernel with HIP events;
-    ``graph=False`` launches the day's kernels eagerly instead of replaying a HIP graph.
+    ``graph=False`` launches the day's kernels eagerly instead of replaying a HIP graph;
+    ``claim_builder`` selects the per-edge atomic-claim graph builder.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
-                 stream=None):
+                 claim_builder: bool = False, stream=None):
         torch = _torch()
         self._lib = L.lib()
-        flags = (L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
+        flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
+                 | (L.FLAG_CLAIM_BUILDER if claim_builder else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)
@@ -151,11 +153,12 @@ class Simulator:
 
     def profile(self):
         """{kernel name: (total ms, launches)} since create/reset (profile mode)."""
-        K = self._lib.abm_profile_kernels()
+        K = self._lib.abm_profile_kernels(self._h)
         ms = np.zeros(K, np.float64)
         n = np.zeros(K, np.int64)
         self._check(self._lib.abm_profile_get(self._h, ms.ctypes.data, n.ctypes.data))
-        return {self._lib.abm_profile_name(k).decode(): (float(ms[k]), int(n[k])) for k in range(K)}
+        return {self._lib.abm_profile_name(self._h, k).decode(): (float(ms[k]), int(n[k]))
+                for k in range(K)}
 
     def profile_reset(self):
         self._check(self._lib.abm_profile_reset(self._h))

@@ -181,3 +181,28 @@ def test_resume_equals_uninterrupted():
         s.set_state(12, latch, st)
         b = s.run(18)
     assert np.array_equal(np.concatenate([a, b]), full)
+
+
+def test_claim_builder_builds_the_same_graph():
+    p, pop = workload(3, n=40000, n_rep=5, n_steps=4)
+    outs = []
+    for claim in (False, True):
+        with _sim(p, pop, claim_builder=claim) as s:
+            c = s.run(3)
+            outs.append((c, s.csr(), s.state()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_csr_bit_exact_several_level1_buckets():
+    # 600k agents: the partitioned builder splits destinations over 3 level-1 buckets
+    p, pop = workload(1, n=600_000, n_steps=2)
+    with _sim(p, pop) as s:
+        s.run(1)
+        rp, col, w = s.csr()
+    rp_o, col_o, w_o, _ = og.build_graph(pop, p, 0)
+    assert np.array_equal(rp.astype(np.int64), rp_o)
+    assert np.array_equal(col.astype(np.int64), col_o)
+    assert np.array_equal(w, w_o.astype(np.float32))
