@@ -41,24 +41,85 @@ def household_edges(pop) -> int:
     return int((s * (s - 1)).sum())
 
 
-def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool) -> float:
-    """Algorithmic HBM bytes of one launch (one day) of a kernel.  E = directed edges of
-    the day, C = contacts drawn (each gives two edges), N = agents."""
-    if name == "message":      # col + w + 1-byte code gather per edge; row_ptr, age, lambda per row
-        return 9.0 * E + 9.0 * N
-    if name == "fill":         # write col + w per edge; claim RMW per received edge; per-agent reads
-        return 8.0 * E + 8.0 * C + 24.0 * N
-    if name == "count":        # static record, own counts; RMW per received edge
-        return 18.0 * N + 8.0 * C
-    if name == "canon":        # counts, row start, received blocks read + written
-        return 11.0 * N + 8.0 * C
-    if name == "scan":         # two passes over degree parts, row_ptr + 2 cursors written
-        return 26.0 * N
-    if name == "pre":          # state read, code + cleared counter written (+ age for classes)
-        return (22.0 if vacc else 21.0) * N
-    if name == "fused":        # state read + written, lambda, age
-        return 37.0 * N
-    return 0.0
+def leaf_bits(N: int, C: float) -> int:
+    """Leaf size exponent of the partitioned builder (same rule as the library)."""
+    rbar = max(C / N, 0.5)
+    lb = min(11, max(6, int(np.floor(np.log2(6000.0 / rbar)))))
+    while lb < 11 and -(-N // (1 << (lb + 8))) > 1024:
+        lb += 1
+    return lb
+
+
+def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float = None) -> float:
+    """Algorithmic HBM bytes of one launch (one day) of a step.  E = directed edges of
+    the day, Einf = those with an infectious source, C = contacts drawn (each gives two
+    edges), N = agents."""
+    Einf = E if Einf is None else Einf
+    lb = leaf_bits(N, C)
+    nst, nb1 = -(-N // 4096), -(-N // (1 << (lb + 8)))
+    table = {
+        # force of infection: col + 1 mask bit per edge, w + code byte per infectious
+        # edge; row_ptr, age, lambda per row
+        "message": 4.125 * E + 5.0 * Einf + 9.0 * N,
+        # partitioned builder
+        "pb_hist1": 18.0 * N,                      # static record in, own counts out
+        "pb_scan1": 12.0 * nst * nb1,              # histogram read twice, offsets written
+        "pb_scatter1": 16.0 * N + 8.0 * C,         # static record in, (dest, src) out
+        "pb_hist2": 8.0 * C,
+        "pb_scatter2": 16.0 * C,
+        "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
+        "rowptr": 18.0 * N,
+        "pb_assemble": 8.0 * E + 4.0 * C + 28.0 * N,
+        # claim-based builder
+        "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 8.0 * E + 8.0 * C + 24.0 * N,
+        "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
+        # agent kernels
+        "pre": (22.0 if vacc else 21.0) * N,       # state in, code + counters out
+        "mask": 1.125 * N,
+        "fused": 37.0 * N,                         # state in/out, lambda, age
+    }
+    return table.get(name, 0.0)
+
+
+KERNEL_SOURCES = {"message": "k_step.hip", "fused": "k_step.hip", "pre": "k_step.hip",
+                  "mask": "k_step.hip", "rowptr": "k_graph.hip", "pb_assemble": "k_build.hip",
+                  "pb_hist1": "k_build.hip", "pb_scatter1": "k_build.hip",
+                  "pb_hist2": "k_build.hip", "pb_scatter2": "k_build.hip",
+                  "pb_leaf": "k_build.hip", "pb_scan1": "k_build.hip"}
+
+
+def source_sha(kernel: str):
+    import hashlib
+    f = KERNEL_SOURCES.get(kernel)
+    if not f:
+        return None
+    path = os.path.join(ROOT, "paper_2110_04421_amd", "csrc", f)
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the same counters on a copy kernel of known size), or None
+    when the summary is missing or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh).get(kernel)
+    if not t or t.get("source_sha256") != source_sha(kernel):
+        return None
+    return t["bytes_per_launch"]
+
+
+def copy_probe(nbytes: int = 1 << 30):
+    """A plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
 
 
 def time_days(sim, W: int, K: int):
@@ -172,6 +233,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the agent count (testing)")
     ap.add_argument("--no-extras", action="store_true", help="skip the 100k, batched and CPU legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (PMC counter scale)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -198,6 +261,7 @@ def main():
     E_days = counts[:, :, 10].sum(axis=1).astype(np.float64)
     E_tot = float(E_days.sum())
     E_mean = float(E_days.mean())
+    Einf_mean = float(counts[:, :, 12].sum(axis=1).astype(np.float64).mean())
     C_mean = (E_mean - ehh) / 2.0
     vacc = p["vacc_rate"] > 0
     kernels = {}
@@ -205,14 +269,14 @@ def main():
         if n == 0:
             continue
         avg = ms / n
-        b = kernel_bytes(name, N, E_mean, C_mean, vacc)
+        b = kernel_bytes(name, N, E_mean, C_mean, vacc, Einf_mean)
         kernels[name] = {"ms_per_launch": avg, "launches": n,
                          "algorithmic_GB": b / 1e9,
                          "GB_per_s": (b / 1e9) / (avg / 1e3) if b and avg > 0 else None}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
     dk = kernels[dom]
     achieved = dk["GB_per_s"] or 0.0
-    step_bytes = sum(kernel_bytes(nm, N, E_mean, C_mean, vacc) for nm in kernels)
+    step_bytes = sum(kernel_bytes(nm, N, E_mean, C_mean, vacc, Einf_mean) for nm in kernels)
     step_ms = sum(v["ms_per_launch"] for v in kernels.values())
     line = {
         "metric": METRIC,
@@ -224,14 +288,18 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "agents": N, "days_timed": args.steps,
                    "edges_per_day": E_mean, "contacts_per_agent_day": E_mean / N,
+                   "infectious_source_edges_per_day": Einf_mean,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom),
                      "algorithmic_bytes_per_launch": dk["algorithmic_GB"] * 1e9,
                      "step_kernels_GB_per_s": (step_bytes / 1e9) / (step_ms / 1e3),
                      "step_kernels_frac": (step_bytes / 1e9) / (step_ms / 1e3) / HBM_PEAK_GBS},
         "kernels": kernels,
     }
+    if args.copy_probe:
+        copy_probe()
     if not args.no_extras:
         log("100k-agent runs")
         line["c1"] = c1_run()

@@ -72,6 +72,7 @@ enum {
   ABM_C_DOSE1, ABM_C_DOSE2,
   ABM_C_EDGES,      /* directed edges of the day's contact graph (interactions)    */
   ABM_C_NEAR,       /* susceptible draws with |u - p| <= 1e-6 (rounding-sensitive)  */
+  ABM_C_INF_EDGES,  /* edges of the day's graph whose source was infectious        */
   ABM_NC
 };
 

@@ -31,8 +31,9 @@ from .graph import build_graph, static_maps
 from .tables import STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M, infectiousness_table
 
 NEVER = -32768
-NC = 12
-C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR = range(NC)
+NC = 13
+(C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
+ C_INF_EDGES) = range(NC)
 NEAR_EPS = 1e-6
 
 
@@ -223,6 +224,9 @@ class Model:
         lam, sigma = self.force_of_infection(code, graph)
         counts[:, C_EDGES] = np.bincount(self.rep, weights=np.diff(graph[0]),
                                          minlength=self.nrep).astype(np.int64)
+        rows = np.repeat(np.arange(self.N), np.diff(graph[0]))
+        counts[:, C_INF_EDGES] = np.bincount(self.rep[rows[code[graph[1]] != 0]],
+                                             minlength=self.nrep)
         # 5. infection and progression
         u0, u1, u2, u3 = self.uniforms(t, philox.PURPOSE_AGENT)
         prob = -np.expm1(-lam * f32(p["dt"]))

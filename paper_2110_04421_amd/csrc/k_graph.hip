@@ -209,9 +209,11 @@ __global__ __launch_bounds__(TILE) void k_scan3(Dev d) {
       const int rp = (int)run;
       const uint32_t o = d.own[i], r = d.recv[i];
       d.row_ptr[i] = rp;
-      const int co = rp + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
-      d.cur_occ[i] = co;
-      d.cur_rand[i] = co + (int)(r >> 16) + (int)(o >> 8);
+      if (!d.pb_on) {            // claim cursors of the claim-based builder
+        const int co = rp + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
+        d.cur_occ[i] = co;
+        d.cur_rand[i] = co + (int)(r >> 16) + (int)(o >> 8);
+      }
       run += deg[k];
     }
   }

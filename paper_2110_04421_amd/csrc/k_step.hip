@@ -187,11 +187,13 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 
 // ---- force of infection: lambda_j = coef[a_j] * sum_{e in row j} w_e * Atab[code[src_e]]
 // A tile of 256 rows streams its contiguous edge range through LDS in chunks: the
-// edge loads and the 1-byte code gathers are spread over all lanes, then each lane
-// sums its own row left to right (FP32, canonical order) from LDS.
+// column loads and the 1-bit infectious-mask tests are spread over all lanes; the
+// weight and the code byte are read only for infectious sources (the others add +0).
+// Each lane then sums its own row left to right (FP32, canonical order) from LDS.
 __global__ __launch_bounds__(TILE) void k_message(Dev d) {
   __shared__ float atab[ATAB];
   __shared__ float term[MSG_CHUNK];
+  __shared__ uint32_t ninf[TILE / 64];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
   const int4 tl = d.tiles[blockIdx.x];
@@ -200,16 +202,21 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
   const int e0 = d.row_ptr[tl.y], e1 = d.row_ptr[tl.z];
   const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
   float sum = 0.f;
+  uint32_t infected_edges = 0;
   __syncthreads();
   for (int c0 = e0; c0 < e1; c0 += MSG_CHUNK) {
     const int cn = min(MSG_CHUNK, e1 - c0);
     for (int k = threadIdx.x; k < cn; k += TILE) {
       const int e = c0 + k;
       uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
-      const float we = __builtin_nontemporal_load(d.w + e);
       src = src < (uint32_t)d.N ? src : 0u;
       const bool inf = (d.imask[src >> 5] >> (src & 31u)) & 1u;
-      term[k] = inf ? we * atab[d.code[src]] : 0.f;
+      float v = 0.f;
+      if (inf) {
+        v = __builtin_nontemporal_load(d.w + e) * atab[d.code[src]];
+        ++infected_edges;
+      }
+      term[k] = v;
     }
     __syncthreads();
     const int lo = max(rs, c0), hi = min(re, c0 + cn);
@@ -217,6 +224,13 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
     __syncthreads();
   }
   if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
+  for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
+  if ((threadIdx.x & 63) == 0) ninf[threadIdx.x >> 6] = infected_edges;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t s = ninf[0] + ninf[1] + ninf[2] + ninf[3];
+    if (s) atomicAdd(&d.counts_day[(size_t)tl.x * ABM_NC + ABM_C_INF_EDGES], (unsigned long long)s);
+  }
 }
 
 // ---- fused day step ---------------------------------------------------------------
