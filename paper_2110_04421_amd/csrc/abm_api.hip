@@ -83,7 +83,7 @@ struct Layout {
 
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, lambda, own, recv, row_ptr,
-      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, counts_day, prev_counts,
+      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, prev_counts,
       traj, day, flags, seeds;
   size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
       pb_buf2, pb_rsrc, pb_rstart;
@@ -313,7 +313,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.vplan = L.take<int32_t>(2 * z.R);
   o.vtile = L.take<int32_t>(z.ntiles);
   o.latch = L.take<uint8_t>(z.R);
-  o.counts_day = L.take<unsigned long long>(z.R * ABM_NC);
+  o.tile_counts = L.take<uint32_t>(z.ntiles * TILE_NC);
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
   o.day = L.take<int32_t>(1);
@@ -514,7 +514,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.vplan = (int32_t*)(ws + o.vplan);
   d.vtile_base = (int32_t*)(ws + o.vtile);
   d.latch = (uint8_t*)(ws + o.latch);
-  d.counts_day = (unsigned long long*)(ws + o.counts_day);
+  d.tile_counts = (uint32_t*)(ws + o.tile_counts);
   d.prev_counts = (long long*)(ws + o.prev_counts);
   d.traj = (long long*)(ws + o.traj);
   d.day = (int32_t*)(ws + o.day);

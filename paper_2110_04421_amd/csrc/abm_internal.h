@@ -16,6 +16,8 @@ constexpr int NBUCKET = 18;        // vaccination priority classes (dose x age g
 constexpr int SCAN_ITEMS = 8;      // degrees per thread in the row-pointer scan
 constexpr int SCAN_BLOCK = TILE * SCAN_ITEMS;
 constexpr int MSG_CHUNK = 4096;    // edges staged in LDS per step of the message kernel
+constexpr int TILE_NC = 16;       // per-tile count row (ABM_NC slots, padded)
+static_assert(ABM_NC <= TILE_NC, "count slots fit a tile row");
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
 enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };
@@ -95,7 +97,7 @@ struct Dev {
   int32_t* vtile_base;          // [ntiles]
   uint8_t* latch;               // [R]
 
-  unsigned long long* counts_day;   // [R][ABM_NC]
+  uint32_t* tile_counts;            // [ntiles][TILE_NC] each day's per-tile counts
   long long* prev_counts;           // [R][ABM_NC]
   long long* traj;                  // [T][R][ABM_NC]
   int32_t* day;

@@ -29,6 +29,26 @@ __device__ __forceinline__ void block_count_add(const bool (&v)[NV], const int (
   }
 }
 
+// Sum per-thread boolean counters over the workgroup and store them in this tile's row
+// of the per-tile count table (one writer per slot per day: no atomics).
+template <int NV>
+__device__ __forceinline__ void block_count_store(const bool (&v)[NV], const int (&slot)[NV],
+                                                  uint32_t* row) {
+  __shared__ uint32_t part[TILE / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const uint32_t c = wave_count(v[k]);
+    if (lane == 0) part[wv][k] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    uint32_t s = 0;
+    for (int q = 0; q < TILE / 64; ++q) s += part[q][threadIdx.x];
+    row[slot[threadIdx.x]] = s;
+  }
+}
+
 __device__ __forceinline__ int vacc_bucket(const Dev& d, const AgentState& a, int t, int age,
                                            int delay) {
   if (a.stage == ABM_STAGE_M) return NBUCKET;
@@ -73,7 +93,7 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   }
   const bool v[1] = {pos_due};
   const int sl[1] = {ABM_C_POS};
-  block_count_add<1>(v, sl, d.counts_day + (size_t)tl.x * ABM_NC);
+  block_count_store<1>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
   if (d.vacc_on) {
     __syncthreads();
     if (threadIdx.x < NBUCKET) d.vhist[(size_t)blockIdx.x * NBUCKET + threadIdx.x] = hist[threadIdx.x];
@@ -227,10 +247,8 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
   for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
   if ((threadIdx.x & 63) == 0) ninf[threadIdx.x >> 6] = infected_edges;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t s = ninf[0] + ninf[1] + ninf[2] + ninf[3];
-    if (s) atomicAdd(&d.counts_day[(size_t)tl.x * ABM_NC + ABM_C_INF_EDGES], (unsigned long long)s);
-  }
+  if (threadIdx.x == 0)
+    d.tile_counts[(size_t)blockIdx.x * TILE_NC + ABM_C_INF_EDGES] = ninf[0] + ninf[1] + ninf[2] + ninf[3];
 }
 
 // ---- fused day step ---------------------------------------------------------------
@@ -323,25 +341,45 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
   const bool v[10] = {st == 0, st == 1, st == 2, st == 3, st == 4, is_new, tested, dose1, dose2, near};
   const int sl[10] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_NEW, ABM_C_TESTS,
                       ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR};
-  block_count_add<10>(v, sl, d.counts_day + (size_t)tl.x * ABM_NC);
+  block_count_store<10>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
 }
 
-// ---- end of day: counts -> trajectory, edges per replicate, advance the day ---------
-__global__ __launch_bounds__(TILE) void k_finalize(Dev d) {
+// ---- end of day: tile counts -> per-replicate counts -> trajectory ----------------
+// One workgroup per replicate sums its tiles' rows in a fixed order.
+__global__ __launch_bounds__(1024) void k_finalize(Dev d) {
+  __shared__ unsigned long long part[1024 / 64][ABM_NC];
+  const int r = blockIdx.x;
+  const RepInfo& ri = d.rep[r];
   const int t = *d.day;
   const bool ok = *d.flags == 0;
-  for (int k = threadIdx.x; k < d.R * ABM_NC; k += TILE) {
-    const int r = k / ABM_NC, c = k % ABM_NC;
-    long long v = (long long)d.counts_day[k];
-    if (c == ABM_C_EDGES)
-      v = ok ? (long long)d.row_ptr[d.rep[r].start + d.rep[r].n] - d.row_ptr[d.rep[r].start] : 0;
-    if (t < d.T) d.traj[(size_t)t * d.R * ABM_NC + k] = v;
-    d.prev_counts[k] = v;
-    d.counts_day[k] = 0ull;
+  unsigned long long acc[ABM_NC];
+#pragma unroll
+  for (int c = 0; c < ABM_NC; ++c) acc[c] = 0ull;
+  for (int k = threadIdx.x; k < ri.ntiles; k += 1024) {
+    const uint32_t* row = d.tile_counts + (size_t)(ri.tile0 + k) * TILE_NC;
+#pragma unroll
+    for (int c = 0; c < ABM_NC; ++c) acc[c] += row[c];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < ABM_NC; ++c) {
+    unsigned long long v = acc[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) part[wv][c] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *d.day = t + 1;
+  if (threadIdx.x < ABM_NC) {
+    const int c = threadIdx.x;
+    long long v = 0;
+    for (int q = 0; q < 1024 / 64; ++q) v += (long long)part[q][c];
+    if (c == ABM_C_EDGES) v = ok ? (long long)d.row_ptr[ri.start + ri.n] - d.row_ptr[ri.start] : 0;
+    if (c == ABM_C_INF_EDGES && !ok) v = 0;
+    if (t < d.T) d.traj[((size_t)t * d.R + r) * ABM_NC + c] = v;
+    d.prev_counts[(size_t)r * ABM_NC + c] = v;
+  }
 }
+
+__global__ void k_advance_day(Dev d) { *d.day = *d.day + 1; }
 
 // ---- initial state: everyone susceptible, seeds exposed on day -1 --------------------
 __global__ __launch_bounds__(TILE) void k_init_state(Dev d) {
@@ -372,10 +410,7 @@ __global__ void k_seed(Dev d, const int32_t* seeds, int64_t n) {
 }
 
 __global__ void k_zero_counts(Dev d) {
-  for (int k = threadIdx.x; k < d.R * ABM_NC; k += blockDim.x) {
-    d.counts_day[k] = 0ull;
-    d.prev_counts[k] = 0;
-  }
+  for (int k = threadIdx.x; k < d.R * ABM_NC; k += blockDim.x) d.prev_counts[k] = 0;
 }
 
 // Stage counts of the current state into prev_counts (for the prevalence latch).
@@ -418,7 +453,8 @@ void launch_fused(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
 void launch_finalize(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TILE), 0, s, d);
+  hipLaunchKernelGGL(k_finalize, dim3(d.R), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_advance_day, dim3(1), dim3(1), 0, s, d);
 }
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3((d.N + TILE - 1) / TILE), dim3(TILE), 0, s, d);
