@@ -56,7 +56,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
     edges), N = agents."""
     Einf = E if Einf is None else Einf
     lb = leaf_bits(N, C)
-    nst, nb1 = -(-N // 4096), -(-N // (1 << (lb + 8)))
+    nst, nb1 = -(-N // 16384), -(-N // (1 << (lb + 8)))
     table = {
         # force of infection: col + 1 mask bit per edge, w + code byte per infectious
         # edge; row_ptr, age, lambda per row
@@ -215,6 +215,37 @@ def batched_vs_plain(n_rep: int = 256):
             "speedup": ts / tb, "per_replicate_bit_equal": equal}
 
 
+def adjoint_cost(days: int = 180):
+    """Relaxed forward + hand-written adjoint vs the relaxed and the plain forward, at
+    100,000 agents (checkpoints every 10 days)."""
+    import torch
+    from paper_2110_04421_amd.sim import Simulator
+    from synthpop import workload
+    p, pop = workload(4, n_steps=days)
+    dL = np.ones((1, days), np.float32)
+    with Simulator(p, pop) as s:
+        s.run(days)                                  # warm-up
+    with Simulator(p, pop) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(days)
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g = s.grad(dL)
+        t_bwd = time.perf_counter() - t0
+    with Simulator(dict(p, mode=0), pop) as s:
+        s.run(days)
+    with Simulator(dict(p, mode=0), pop) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run(days)
+        t_hard = time.perf_counter() - t0
+    return {"workload": "calib-100k", "days": days, "soft_forward_s": t_fwd, "adjoint_s": t_bwd,
+            "plain_forward_s": t_hard, "cost_vs_soft_forward": (t_fwd + t_bwd) / t_fwd,
+            "cost_vs_plain_forward": (t_fwd + t_bwd) / t_hard,
+            "dL_dR_of_total_incidence": float(g[0, 0])}
+
+
 def _initial(sim, pop):
     rec = np.zeros(sim.N, sim.state().dtype)
     rec["t_exp"] = rec["q_until"] = rec["test_day"] = rec["d1"] = rec["d2"] = -32768
@@ -305,6 +336,8 @@ def main():
         line["c1"] = c1_run()
         log("batched ensemble vs one by one")
         line["batched"] = batched_vs_plain()
+        log("adjoint cost")
+        line["adjoint"] = adjoint_cost()
     if not args.no_extras and not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()

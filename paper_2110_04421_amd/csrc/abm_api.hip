@@ -96,6 +96,7 @@ struct Sizes {
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
   int64_t pb_on = 0, lb = 0, nb1 = 0, nst = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
+  int64_t leaf_cap = 0;
 };
 
 }  // namespace
@@ -274,11 +275,14 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   while (lb < 11 && nb1_of(lb) > 1024) ++lb;
   z.lb = lb;
   z.nb1 = nb1_of(lb);
+  // a leaf holds about rbar * 2^lb entries; room for 3x that (+1024), within LDS
+  const double leaf_mean = rbar * (double)((int64_t)1 << lb);
+  z.leaf_cap = std::min<int64_t>(24576, ((int64_t)(3.0 * leaf_mean) + 1024 + 255) / 256 * 256);
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
-            rbar * (double)((int64_t)1 << lb) * 2.0 < 24576.0 && z.ccap < ((int64_t)1 << 31);
-  z.nst = (z.ntiles + 15) / 16;
+            3.0 * leaf_mean + 1024 <= 24576.0 && z.ccap < ((int64_t)1 << 31);
+  z.nst = (z.ntiles + 63) / 64;
   z.s1_nparts = (z.nb1 * z.nst + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  z.maxch = (z.ccap + 16383) / 16384 + z.nb1;
+  z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
   z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;
   if (p->mode == ABM_SOFT) {
     z.seg = p->checkpoint_every;
@@ -546,6 +550,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_s1_nparts = (int32_t)z.s1_nparts;
     d.pb_maxch = (int32_t)z.maxch;
     d.pb_nleaf = (int32_t)z.nleaf;
+    d.pb_leaf_cap = (int32_t)z.leaf_cap;
     d.pb_ccap = z.ccap;
     d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
     d.pb_part = (int64_t*)(ws + o.pb_part);

@@ -104,7 +104,7 @@ struct Dev {
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)
-  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf;
+  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
   int64_t* pb_part;         // [s1_nparts + 1]

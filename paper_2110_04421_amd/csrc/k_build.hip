@@ -2,7 +2,7 @@
 // claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
 // global atomics and without random 4-byte scatters:
 //
-//   P1  gen/hist    per 16-tile super-tile: draw every agent's contacts, keep its own
+//   P1  gen/hist    per 64-tile super-tile: draw every agent's contacts, keep its own
 //                   counts, histogram the partners by level-1 digit (dest >> (LB + 8)).
 //   S1  scan        digit-major exclusive scan of the histograms -> each (super-tile,
 //                   digit) run's offset; level-1 bucket bounds; chunk table.
@@ -22,10 +22,12 @@
 
 namespace abm {
 
-constexpr int PB_ST = 16;              // tiles per super-tile in P1/P2
-constexpr int PB_CHUNK = 16384;        // entries per level-2 chunk
-constexpr int PB_LEAF_CAP = 24576;     // entries a leaf may hold in LDS
+constexpr int PB_ST = 64;              // tiles per super-tile in P1/P2
+constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: 4 tiles in flight
+constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
+constexpr int PB_ASM_CAP = 8192;       // edges of a tile staged in LDS by the row assembly
+constexpr int PB_S1_PAD = 96 * 1024;   // extra LDS that keeps one P2 workgroup per CU
 
 // Contact generation shared with k_graph.hip (same draws, same order).
 struct Gen {
@@ -73,18 +75,19 @@ __device__ __forceinline__ void load_ptab(const Dev& d, uint32_t* T) {
 }
 
 // ---- P1: own counts and level-1 histogram per super-tile -----------------------------
-__global__ __launch_bounds__(TILE) void k_pb_hist1(Dev d) {
+// 1024 lanes = 4 tiles of 256 agents in flight; a super-tile is PB_ST tiles.
+__global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
   __shared__ uint32_t T[NPT * 64];
   __shared__ int hist[PB_NB1_MAX];
-  load_ptab(d, T);
-  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) hist[k] = 0;
+  for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
+  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS) hist[k] = 0;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
   const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
-  for (int tix = blockIdx.x * PB_ST; tix < tile_end; ++tix) {
+  for (int tix = blockIdx.x * PB_ST + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
     const int4 tl = d.tiles[tix];
-    const int i = tl.y + threadIdx.x;
+    const int i = tl.y + (threadIdx.x & (TILE - 1));
     if (i < tl.z) {
       const RepInfo& ri = d.rep[tl.x];
       const StaticRec sr = d.srec[i];
@@ -99,7 +102,8 @@ __global__ __launch_bounds__(TILE) void k_pb_hist1(Dev d) {
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[k];
+  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS)
+    d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[k];
 }
 
 // ---- generic three-phase exclusive scan over a virtual index ----------------------------
@@ -215,19 +219,23 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 }
 
 // ---- P2: scatter into level-1 runs ---------------------------------------------------
-__global__ __launch_bounds__(TILE) void k_pb_scatter1(Dev d) {
+// One 1024-lane workgroup per CU (the dynamic LDS request keeps it so): the open
+// cache lines of its <= 1024 runs then fit in the XCD's L2, and each run's lines are
+// completed before they are evicted.
+__global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint32_t T[NPT * 64];
   __shared__ int cur[PB_NB1_MAX];
   if (*d.flags) return;
-  load_ptab(d, T);
-  for (int k = threadIdx.x; k < d.pb_nb1; k += TILE) cur[k] = d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k];
+  for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
+  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS)
+    cur[k] = d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k];
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
   const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
-  for (int tix = blockIdx.x * PB_ST; tix < tile_end; ++tix) {
+  for (int tix = blockIdx.x * PB_ST + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
     const int4 tl = d.tiles[tix];
-    const int i = tl.y + threadIdx.x;
+    const int i = tl.y + (threadIdx.x & (TILE - 1));
     if (i < tl.z) {
       const RepInfo& ri = d.rep[tl.x];
       const StaticRec sr = d.srec[i];
@@ -305,18 +313,46 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
 }
 
 // ---- P4: scatter into leaves ---------------------------------------------------------
+// The chunk is counting-sorted by leaf digit in LDS first, so each leaf's part of the
+// chunk leaves as one contiguous run of consecutive lanes.
 __global__ __launch_bounds__(TILE) void k_pb_scatter2(Dev d) {
-  __shared__ int cur[256];
+  __shared__ uint2 sorted[PB_CHUNK];
+  __shared__ int cnt[256], first[256], cur[256];
+  __shared__ int wsum[TILE / 64];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
-  cur[threadIdx.x] = d.pb_hist2[(size_t)c * 256 + threadIdx.x];
-  __syncthreads();
   const int4 ch = d.pb_chunks[c];
+  const int n = ch.z - ch.y;
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE)
+    atomicAdd(&cnt[(d.pb_buf1[e].x >> d.pb_lb) & 255u], 1);
+  __syncthreads();
+  const int v = cnt[threadIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int q = 0; q < wv; ++q) wb += wsum[q];
+  first[threadIdx.x] = wb + inc - v;
+  cur[threadIdx.x] = wb + inc - v;
+  __syncthreads();
   for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE) {
-    const uint2 v = d.pb_buf1[e];
-    const int pos = atomicAdd(&cur[(v.x >> d.pb_lb) & 255u], 1);
-    d.pb_buf2[pos] = v;
+    const uint2 x = d.pb_buf1[e];
+    sorted[atomicAdd(&cur[(x.x >> d.pb_lb) & 255u], 1)] = x;
+  }
+  __syncthreads();
+  const int* off = d.pb_hist2 + (size_t)c * 256;
+  for (int k = threadIdx.x; k < n; k += TILE) {
+    const uint2 x = sorted[k];
+    const int dg = (x.x >> d.pb_lb) & 255u;
+    d.pb_buf2[off[dg] + (k - first[dg])] = x;
   }
 }
 
@@ -327,13 +363,13 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
   const int L = blockIdx.x;
   const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
   const int n = hi - lo;
-  if (n > PB_LEAF_CAP) {
+  if (n > d.pb_leaf_cap) {
     if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
     return;
   }
   const int nkeys = 2 << d.pb_lb;             // (destination offset, network)
-  uint32_t* sorted = lds;                     // [PB_LEAF_CAP]
-  int* cnt = (int*)(lds + PB_LEAF_CAP);       // [nkeys + 1]
+  uint32_t* sorted = lds;                     // [leaf_cap]
+  int* cnt = (int*)(lds + d.pb_leaf_cap);     // [nkeys + 1]
   __shared__ int wsum[TILE / 64];
   __shared__ int carry;
   for (int k = threadIdx.x; k <= nkeys; k += TILE) cnt[k] = 0;
@@ -406,52 +442,58 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
 }
 
 // ---- P6: assemble each row --------------------------------------------------------
+// Rows of a tile are contiguous in the CSR; each lane fills its row in LDS (source id
+// and network), then the tile's edge range is written with consecutive lanes on
+// consecutive addresses.  A tile with more than PB_ASM_CAP edges writes directly.
+__device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* scol, uint8_t* snet,
+                                         int base, int pos, int src, int net) {
+  if (staged) {
+    scol[pos - base] = src;
+    snet[pos - base] = (uint8_t)net;
+  } else {
+    d.col[pos] = src;
+    d.w[pos] = net == 0 ? d.w_h : (net == 1 ? d.w_o : d.w_r);
+  }
+}
+
 __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   __shared__ uint32_t T[NPT * 64];
+  __shared__ int32_t scol[PB_ASM_CAP];
+  __shared__ uint8_t snet[PB_ASM_CAP];
   load_ptab(d, T);
   __syncthreads();
   if (*d.flags) return;
   const int4 tl = d.tiles[blockIdx.x];
+  const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
+  const bool staged = end - base <= PB_ASM_CAP;
   const int i = tl.y + threadIdx.x;
-  if (i >= tl.z) return;
-  const RepInfo& ri = d.rep[tl.x];
-  const uint32_t t = (uint32_t)(*d.day);
-  const StaticRec sr = d.srec[i];
-  const uint32_t loc = (uint32_t)(i - ri.start);
-  const uint32_t r = d.recv[i];
-  const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
-  int pos = d.row_ptr[i];
-  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;
-  for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m) {
-    if (m == i) continue;
-    d.col[pos] = m;
-    d.w[pos] = wh;
-    ++pos;
+  if (i < tl.z) {
+    const RepInfo& ri = d.rep[tl.x];
+    const uint32_t t = (uint32_t)(*d.day);
+    const StaticRec sr = d.srec[i];
+    const uint32_t loc = (uint32_t)(i - ri.start);
+    const uint32_t r = d.recv[i];
+    const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
+    int pos = d.row_ptr[i];
+    for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
+      if (m != i) put_edge(d, staged, scol, snet, base, pos++, m, 0);
+    Gen go = gen_occ(d, sr, loc, t, ri.stream);
+    const int ko = go.count(T + sr.occ * 64);
+    for (int q = 1; q <= ko; ++q) put_edge(d, staged, scol, snet, base, pos++, go.partner(d, q), 1);
+    const int rs = d.pb_rstart[i];
+    for (int q = 0; q < ro; ++q) put_edge(d, staged, scol, snet, base, pos++, (int)d.pb_rsrc[rs + q], 1);
+    Gen gr = gen_rand(d, ri, loc, t);
+    const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+    for (int q = 1; q <= kr; ++q) put_edge(d, staged, scol, snet, base, pos++, gr.partner(d, q), 2);
+    for (int q = 0; q < rr; ++q)
+      put_edge(d, staged, scol, snet, base, pos++, (int)d.pb_rsrc[rs + ro + q], 2);
   }
-  Gen go = gen_occ(d, sr, loc, t, ri.stream);
-  const int ko = go.count(T + sr.occ * 64);
-  for (int q = 1; q <= ko; ++q) {
-    d.col[pos] = go.partner(d, q);
-    d.w[pos] = wo;
-    ++pos;
-  }
-  const int rs = d.pb_rstart[i];
-  for (int q = 0; q < ro; ++q) {
-    d.col[pos] = (int)d.pb_rsrc[rs + q];
-    d.w[pos] = wo;
-    ++pos;
-  }
-  Gen gr = gen_rand(d, ri, loc, t);
-  const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-  for (int q = 1; q <= kr; ++q) {
-    d.col[pos] = gr.partner(d, q);
-    d.w[pos] = wr;
-    ++pos;
-  }
-  for (int q = 0; q < rr; ++q) {
-    d.col[pos] = (int)d.pb_rsrc[rs + ro + q];
-    d.w[pos] = wr;
-    ++pos;
+  if (!staged) return;
+  __syncthreads();
+  const float wt[3] = {d.w_h, d.w_o, d.w_r};
+  for (int k = threadIdx.x; k < end - base; k += TILE) {
+    d.col[base + k] = scol[k];
+    d.w[base + k] = wt[snet[k]];
   }
 }
 
@@ -466,12 +508,15 @@ const char* build_step_name(const Dev& d, int k) {
   return d.pb_on ? pb[k] : cl[k];
 }
 
-static size_t leaf_lds(const Dev& d) { return (size_t)(PB_LEAF_CAP + (2u << d.pb_lb) + 1) * 4; }
+static size_t leaf_lds(const Dev& d) { return (size_t)(d.pb_leaf_cap + (2u << d.pb_lb) + 1) * 4; }
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)leaf_lds(d));
+  hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)leaf_lds(d));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pb_scatter1, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             PB_S1_PAD);
 }
 
 void launch_build_step(const Dev& d, int k, hipStream_t s) {
@@ -486,14 +531,14 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     return;
   }
   switch (k) {
-    case 0: hipLaunchKernelGGL(k_pb_hist1, dim3(d.pb_nst), dim3(TILE), 0, s, d); break;
+    case 0: hipLaunchKernelGGL(k_pb_hist1, dim3(d.pb_nst), dim3(PB_THREADS), 0, s, d); break;
     case 1:
       hipLaunchKernelGGL(k_pb_s1a, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_part, d.pb_s1_nparts);
       hipLaunchKernelGGL(k_pb_s1c, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_buckets, dim3(1), dim3(1024), 0, s, d);
       break;
-    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(TILE), 0, s, d); break;
+    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(PB_THREADS), PB_S1_PAD, s, d); break;
     case 3:
       hipLaunchKernelGGL(k_pb_hist2, dim3(d.pb_maxch), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
