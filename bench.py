@@ -193,7 +193,7 @@ def batched_vs_plain(n_rep: int = 256):
     from paper_2110_04421_amd.sim import Simulator
     from synthpop import workload, split_replicates
     p, pop = workload(3, n_rep=n_rep)
-    with Simulator(p, pop) as s:
+    with Simulator(p, pop, autotune=True) as s:
         s.run(1)
         s.set_state(0, np.zeros(n_rep, np.uint8), _initial(s, pop))
         torch.cuda.synchronize()
@@ -284,8 +284,9 @@ def main():
     N = pop.n_agents
     log(f"{N} agents; creating the simulation")
     ehh = household_edges(pop)
-    with Simulator(p, pop, profile=True) as sim:
-        log(f"warm-up {args.warmup} days, timing {args.steps} days")
+    with Simulator(p, pop, profile=True, autotune=True) as sim:
+        tuning = sim.tuning()
+        log(f"warm-up {args.warmup} days, timing {args.steps} days (tiling {tuning})")
         counts, wall = time_days(sim, args.warmup, args.steps)
         prof = sim.profile()
     log(f"timed {args.steps} days in {wall:.3f} s")
@@ -319,7 +320,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "agents": N, "days_timed": args.steps,
                    "edges_per_day": E_mean, "contacts_per_agent_day": E_mean / N,
-                   "infectious_source_edges_per_day": Einf_mean,
+                   "infectious_source_edges_per_day": Einf_mean, "autotuned_tiling": tuning,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -86,6 +86,9 @@ enum {
 #define ABM_FLAG_NO_GRAPH 2 /* launch day kernels eagerly instead of a HIP graph  */
 #define ABM_FLAG_CLAIM_BUILDER 4 /* build the daily graph with per-edge atomic slot claims
                                     (the default partitions contacts by destination)     */
+#define ABM_FLAG_AUTOTUNE 8 /* at create, time the force-of-infection kernel's tilings
+                               (LDS chunk x grid shape) on day 0's graph, keep the fastest;
+                               results are bitwise the same for every tiling            */
 
 /* Model parameters; copied at create.  Section 3 eq. 1: lambda = R * S_a * A_s * B_n /
  * Ibar * integral of the Gamma infectiousness density over the day. */
@@ -190,7 +193,8 @@ enum {
   ABM_GET_DAY = 8,     /* int32: days run so far                                      */
   ABM_GET_LATCH = 9,   /* uint8[R]: vaccination started                              */
   ABM_GET_SOFT_S = 10, /* float[N]: soft susceptible mass                             */
-  ABM_GET_COEF = 11    /* float[R][9]: fl(fl(R*kappa)*S_a)                             */
+  ABM_GET_COEF = 11,   /* float[R][9]: fl(fl(R*kappa)*S_a)                             */
+  ABM_GET_TUNING = 12  /* int32[2]: message-kernel LDS chunk (edges) and grid (workgroups) */
 };
 /* Copy a device quantity to host (synchronous; h_bytes must be at least its size). */
 int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes);

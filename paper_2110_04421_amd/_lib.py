@@ -14,11 +14,11 @@ HARD, SOFT = 0, 1
 NC = 13
 N_AGE, N_OCC, N_THETA = 9, 23, 10
 NEVER = -32768
-FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER = 1, 2, 4
+FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER, FLAG_AUTOTUNE = 1, 2, 4, 8
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
  C_INF_EDGES) = range(NC)
 (GET_STATE, GET_LAMBDA, GET_CODE, GET_ROWPTR, GET_COL, GET_W, GET_ATAB, GET_POISSON, GET_DAY,
- GET_LATCH, GET_SOFT_S, GET_COEF) = range(12)
+ GET_LATCH, GET_SOFT_S, GET_COEF, GET_TUNING) = range(13)
 MLP_IN, MLP_H, MLP_OUT = 192, 256, 16
 MLP_NPARAM = 256 * 192 + 256 + 256 * 256 + 256 + 16 * 256 + 16
 

@@ -82,7 +82,7 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, lambda, own, recv, row_ptr,
+  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, prev_counts,
       traj, day, flags, seeds;
   size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
@@ -303,7 +303,8 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.ptab = L.take<uint32_t>(NPT * 64);
   o.state = L.take<AgentState>(z.N);
   o.code = L.take<uint8_t>(z.N + 32);
-  o.imask = L.take<uint32_t>((z.N + 31) / 32 + 1);
+  o.imask = L.take<uint32_t>((z.N + 255) / 256 * 8 + 8);
+  o.cmask = L.take<uint32_t>((z.N + 255) / 256 + 1);
   o.lambda = L.take<float>(z.N);
   o.own = L.take<uint16_t>(z.N);
   o.recv = L.take<uint32_t>(z.N);
@@ -413,6 +414,44 @@ int drain_profile(abm_sim* s) {
   return ABM_OK;
 }
 
+// Autotuner: time every message-kernel variant (LDS chunk x grid shape) on day 0's
+// graph and keep the fastest.  Every variant sums each row in the same order, so the
+// choice changes timing only.  Day 0's pre-pass and graph build leave the agent state
+// untouched (no result is due and nobody is quarantined before day 0).
+int autotune(abm_sim* s) {
+  Dev& d = s->d;
+  hipStream_t st = s->stream;
+  launch_pre(d, st);
+  launch_mask(d, st);
+  for (int b = 0; b < build_steps(d); ++b) launch_build_step(d, b, st);
+  hipEvent_t e0, e1;
+  HIPCHK(s, hipEventCreate(&e0));
+  HIPCHK(s, hipEventCreate(&e1));
+  float best = 1e30f;
+  int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid;
+  for (int v = 0; v < message_variants(); ++v) {
+    message_variant(d, v, &d.msg_chunk, &d.msg_grid);
+    launch_message(d, st);                                 // warm-up
+    HIPCHK(s, hipEventRecord(e0, st));
+    for (int rep = 0; rep < 3; ++rep) launch_message(d, st);
+    HIPCHK(s, hipEventRecord(e1, st));
+    HIPCHK(s, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_chunk = d.msg_chunk;
+      best_grid = d.msg_grid;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  d.msg_chunk = best_chunk;
+  d.msg_grid = best_grid;
+  HIPCHK(s, hipGetLastError());
+  return ABM_OK;
+}
+
 int check_dev_flags(abm_sim* s) {
   int32_t f = 0;
   HIPCHK(s, hipMemcpyAsync(&f, s->d.flags, sizeof f, hipMemcpyDeviceToHost, s->stream));
@@ -505,6 +544,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.state = (AgentState*)(ws + o.state);
   d.code = (uint8_t*)(ws + o.code);
   d.imask = (uint32_t*)(ws + o.imask);
+  d.cmask = (uint32_t*)(ws + o.cmask);
   d.lambda = (float*)(ws + o.lambda);
   d.own = (uint16_t*)(ws + o.own);
   d.recv = (uint32_t*)(ws + o.recv);
@@ -542,6 +582,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.dL = (const float*)(ws + o.dL);
     d.seg = (int32_t)z.seg;
   }
+  d.msg_chunk = 4096;
+  d.msg_grid = d.ntiles;
   d.pb_on = (int32_t)z.pb_on;
   if (z.pb_on) {
     d.pb_lb = (int32_t)z.lb;
@@ -661,6 +703,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   HIPCHK(s, prepare_build(d));
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipStreamSynchronize(st));
+  if ((p->flags & ABM_FLAG_AUTOTUNE) && p->mode == ABM_HARD) {
+    rc = autotune(s);
+    if (rc) return rc;
+  }
   const bool use_graph = !(p->flags & (ABM_FLAG_PROFILE | ABM_FLAG_NO_GRAPH)) && p->mode == ABM_HARD;
   if (use_graph) {
     HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
@@ -749,6 +795,13 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
       if (h_bytes < 4) return s->fail(ABM_E_ARG, "buffer too small");
       *(int32_t*)h_dst = s->host_day;
       return ABM_OK;
+    case ABM_GET_TUNING: {
+      if (h_bytes < 8) return s->fail(ABM_E_ARG, "buffer too small");
+      int32_t* v = (int32_t*)h_dst;
+      v[0] = s->d.msg_chunk;
+      v[1] = s->d.msg_grid;
+      return ABM_OK;
+    }
     case ABM_GET_COEF: {
       if (h_bytes < (size_t)s->z.R * ABM_N_AGE * 4) return s->fail(ABM_E_ARG, "buffer too small");
       float* f = (float*)h_dst;

@@ -80,6 +80,7 @@ struct Dev {
   AgentState* state;
   uint8_t* code;
   uint32_t* imask;              // bit i: agent i infectious today (code != 0)
+  uint32_t* cmask;              // bit g: one of agents [8g, 8g + 8) infectious today
   float* lambda;
 
   uint16_t* own;                // k_occ | k_rand << 8 (drawn by the agent)
@@ -104,6 +105,7 @@ struct Dev {
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)
+  int32_t msg_chunk, msg_grid;    // message-kernel tiling (autotuned or default)
   int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
@@ -185,6 +187,8 @@ void launch_scan(const Dev& d, hipStream_t s);
 void launch_fill(const Dev& d, hipStream_t s);
 void launch_canon(const Dev& d, hipStream_t s);
 void launch_message(const Dev& d, hipStream_t s);
+int message_variants();
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid);
 void launch_fused(const Dev& d, hipStream_t s);
 void launch_finalize(const Dev& d, hipStream_t s);
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);

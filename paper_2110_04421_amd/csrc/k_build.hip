@@ -78,12 +78,13 @@ __device__ __forceinline__ void load_ptab(const Dev& d, uint32_t* T) {
 // 1024 lanes = 4 tiles of 256 agents in flight; a super-tile is PB_ST tiles.
 __global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int hist[PB_NB1_MAX];
+  __shared__ int hist[PB_THREADS / TILE][PB_NB1_MAX];   // one copy per tile lane group
   for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
-  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS) hist[k] = 0;
+  for (int k = threadIdx.x; k < (PB_THREADS / TILE) * PB_NB1_MAX; k += PB_THREADS) (&hist[0][0])[k] = 0;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
+  int* h = hist[threadIdx.x >> 8];
   const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
   for (int tix = blockIdx.x * PB_ST + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
     const int4 tl = d.tiles[tix];
@@ -94,16 +95,16 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
       const uint32_t loc = (uint32_t)(i - ri.start);
       Gen go = gen_occ(d, sr, loc, t, ri.stream);
       const int ko = go.count(T + sr.occ * 64);
-      for (int q = 1; q <= ko; ++q) atomicAdd(&hist[go.partner(d, q) >> s1], 1);
+      for (int q = 1; q <= ko; ++q) atomicAdd(&h[go.partner(d, q) >> s1], 1);
       Gen gr = gen_rand(d, ri, loc, t);
       const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-      for (int q = 1; q <= kr; ++q) atomicAdd(&hist[gr.partner(d, q) >> s1], 1);
+      for (int q = 1; q <= kr; ++q) atomicAdd(&h[gr.partner(d, q) >> s1], 1);
       d.own[i] = (uint16_t)(ko | (kr << 8));
     }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS)
-    d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[k];
+    d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[0][k] + hist[1][k] + hist[2][k] + hist[3][k];
 }
 
 // ---- generic three-phase exclusive scan over a virtual index ----------------------------

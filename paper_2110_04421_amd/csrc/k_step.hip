@@ -1,6 +1,8 @@
 // Per-day agent kernels: interventions before transmission, the edge-message force of
 // infection (eq. 1), the fused infection / progression / testing / vaccination step
 // (eq. 2; sections 3-5), and the end-of-day bookkeeping.
+#include <algorithm>
+
 #include "abm_internal.h"
 
 namespace abm {
@@ -100,29 +102,38 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   }
 }
 
-// ---- infectious bit mask: one 32-bit word per 32 agents ----------------------------
-// Most edges come from non-infectious sources; the message kernel tests a bit from this
-// 1-bit-per-agent mask (cache resident) before gathering the source's code byte.
+// ---- infectious bit masks ---------------------------------------------------------
+// Fine: bit i = agent i infectious today (one 32-bit word per 32 agents, 1/8 byte per
+// agent).  Coarse: bit g = some agent of the group [8g, 8g+8) infectious (1/64 byte per
+// agent, small enough to stay in L2).  The message kernel tests the coarse bit, then the
+// fine bit, before it reads an edge's weight and the source's code byte.
 __global__ __launch_bounds__(TILE) void k_mask(Dev d) {
-  const int w = blockIdx.x * TILE + threadIdx.x;
-  const int nw = (d.N + 31) >> 5;
-  if (w >= nw) return;
-  const int i0 = w << 5;
-  uint32_t m = 0;
-  if (i0 + 32 <= d.N) {
-    const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
-    const uint4 a = c4[0], b = c4[1];
-    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  const int w = blockIdx.x * TILE + threadIdx.x;       // coarse word: agents [256w, 256w+256)
+  const int ncw = (d.N + 255) >> 8;
+  if (w >= ncw) return;
+  uint32_t coarse = 0;
+  for (int f = 0; f < 8; ++f) {
+    const int i0 = (w << 8) + (f << 5);
+    uint32_t m = 0;
+    if (i0 + 32 <= d.N) {
+      const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
+      const uint4 a = c4[0], b = c4[1];
+      const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
-  } else {
-    for (int k = 0; i0 + k < d.N; ++k)
-      if (d.code[i0 + k]) m |= 1u << k;
+        for (int k = 0; k < 4; ++k)
+          if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
+    } else {
+      for (int k = 0; i0 + k < d.N && k < 32; ++k)
+        if (d.code[i0 + k]) m |= 1u << k;
+    }
+    if (i0 < d.N) d.imask[i0 >> 5] = m;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      if ((m >> (8 * g)) & 0xFFu) coarse |= 1u << (4 * f + g);
   }
-  d.imask[w] = m;
+  d.cmask[w] = coarse;
 }
 
 // ---- vaccination plan: one workgroup per replicate ------------------------------------
@@ -206,49 +217,55 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 }
 
 // ---- force of infection: lambda_j = coef[a_j] * sum_{e in row j} w_e * Atab[code[src_e]]
-// A tile of 256 rows streams its contiguous edge range through LDS in chunks: the
-// column loads and the 1-bit infectious-mask tests are spread over all lanes; the
+// A tile of 256 rows streams its contiguous edge range through LDS in chunks of CHUNK
+// edges: the column loads and the infectious-mask tests are spread over all lanes; the
 // weight and the code byte are read only for infectious sources (the others add +0).
-// Each lane then sums its own row left to right (FP32, canonical order) from LDS.
+// Each lane then sums its own row left to right (FP32, canonical order) from LDS, so
+// the result does not depend on CHUNK or on how tiles map to workgroups (the grid may
+// be one workgroup per tile or a persistent grid striding over the tiles).
+template <int CHUNK>
 __global__ __launch_bounds__(TILE) void k_message(Dev d) {
   __shared__ float atab[ATAB];
-  __shared__ float term[MSG_CHUNK];
+  __shared__ float term[CHUNK];
   __shared__ uint32_t ninf[TILE / 64];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
-  const int4 tl = d.tiles[blockIdx.x];
-  const int i = tl.y + threadIdx.x;
-  const bool live = i < tl.z;
-  const int e0 = d.row_ptr[tl.y], e1 = d.row_ptr[tl.z];
-  const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
-  float sum = 0.f;
-  uint32_t infected_edges = 0;
-  __syncthreads();
-  for (int c0 = e0; c0 < e1; c0 += MSG_CHUNK) {
-    const int cn = min(MSG_CHUNK, e1 - c0);
-    for (int k = threadIdx.x; k < cn; k += TILE) {
-      const int e = c0 + k;
-      uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
-      src = src < (uint32_t)d.N ? src : 0u;
-      const bool inf = (d.imask[src >> 5] >> (src & 31u)) & 1u;
-      float v = 0.f;
-      if (inf) {
-        v = __builtin_nontemporal_load(d.w + e) * atab[d.code[src]];
-        ++infected_edges;
+  for (int tix = blockIdx.x; tix < d.ntiles; tix += gridDim.x) {
+    const int4 tl = d.tiles[tix];
+    const int i = tl.y + threadIdx.x;
+    const bool live = i < tl.z;
+    const int e0 = d.row_ptr[tl.y], e1 = d.row_ptr[tl.z];
+    const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
+    float sum = 0.f;
+    uint32_t infected_edges = 0;
+    __syncthreads();
+    for (int c0 = e0; c0 < e1; c0 += CHUNK) {
+      const int cn = min(CHUNK, e1 - c0);
+      for (int k = threadIdx.x; k < cn; k += TILE) {
+        const int e = c0 + k;
+        uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
+        src = src < (uint32_t)d.N ? src : 0u;
+        const bool inf = ((d.cmask[src >> 8] >> ((src >> 3) & 31u)) & 1u) &&
+                         ((d.imask[src >> 5] >> (src & 31u)) & 1u);
+        float v = 0.f;
+        if (inf) {
+          v = __builtin_nontemporal_load(d.w + e) * atab[d.code[src]];
+          ++infected_edges;
+        }
+        term[k] = v;
       }
-      term[k] = v;
+      __syncthreads();
+      const int lo = max(rs, c0), hi = min(re, c0 + cn);
+      for (int e = lo; e < hi; ++e) sum += term[e - c0];
+      __syncthreads();
     }
+    if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
+    for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
+    if ((threadIdx.x & 63) == 0) ninf[threadIdx.x >> 6] = infected_edges;
     __syncthreads();
-    const int lo = max(rs, c0), hi = min(re, c0 + cn);
-    for (int e = lo; e < hi; ++e) sum += term[e - c0];
-    __syncthreads();
+    if (threadIdx.x == 0)
+      d.tile_counts[(size_t)tix * TILE_NC + ABM_C_INF_EDGES] = ninf[0] + ninf[1] + ninf[2] + ninf[3];
   }
-  if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
-  for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
-  if ((threadIdx.x & 63) == 0) ninf[threadIdx.x >> 6] = infected_edges;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    d.tile_counts[(size_t)blockIdx.x * TILE_NC + ABM_C_INF_EDGES] = ninf[0] + ninf[1] + ninf[2] + ninf[3];
 }
 
 // ---- fused day step ---------------------------------------------------------------
@@ -440,14 +457,29 @@ void launch_pre(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pre, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
 void launch_mask(const Dev& d, hipStream_t s) {
-  const int nw = (d.N + 31) >> 5;
-  hipLaunchKernelGGL(k_mask, dim3((nw + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+  const int ncw = (d.N + 255) >> 8;
+  hipLaunchKernelGGL(k_mask, dim3((ncw + TILE - 1) / TILE), dim3(TILE), 0, s, d);
 }
 void launch_vplan(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
 }
+// Message-kernel variants the autotuner chooses from: LDS chunk x grid shape.
+int message_variants() { return 12; }
+
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid) {
+  static const int chunks[3] = {1024, 2048, 4096};
+  const int grids[4] = {d.ntiles, 256 * 4, 256 * 8, 256 * 16};
+  *chunk = chunks[v % 3];
+  *grid = std::min(d.ntiles, grids[v / 3]);
+}
+
 void launch_message(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_message, dim3(d.ntiles), dim3(TILE), 0, s, d);
+  const dim3 g(d.msg_grid > 0 ? d.msg_grid : d.ntiles);
+  switch (d.msg_chunk) {
+    case 1024: hipLaunchKernelGGL(k_message<1024>, g, dim3(TILE), 0, s, d); break;
+    case 2048: hipLaunchKernelGGL(k_message<2048>, g, dim3(TILE), 0, s, d); break;
+    default: hipLaunchKernelGGL(k_message<4096>, g, dim3(TILE), 0, s, d); break;
+  }
 }
 void launch_fused(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);

@@ -25,15 +25,17 @@ class Simulator:
     ``params``: flat parameter dict (see synthpop.configs); ``pop``: population object with
     the arrays of abm_population.  ``profile`` times every kernel with HIP events;
     ``graph=False`` launches the day's kernels eagerly instead of replaying a HIP graph;
-    ``claim_builder`` selects the per-edge atomic-claim graph builder.
+    ``claim_builder`` selects the per-edge atomic-claim graph builder; ``autotune`` times
+    the force-of-infection kernel's tilings at create and keeps the fastest.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
-                 claim_builder: bool = False, stream=None):
+                 claim_builder: bool = False, autotune: bool = False, stream=None):
         torch = _torch()
         self._lib = L.lib()
         flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
-                 | (L.FLAG_CLAIM_BUILDER if claim_builder else 0))
+                 | (L.FLAG_CLAIM_BUILDER if claim_builder else 0)
+                 | (L.FLAG_AUTOTUNE if autotune else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)
@@ -141,6 +143,10 @@ class Simulator:
 
     def coef(self) -> np.ndarray:
         return self._get(L.GET_COEF, np.float32, self.R * 9).reshape(self.R, 9)
+
+    def tuning(self) -> dict:
+        v = self._get(L.GET_TUNING, np.int32, 2)
+        return {"message_chunk": int(v[0]), "message_grid": int(v[1])}
 
     def soft_s(self) -> np.ndarray:
         return self._get(L.GET_SOFT_S, np.float32, self.N)

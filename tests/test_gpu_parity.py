@@ -206,3 +206,16 @@ def test_csr_bit_exact_several_level1_buckets():
     assert np.array_equal(rp.astype(np.int64), rp_o)
     assert np.array_equal(col.astype(np.int64), col_o)
     assert np.array_equal(w, w_o.astype(np.float32))
+
+
+def test_autotuned_tiling_gives_identical_results():
+    p, pop = workload(3, n=50000, n_rep=6, n_steps=12, vacc_trigger=0.001)
+    outs = []
+    for tune in (False, True):
+        with _sim(p, pop, autotune=tune) as s:
+            outs.append((s.run(12), s.state(), s.lam(), s.tuning()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2].view(np.uint32), outs[1][2].view(np.uint32))
+    t = outs[1][3]
+    assert t["message_chunk"] in (1024, 2048, 4096) and 1 <= t["message_grid"]
