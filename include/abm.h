@@ -194,7 +194,8 @@ enum {
   ABM_GET_LATCH = 9,   /* uint8[R]: vaccination started                              */
   ABM_GET_SOFT_S = 10, /* float[N]: soft susceptible mass                             */
   ABM_GET_COEF = 11,   /* float[R][9]: fl(fl(R*kappa)*S_a)                             */
-  ABM_GET_TUNING = 12  /* int32[2]: message-kernel LDS chunk (edges) and grid (workgroups) */
+  ABM_GET_TUNING = 12  /* int32[3]: message-kernel LDS chunk (edges), grid (workgroups),
+                          first mask level in LDS (1) or L2 (0)                        */
 };
 /* Copy a device quantity to host (synchronous; h_bytes must be at least its size). */
 int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes);

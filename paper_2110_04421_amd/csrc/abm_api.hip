@@ -82,7 +82,7 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, lambda, own, recv, row_ptr,
+  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, prev_counts,
       traj, day, flags, seeds;
   size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
@@ -305,6 +305,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.code = L.take<uint8_t>(z.N + 32);
   o.imask = L.take<uint32_t>((z.N + 255) / 256 * 8 + 8);
   o.cmask = L.take<uint32_t>((z.N + 255) / 256 + 1);
+  o.scmask = L.take<unsigned long long>((z.N + 16383) / 16384 + 4);
   o.lambda = L.take<float>(z.N);
   o.own = L.take<uint16_t>(z.N);
   o.recv = L.take<uint32_t>(z.N);
@@ -428,9 +429,9 @@ int autotune(abm_sim* s) {
   HIPCHK(s, hipEventCreate(&e0));
   HIPCHK(s, hipEventCreate(&e1));
   float best = 1e30f;
-  int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid;
+  int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid, best_lds = d.msg_ldsmask;
   for (int v = 0; v < message_variants(); ++v) {
-    message_variant(d, v, &d.msg_chunk, &d.msg_grid);
+    message_variant(d, v, &d.msg_chunk, &d.msg_grid, &d.msg_ldsmask);
     launch_message(d, st);                                 // warm-up
     HIPCHK(s, hipEventRecord(e0, st));
     for (int rep = 0; rep < 3; ++rep) launch_message(d, st);
@@ -442,12 +443,14 @@ int autotune(abm_sim* s) {
       best = ms;
       best_chunk = d.msg_chunk;
       best_grid = d.msg_grid;
+      best_lds = d.msg_ldsmask;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   d.msg_chunk = best_chunk;
   d.msg_grid = best_grid;
+  d.msg_ldsmask = best_lds;
   HIPCHK(s, hipGetLastError());
   return ABM_OK;
 }
@@ -545,6 +548,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.code = (uint8_t*)(ws + o.code);
   d.imask = (uint32_t*)(ws + o.imask);
   d.cmask = (uint32_t*)(ws + o.cmask);
+  d.scmask = (unsigned long long*)(ws + o.scmask);
+  d.nsc = (int32_t)((z.N + 16383) / 16384);
   d.lambda = (float*)(ws + o.lambda);
   d.own = (uint16_t*)(ws + o.own);
   d.recv = (uint32_t*)(ws + o.recv);
@@ -584,6 +589,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   }
   d.msg_chunk = 4096;
   d.msg_grid = d.ntiles;
+  d.msg_ldsmask = 0;
   d.pb_on = (int32_t)z.pb_on;
   if (z.pb_on) {
     d.pb_lb = (int32_t)z.lb;
@@ -796,10 +802,11 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
       *(int32_t*)h_dst = s->host_day;
       return ABM_OK;
     case ABM_GET_TUNING: {
-      if (h_bytes < 8) return s->fail(ABM_E_ARG, "buffer too small");
+      if (h_bytes < 12) return s->fail(ABM_E_ARG, "buffer too small");
       int32_t* v = (int32_t*)h_dst;
       v[0] = s->d.msg_chunk;
       v[1] = s->d.msg_grid;
+      v[2] = s->d.msg_ldsmask;
       return ABM_OK;
     }
     case ABM_GET_COEF: {

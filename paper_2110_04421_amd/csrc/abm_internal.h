@@ -18,6 +18,7 @@ constexpr int SCAN_BLOCK = TILE * SCAN_ITEMS;
 constexpr int MSG_CHUNK = 4096;    // edges staged in LDS per step of the message kernel
 constexpr int TILE_NC = 16;       // per-tile count row (ABM_NC slots, padded)
 static_assert(ABM_NC <= TILE_NC, "count slots fit a tile row");
+constexpr size_t SCMASK_LDS_MAX = 48 * 1024;   // largest LDS copy of the super-coarse mask
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
 enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };
@@ -81,6 +82,8 @@ struct Dev {
   uint8_t* code;
   uint32_t* imask;              // bit i: agent i infectious today (code != 0)
   uint32_t* cmask;              // bit g: one of agents [8g, 8g + 8) infectious today
+  unsigned long long* scmask;   // bit g: one of agents [256g, 256g + 256) infectious today
+  int32_t nsc;                  // words of scmask
   float* lambda;
 
   uint16_t* own;                // k_occ | k_rand << 8 (drawn by the agent)
@@ -105,7 +108,7 @@ struct Dev {
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)
-  int32_t msg_chunk, msg_grid;    // message-kernel tiling (autotuned or default)
+  int32_t msg_chunk, msg_grid, msg_ldsmask;   // message-kernel tiling (autotuned or default)
   int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
@@ -188,7 +191,7 @@ void launch_fill(const Dev& d, hipStream_t s);
 void launch_canon(const Dev& d, hipStream_t s);
 void launch_message(const Dev& d, hipStream_t s);
 int message_variants();
-void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid);
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* ldsmask);
 void launch_fused(const Dev& d, hipStream_t s);
 void launch_finalize(const Dev& d, hipStream_t s);
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);

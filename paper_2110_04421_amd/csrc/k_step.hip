@@ -110,30 +110,34 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
 __global__ __launch_bounds__(TILE) void k_mask(Dev d) {
   const int w = blockIdx.x * TILE + threadIdx.x;       // coarse word: agents [256w, 256w+256)
   const int ncw = (d.N + 255) >> 8;
-  if (w >= ncw) return;
   uint32_t coarse = 0;
-  for (int f = 0; f < 8; ++f) {
-    const int i0 = (w << 8) + (f << 5);
-    uint32_t m = 0;
-    if (i0 + 32 <= d.N) {
-      const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
-      const uint4 a = c4[0], b = c4[1];
-      const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  if (w < ncw) {
+    for (int f = 0; f < 8; ++f) {
+      const int i0 = (w << 8) + (f << 5);
+      uint32_t m = 0;
+      if (i0 + 32 <= d.N) {
+        const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
+        const uint4 a = c4[0], b = c4[1];
+        const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 8; ++q)
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
-    } else {
-      for (int k = 0; i0 + k < d.N && k < 32; ++k)
-        if (d.code[i0 + k]) m |= 1u << k;
+          for (int k = 0; k < 4; ++k)
+            if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
+      } else {
+        for (int k = 0; i0 + k < d.N && k < 32; ++k)
+          if (d.code[i0 + k]) m |= 1u << k;
+      }
+      if (i0 < d.N) d.imask[i0 >> 5] = m;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if ((m >> (8 * g)) & 0xFFu) coarse |= 1u << (4 * f + g);
     }
-    if (i0 < d.N) d.imask[i0 >> 5] = m;
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-      if ((m >> (8 * g)) & 0xFFu) coarse |= 1u << (4 * f + g);
+    d.cmask[w] = coarse;
   }
-  d.cmask[w] = coarse;
+  // super-coarse: bit w = some agent of [256w, 256w+256) infectious (one word per wave)
+  const unsigned long long b = __ballot(coarse != 0u);
+  if ((threadIdx.x & 63) == 0 && (w >> 6) < d.nsc) d.scmask[w >> 6] = b;
 }
 
 // ---- vaccination plan: one workgroup per replicate ------------------------------------
@@ -223,13 +227,16 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 // Each lane then sums its own row left to right (FP32, canonical order) from LDS, so
 // the result does not depend on CHUNK or on how tiles map to workgroups (the grid may
 // be one workgroup per tile or a persistent grid striding over the tiles).
-template <int CHUNK>
+template <int CHUNK, bool LDSMASK>
 __global__ __launch_bounds__(TILE) void k_message(Dev d) {
+  extern __shared__ unsigned long long scm[];        // super-coarse mask (LDSMASK)
   __shared__ float atab[ATAB];
   __shared__ float term[CHUNK];
   __shared__ uint32_t ninf[TILE / 64];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
+  if (LDSMASK)
+    for (int q = threadIdx.x; q < d.nsc; q += TILE) scm[q] = d.scmask[q];
   for (int tix = blockIdx.x; tix < d.ntiles; tix += gridDim.x) {
     const int4 tl = d.tiles[tix];
     const int i = tl.y + threadIdx.x;
@@ -245,8 +252,9 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
         const int e = c0 + k;
         uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
         src = src < (uint32_t)d.N ? src : 0u;
-        const bool inf = ((d.cmask[src >> 8] >> ((src >> 3) & 31u)) & 1u) &&
-                         ((d.imask[src >> 5] >> (src & 31u)) & 1u);
+        bool inf = LDSMASK ? ((scm[src >> 14] >> ((src >> 8) & 63u)) & 1ull) != 0 : true;
+        inf = inf && ((d.cmask[src >> 8] >> ((src >> 3) & 31u)) & 1u) &&
+              ((d.imask[src >> 5] >> (src & 31u)) & 1u);
         float v = 0.f;
         if (inf) {
           v = __builtin_nontemporal_load(d.w + e) * atab[d.code[src]];
@@ -463,24 +471,36 @@ void launch_mask(const Dev& d, hipStream_t s) {
 void launch_vplan(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
 }
-// Message-kernel variants the autotuner chooses from: LDS chunk x grid shape.
-int message_variants() { return 12; }
+// Message-kernel variants the autotuner chooses from: LDS chunk x grid shape x where
+// the first mask level lives (L2, or LDS for persistent grids when it fits).
+int message_variants() { return 21; }
 
-void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid) {
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* ldsmask) {
   static const int chunks[3] = {1024, 2048, 4096};
+  const int shape = v / 3;                       // 0: a workgroup per tile; 1..6 persistent
   const int grids[4] = {d.ntiles, 256 * 4, 256 * 8, 256 * 16};
   *chunk = chunks[v % 3];
-  *grid = std::min(d.ntiles, grids[v / 3]);
+  *grid = std::min(d.ntiles, grids[shape == 0 ? 0 : 1 + (shape - 1) % 3]);
+  *ldsmask = (shape >= 4 && (size_t)d.nsc * 8 <= SCMASK_LDS_MAX) ? 1 : 0;
+}
+
+template <int C>
+static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
+  if (d.msg_ldsmask)
+    hipLaunchKernelGGL((k_message<C, true>), g, dim3(TILE), (size_t)d.nsc * 8, s, d);
+  else
+    hipLaunchKernelGGL((k_message<C, false>), g, dim3(TILE), 0, s, d);
 }
 
 void launch_message(const Dev& d, hipStream_t s) {
   const dim3 g(d.msg_grid > 0 ? d.msg_grid : d.ntiles);
   switch (d.msg_chunk) {
-    case 1024: hipLaunchKernelGGL(k_message<1024>, g, dim3(TILE), 0, s, d); break;
-    case 2048: hipLaunchKernelGGL(k_message<2048>, g, dim3(TILE), 0, s, d); break;
-    default: hipLaunchKernelGGL(k_message<4096>, g, dim3(TILE), 0, s, d); break;
+    case 1024: launch_msg<1024>(d, g, s); break;
+    case 2048: launch_msg<2048>(d, g, s); break;
+    default: launch_msg<4096>(d, g, s); break;
   }
 }
+
 void launch_fused(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }

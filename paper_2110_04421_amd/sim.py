@@ -145,8 +145,8 @@ class Simulator:
         return self._get(L.GET_COEF, np.float32, self.R * 9).reshape(self.R, 9)
 
     def tuning(self) -> dict:
-        v = self._get(L.GET_TUNING, np.int32, 2)
-        return {"message_chunk": int(v[0]), "message_grid": int(v[1])}
+        v = self._get(L.GET_TUNING, np.int32, 3)
+        return {"message_chunk": int(v[0]), "message_grid": int(v[1]), "mask_in_lds": int(v[2])}
 
     def soft_s(self) -> np.ndarray:
         return self._get(L.GET_SOFT_S, np.float32, self.N)
