@@ -56,14 +56,14 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
     edges), N = agents."""
     Einf = E if Einf is None else Einf
     lb = leaf_bits(N, C)
-    nst, nb1 = -(-N // 16384), -(-N // (1 << (lb + 8)))
+    nbt, nb1 = -(-N // 1024), -(-N // (1 << (lb + 8)))
     table = {
         # force of infection: col + 1 mask bit per edge, w + code byte per infectious
         # edge; row_ptr, age, lambda per row
         "message": 4.125 * E + 5.0 * Einf + 9.0 * N,
         # partitioned builder
-        "pb_hist1": 18.0 * N,                      # static record in, own counts out
-        "pb_scan1": 12.0 * nst * nb1,              # histogram read twice, offsets written
+        "pb_hist1": 18.0 * N + 4.0 * nbt * nb1,    # static record in, own counts + histograms out
+        "pb_scan1": 12.0 * nbt * nb1,              # histograms read twice, offsets written
         "pb_scatter1": 16.0 * N + 8.0 * C,         # static record in, (dest, src) out
         "pb_hist2": 8.0 * C,
         "pb_scatter2": 16.0 * C,

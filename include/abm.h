@@ -89,6 +89,10 @@ enum {
 #define ABM_FLAG_AUTOTUNE 8 /* at create, time the force-of-infection kernel's tilings
                                (LDS chunk x grid shape) on day 0's graph, keep the fastest;
                                results are bitwise the same for every tiling            */
+#define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
+                                    assembly their smallest LDS room, so that leaves are
+                                    sorted in several groups and tiles are written
+                                    directly; the graph is bitwise the same             */
 
 /* Model parameters; copied at create.  Section 3 eq. 1: lambda = R * S_a * A_s * B_n /
  * Ibar * integral of the Gamma infectiousness density over the day. */

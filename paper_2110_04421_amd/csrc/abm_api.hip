@@ -83,7 +83,7 @@ struct Layout {
 
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
-      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, prev_counts,
+      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds;
   size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
       pb_buf2, pb_rsrc, pb_rstart;
@@ -95,8 +95,9 @@ struct Sizes {
   int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
-  int64_t pb_on = 0, lb = 0, nb1 = 0, nst = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
-  int64_t leaf_cap = 0;
+  int64_t pb_on = 0, lb = 0, nb1 = 0, nst = 0, nbatch = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
+  int64_t leaf_cap = 0, asm_cap = 0;
+  int64_t fseg = 1;
 };
 
 }  // namespace
@@ -234,7 +235,14 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
         return bad("initial infection outside its replicate");
     }
   z.ntiles = 0;
-  for (int r = 0; r < R; ++r) z.ntiles += (pop->agent_offset[r + 1] - pop->agent_offset[r] + TILE - 1) / TILE;
+  int64_t max_rep_tiles = 0;
+  for (int r = 0; r < R; ++r) {
+    const int64_t nt = (pop->agent_offset[r + 1] - pop->agent_offset[r] + TILE - 1) / TILE;
+    z.ntiles += nt;
+    max_rep_tiles = std::max(max_rep_tiles, nt);
+  }
+  // end-of-day count reduction: each replicate's tile rows in fseg parts of 256 lanes
+  z.fseg = std::max<int64_t>(1, std::min<int64_t>(256, (max_rep_tiles + 255) / 256));
   z.nscan = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
   // Edge room: mean directed edges + 8 standard deviations of the Poisson contact count.
   double hh_edges = 0;
@@ -275,13 +283,23 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   while (lb < 11 && nb1_of(lb) > 1024) ++lb;
   z.lb = lb;
   z.nb1 = nb1_of(lb);
-  // a leaf holds about rbar * 2^lb entries; room for 3x that (+1024), within LDS
+  // a leaf holds about rbar * 2^lb entries; its LDS room is 1.25x that (+512).  A
+  // larger leaf is sorted in several groups of destinations, so the room only bounds
+  // occupancy, not correctness.
   const double leaf_mean = rbar * (double)((int64_t)1 << lb);
-  z.leaf_cap = std::min<int64_t>(24576, ((int64_t)(3.0 * leaf_mean) + 1024 + 255) / 256 * 256);
+  z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
-            3.0 * leaf_mean + 1024 <= 24576.0 && z.ccap < ((int64_t)1 << 31);
+            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31);
+  // edges of a tile staged in LDS by the row assembly: 1.25x the mean (+512)
+  const double tile_mean = emean * (double)TILE / (double)N;
+  z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.25 * tile_mean) + 512 + 255) / 256 * 256));
+  if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {
+    z.leaf_cap = 1024;
+    z.asm_cap = 2048;
+  }
   z.nst = (z.ntiles + 63) / 64;
-  z.s1_nparts = (z.nb1 * z.nst + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  z.nbatch = (z.ntiles + 3) / 4;
+  z.s1_nparts = (z.nb1 * z.nbatch + SCAN_BLOCK - 1) / SCAN_BLOCK;
   z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
   z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;
   if (p->mode == ABM_SOFT) {
@@ -320,13 +338,14 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.vtile = L.take<int32_t>(z.ntiles);
   o.latch = L.take<uint8_t>(z.R);
   o.tile_counts = L.take<uint32_t>(z.ntiles * TILE_NC);
+  o.fin_part = L.take<unsigned long long>(z.R * z.fseg * TILE_NC);
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
   o.day = L.take<int32_t>(1);
   o.flags = L.take<int32_t>(1);
   o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
   if (z.pb_on) {
-    o.pb_hist1 = L.take<int32_t>(z.nst * z.nb1);
+    o.pb_hist1 = L.take<int32_t>(z.nbatch * z.nb1 + 1);
     o.pb_part = L.take<int64_t>(z.s1_nparts + 1);
     o.pb_bstart = L.take<int32_t>(z.nb1 + 1);
     o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
@@ -564,6 +583,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.vtile_base = (int32_t*)(ws + o.vtile);
   d.latch = (uint8_t*)(ws + o.latch);
   d.tile_counts = (uint32_t*)(ws + o.tile_counts);
+  d.fin_part = (unsigned long long*)(ws + o.fin_part);
+  d.fseg = (int32_t)z.fseg;
   d.prev_counts = (long long*)(ws + o.prev_counts);
   d.traj = (long long*)(ws + o.traj);
   d.day = (int32_t*)(ws + o.day);
@@ -595,10 +616,12 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_lb = (int32_t)z.lb;
     d.pb_nb1 = (int32_t)z.nb1;
     d.pb_nst = (int32_t)z.nst;
+    d.pb_nbatch = (int32_t)z.nbatch;
     d.pb_s1_nparts = (int32_t)z.s1_nparts;
     d.pb_maxch = (int32_t)z.maxch;
     d.pb_nleaf = (int32_t)z.nleaf;
     d.pb_leaf_cap = (int32_t)z.leaf_cap;
+    d.pb_asm_cap = (int32_t)z.asm_cap;
     d.pb_ccap = z.ccap;
     d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
     d.pb_part = (int64_t*)(ws + o.pb_part);

@@ -102,6 +102,8 @@ struct Dev {
   uint8_t* latch;               // [R]
 
   uint32_t* tile_counts;            // [ntiles][TILE_NC] each day's per-tile counts
+  unsigned long long* fin_part;     // [R][fseg][TILE_NC] partial sums of the tile rows
+  int32_t fseg;
   long long* prev_counts;           // [R][ABM_NC]
   long long* traj;                  // [T][R][ABM_NC]
   int32_t* day;
@@ -109,7 +111,8 @@ struct Dev {
 
   // partitioned graph builder (k_build.hip)
   int32_t msg_chunk, msg_grid, msg_ldsmask;   // message-kernel tiling (autotuned or default)
-  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap;
+  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_nbatch, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap,
+      pb_asm_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
   int64_t* pb_part;         // [s1_nparts + 1]
@@ -174,10 +177,14 @@ __device__ __forceinline__ float u01(uint32_t x) {
 }
 
 // Inverse-CDF Poisson count from a 32-bit word: #{k < 63 : T_k <= x}.
+// #{k < 63 : T[k] <= x} for nondecreasing thresholds: the first k with T[k] > x, capped
+// at 63, found in six uniform steps.
 __device__ __forceinline__ int poisson_k(const uint32_t* T, uint32_t x) {
-  int k = 0;
-  while (k < 63 && T[k] <= x) ++k;
-  return k;
+  int lo = 0;
+#pragma unroll
+  for (int h = 32; h > 0; h >>= 1)
+    if (lo + h <= 63 && T[lo + h - 1] <= x) lo += h;
+  return lo;
 }
 
 // ---- kernel launchers (one per translation unit that owns the kernel) ---------------

@@ -2,11 +2,12 @@
 // claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
 // global atomics and without random 4-byte scatters:
 //
-//   P1  gen/hist    per 64-tile super-tile: draw every agent's contacts, keep its own
+//   P1  gen/hist    per batch of 4 tiles: draw every agent's contacts, keep its own
 //                   counts, histogram the partners by level-1 digit (dest >> (LB + 8)).
-//   S1  scan        digit-major exclusive scan of the histograms -> each (super-tile,
-//                   digit) run's offset; level-1 bucket bounds; chunk table.
-//   P2  scatter-1   draw the contacts again, write (dest, src | net) into the runs.
+//   S1  scan        digit-major exclusive scan of the histograms -> each (digit, batch)
+//                   run's offset; level-1 bucket bounds; chunk table.
+//   P2  scatter-1   draw the contacts again, counting-sort the batch's entries
+//                   (dest, src | net) by digit in LDS, write each run contiguously.
 //   P3  hist-2      per chunk of a level-1 bucket: histogram by level-2 digit.
 //   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
 //   P4  scatter-2   entries into leaves of 2^LB destinations.
@@ -16,18 +17,18 @@
 //   row pointers    the prefix scan of k_graph.hip (scan1-3).
 //   P6  assemble    each row: household, own occupation draws, received occupation
 //                   (copied), own random draws, received random (copied).
-// Every run written in P2/P4 is a contiguous block of a few hundred bytes, and every
-// random access of the old builder becomes an LDS access.
+// Every run written in P2/P4 leaves as consecutive lanes on consecutive addresses, and
+// every random access of a per-edge scatter becomes an LDS access.
 #include "abm_internal.h"
 
 namespace abm {
 
-constexpr int PB_ST = 64;              // tiles per super-tile in P1/P2
-constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: 4 tiles in flight
+constexpr int PB_ST = 64;              // tiles per workgroup in P1/P2
+constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles in flight
+constexpr int PB_BT = PB_ST / 4;       // batches per workgroup
+constexpr int PB_S1_CAP = 12288;       // entries of a batch staged in LDS by P2
 constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
-constexpr int PB_ASM_CAP = 8192;       // edges of a tile staged in LDS by the row assembly
-constexpr int PB_S1_PAD = 96 * 1024;   // extra LDS that keeps one P2 workgroup per CU
 
 // Contact generation shared with k_graph.hip (same draws, same order).
 struct Gen {
@@ -35,24 +36,34 @@ struct Gen {
   int base, wp_lo;
   bool rnd;
   uint4 blk;
-  uint32_t blk_id;
   __device__ __forceinline__ int count(const uint32_t* T) {
     if (m < 2) return 0;
     blk = philox(loc, t, stream, purpose << 24, k0, k1);
-    blk_id = 0;
     return poisson_k(T, blk.x);
   }
-  __device__ __forceinline__ int partner(const Dev& d, int q) {
-    const uint32_t b = (uint32_t)q >> 2;
-    if (b != blk_id) {
-      blk = philox(loc, t, stream, (purpose << 24) | b, k0, k1);
-      blk_id = b;
+  // f(q, partner) for q = 1..k in draw order (after count()).  The up-to-four partners
+  // of one Philox block are computed, and their member-list loads issued, together.
+  template <class F>
+  __device__ __forceinline__ void each(const Dev& d, int k, F&& f) {
+    for (int q0 = 0; q0 <= k; q0 += 4) {
+      if (q0 > 0) blk = philox(loc, t, stream, (purpose << 24) | (uint32_t)(q0 >> 2), k0, k1);
+      int p[4];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int q = q0 + l;
+        p[l] = 0;
+        if (q >= 1 && q <= k) {
+          const uint32_t x = lane4(blk, l);
+          const uint32_t off = (uint32_t)(((uint64_t)x * (uint64_t)(m - 1)) >> 32);
+          uint32_t slot = pos + 1 + off;
+          if (slot >= m) slot -= m;
+          p[l] = rnd ? base + (int)slot : d.wp_members[wp_lo + (int)slot];
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        if (q0 + l >= 1 && q0 + l <= k) f(q0 + l, p[l]);
     }
-    const uint32_t x = lane4(blk, q & 3);
-    const uint32_t off = (uint32_t)(((uint64_t)x * (uint64_t)(m - 1)) >> 32);
-    uint32_t slot = pos + 1 + off;
-    if (slot >= m) slot -= m;
-    return rnd ? base + (int)slot : d.wp_members[wp_lo + (int)slot];
   }
 };
 
@@ -74,19 +85,22 @@ __device__ __forceinline__ void load_ptab(const Dev& d, uint32_t* T) {
   for (int i = threadIdx.x; i < NPT * 64; i += TILE) T[i] = d.ptab[i];
 }
 
-// ---- P1: own counts and level-1 histogram per super-tile -----------------------------
-// 1024 lanes = 4 tiles of 256 agents in flight; a super-tile is PB_ST tiles.
+// ---- P1: own counts and level-1 histogram per batch --------------------------------
+// 1024 lanes = one batch of 4 tiles of 256 agents; a workgroup takes PB_BT batches.
+// The histograms are stored digit-major (digit * nbatch + batch), so the scan reads
+// them in order and each digit's PB_BT counts leave as one 64-byte run.
 __global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int hist[PB_THREADS / TILE][PB_NB1_MAX];   // one copy per tile lane group
+  __shared__ int hist[PB_BT][PB_NB1_MAX];
   for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
-  for (int k = threadIdx.x; k < (PB_THREADS / TILE) * PB_NB1_MAX; k += PB_THREADS) (&hist[0][0])[k] = 0;
+  for (int k = threadIdx.x; k < PB_BT * PB_NB1_MAX; k += PB_THREADS) (&hist[0][0])[k] = 0;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
-  int* h = hist[threadIdx.x >> 8];
-  const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
-  for (int tix = blockIdx.x * PB_ST + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
+  const int tile0 = blockIdx.x * PB_ST;
+  const int tile_end = min(d.ntiles, tile0 + PB_ST);
+  for (int tix = tile0 + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
+    int* h = hist[(tix - tile0) >> 2];
     const int4 tl = d.tiles[tix];
     const int i = tl.y + (threadIdx.x & (TILE - 1));
     if (i < tl.z) {
@@ -95,28 +109,29 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
       const uint32_t loc = (uint32_t)(i - ri.start);
       Gen go = gen_occ(d, sr, loc, t, ri.stream);
       const int ko = go.count(T + sr.occ * 64);
-      for (int q = 1; q <= ko; ++q) atomicAdd(&h[go.partner(d, q) >> s1], 1);
+      go.each(d, ko, [&](int, int p) { atomicAdd(&h[p >> s1], 1); });
       Gen gr = gen_rand(d, ri, loc, t);
       const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-      for (int q = 1; q <= kr; ++q) atomicAdd(&h[gr.partner(d, q) >> s1], 1);
+      gr.each(d, kr, [&](int, int p) { atomicAdd(&h[p >> s1], 1); });
       d.own[i] = (uint16_t)(ko | (kr << 8));
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS)
-    d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k] = hist[0][k] + hist[1][k] + hist[2][k] + hist[3][k];
+  const int bt0 = blockIdx.x * PB_BT;
+  const int nb = min(PB_BT, d.pb_nbatch - bt0);
+  for (int k = threadIdx.x; k < d.pb_nb1 * PB_BT; k += PB_THREADS) {
+    const int dg = k / PB_BT, j = k % PB_BT;
+    if (j < nb) d.pb_hist1[(size_t)dg * d.pb_nbatch + bt0 + j] = hist[j][dg];
+  }
 }
 
 // ---- generic three-phase exclusive scan over a virtual index ----------------------------
-// Level-1 order: q = digit * nst + super-tile, element hist1[super-tile][digit].
-__device__ __forceinline__ int* h1_at(const Dev& d, int64_t q) {
-  const int64_t b = q / d.pb_nst, s = q % d.pb_nst;
-  return d.pb_hist1 + s * d.pb_nb1 + b;
-}
+// Level-1 order: q = digit * nbatch + batch, the storage order of hist1.
+__device__ __forceinline__ int* h1_at(const Dev& d, int64_t q) { return d.pb_hist1 + q; }
 
 __global__ __launch_bounds__(TILE) void k_pb_s1a(Dev d) {
   __shared__ int red[TILE / 64];
-  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nst;
+  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nbatch;
   const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
   int s = 0;
   for (int k = 0; k < SCAN_ITEMS; ++k)
@@ -154,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_pb_parts(int64_t* parts, int nparts) {
 
 __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
   __shared__ int wsum[TILE / 64];
-  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nst;
+  const int64_t n = (int64_t)d.pb_nb1 * d.pb_nbatch;
   const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
   int s = 0;
@@ -187,8 +202,8 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
   const int b = threadIdx.x;
   int start = 0, size = 0;
   if (b < d.pb_nb1) {
-    start = d.pb_hist1[b];      // q = b * nst + 0 lives at hist1[0][b]
-    const int64_t end = b + 1 < d.pb_nb1 ? (int64_t)d.pb_hist1[b + 1] : total;
+    start = d.pb_hist1[(size_t)b * d.pb_nbatch];
+    const int64_t end = b + 1 < d.pb_nb1 ? (int64_t)d.pb_hist1[(size_t)(b + 1) * d.pb_nbatch] : total;
     size = (int)(end - start);
     d.pb_bstart[b] = start;
     nch[b] = (size + PB_CHUNK - 1) / PB_CHUNK;
@@ -203,6 +218,7 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
     }
     nch[d.pb_nb1] = c;
     *d.pb_nchunks = c;
+    d.pb_hist1[(size_t)d.pb_nb1 * d.pb_nbatch] = (int)total;   // end of the last run
     d.pb_bstart[d.pb_nb1] = (int)total;
     ok = total <= d.pb_ccap && c <= d.pb_maxch;
     if (!ok) atomicOr(d.flags, FLAG_CAPACITY);
@@ -220,41 +236,85 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 }
 
 // ---- P2: scatter into level-1 runs ---------------------------------------------------
-// One 1024-lane workgroup per CU (the dynamic LDS request keeps it so): the open
-// cache lines of its <= 1024 runs then fit in the XCD's L2, and each run's lines are
-// completed before they are evicted.
+// Per batch: its runs' offsets and sizes come from the scanned histograms; the batch's
+// entries are drawn again and counting-sorted by digit into LDS, then each run leaves
+// as consecutive lanes on consecutive addresses.  A batch with more than PB_S1_CAP
+// entries writes each entry directly to its run.  The order inside a run is
+// immaterial: the leaf sort orders fully.
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int cur[PB_NB1_MAX];
+  __shared__ uint2 stage[PB_S1_CAP];
+  __shared__ int gofs[PB_NB1_MAX], lst[PB_NB1_MAX], lcur[PB_NB1_MAX];
+  __shared__ int wsum[PB_THREADS / 64];
+  __shared__ int nstage;
   if (*d.flags) return;
   for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
-  for (int k = threadIdx.x; k < d.pb_nb1; k += PB_THREADS)
-    cur[k] = d.pb_hist1[(size_t)blockIdx.x * d.pb_nb1 + k];
-  __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
-  const int tile_end = min(d.ntiles, (int)(blockIdx.x + 1) * PB_ST);
-  for (int tix = blockIdx.x * PB_ST + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
-    const int4 tl = d.tiles[tix];
-    const int i = tl.y + (threadIdx.x & (TILE - 1));
-    if (i < tl.z) {
-      const RepInfo& ri = d.rep[tl.x];
-      const StaticRec sr = d.srec[i];
-      const uint32_t loc = (uint32_t)(i - ri.start);
-      Gen go = gen_occ(d, sr, loc, t, ri.stream);
-      const int ko = go.count(T + sr.occ * 64);
-      for (int q = 1; q <= ko; ++q) {
-        const int p = go.partner(d, q);
-        const int pos = atomicAdd(&cur[p >> s1], 1);
-        d.pb_buf1[pos] = make_uint2((uint32_t)p, (uint32_t)i);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nbt = d.pb_nbatch;
+  for (int j = 0; j < PB_BT; ++j) {
+    const int bt = blockIdx.x * PB_BT + j;
+    if (bt >= nbt) break;
+    int cntv = 0;
+    if (tid < d.pb_nb1) {
+      const size_t q = (size_t)tid * nbt + bt;
+      const int o = d.pb_hist1[q];
+      gofs[tid] = o;
+      cntv = d.pb_hist1[q + 1] - o;
+    }
+    int inc = cntv;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    if (tid < d.pb_nb1) {
+      lst[tid] = wb + inc - cntv;
+      lcur[tid] = wb + inc - cntv;
+    }
+    if (tid == PB_THREADS - 1) nstage = wb + inc;
+    __syncthreads();
+    const bool staged = nstage <= PB_S1_CAP;
+    const int tix = bt * 4 + (tid >> 8);
+    if (tix < d.ntiles) {
+      const int4 tl = d.tiles[tix];
+      const int i = tl.y + (tid & (TILE - 1));
+      if (i < tl.z) {
+        const RepInfo& ri = d.rep[tl.x];
+        const StaticRec sr = d.srec[i];
+        const uint32_t loc = (uint32_t)(i - ri.start);
+        Gen go = gen_occ(d, sr, loc, t, ri.stream);
+        const int ko = go.count(T + sr.occ * 64);
+        go.each(d, ko, [&](int, int p) {
+          const int dg = p >> s1;
+          const int slot = atomicAdd(&lcur[dg], 1);
+          const uint2 x = make_uint2((uint32_t)p, (uint32_t)i);
+          if (staged) stage[slot] = x;
+          else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+        });
+        Gen gr = gen_rand(d, ri, loc, t);
+        const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+        gr.each(d, kr, [&](int, int p) {
+          const int dg = p >> s1;
+          const int slot = atomicAdd(&lcur[dg], 1);
+          const uint2 x = make_uint2((uint32_t)p, (uint32_t)i | 0x80000000u);
+          if (staged) stage[slot] = x;
+          else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+        });
       }
-      Gen gr = gen_rand(d, ri, loc, t);
-      const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-      for (int q = 1; q <= kr; ++q) {
-        const int p = gr.partner(d, q);
-        const int pos = atomicAdd(&cur[p >> s1], 1);
-        d.pb_buf1[pos] = make_uint2((uint32_t)p, (uint32_t)i | 0x80000000u);
+    }
+    __syncthreads();
+    if (staged) {
+      for (int k = tid; k < nstage; k += PB_THREADS) {
+        const uint2 x = stage[k];
+        const int dg = (int)(x.x >> s1);
+        d.pb_buf1[gofs[dg] + k - lst[dg]] = x;
       }
+      __syncthreads();
     }
   }
 }
@@ -314,65 +374,80 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
 }
 
 // ---- P4: scatter into leaves ---------------------------------------------------------
-// The chunk is counting-sorted by leaf digit in LDS first, so each leaf's part of the
-// chunk leaves as one contiguous run of consecutive lanes.
-__global__ __launch_bounds__(TILE) void k_pb_scatter2(Dev d) {
+// The chunk is read once into registers (PB_S2_PER entries a lane), counting-sorted by
+// leaf digit in LDS, and each leaf's part of the chunk leaves as one contiguous run of
+// consecutive lanes.  The order inside a run is immaterial: the leaf sort orders fully.
+constexpr int PB_S2_THREADS = 1024;
+constexpr int PB_S2_PER = PB_CHUNK / PB_S2_THREADS;
+__global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
   __shared__ uint2 sorted[PB_CHUNK];
-  __shared__ int cnt[256], first[256], cur[256];
-  __shared__ int wsum[TILE / 64];
+  __shared__ int cnt[256], first[256];
+  __shared__ int wsum[4];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
   const int4 ch = d.pb_chunks[c];
   const int n = ch.z - ch.y;
-  cnt[threadIdx.x] = 0;
+  const int tid = threadIdx.x;
+  if (tid < 256) cnt[tid] = 0;
   __syncthreads();
-  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE)
-    atomicAdd(&cnt[(d.pb_buf1[e].x >> d.pb_lb) & 255u], 1);
+  uint2 x[PB_S2_PER];
+  int rank[PB_S2_PER];
+#pragma unroll
+  for (int j = 0; j < PB_S2_PER; ++j) {
+    const int k = j * PB_S2_THREADS + tid;
+    x[j] = k < n ? d.pb_buf1[ch.y + k] : make_uint2(0u, 0u);
+  }
+#pragma unroll
+  for (int j = 0; j < PB_S2_PER; ++j) {
+    const int k = j * PB_S2_THREADS + tid;
+    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d.pb_lb) & 255u], 1) : 0;
+  }
   __syncthreads();
-  const int v = cnt[threadIdx.x];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int v = tid < 256 ? cnt[tid] : 0;
   int inc = v;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
+    if ((tid & 63) >= o) inc += y;
   }
-  if (lane == 63) wsum[wv] = inc;
+  if (tid < 256 && (tid & 63) == 63) wsum[tid >> 6] = inc;
   __syncthreads();
-  int wb = 0;
-  for (int q = 0; q < wv; ++q) wb += wsum[q];
-  first[threadIdx.x] = wb + inc - v;
-  cur[threadIdx.x] = wb + inc - v;
+  if (tid < 256) {
+    int wb = 0;
+    for (int q = 0; q < (tid >> 6); ++q) wb += wsum[q];
+    first[tid] = wb + inc - v;
+  }
   __syncthreads();
-  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE) {
-    const uint2 x = d.pb_buf1[e];
-    sorted[atomicAdd(&cur[(x.x >> d.pb_lb) & 255u], 1)] = x;
+#pragma unroll
+  for (int j = 0; j < PB_S2_PER; ++j) {
+    const int k = j * PB_S2_THREADS + tid;
+    if (k < n) sorted[first[(x[j].x >> d.pb_lb) & 255u] + rank[j]] = x[j];
   }
   __syncthreads();
   const int* off = d.pb_hist2 + (size_t)c * 256;
-  for (int k = threadIdx.x; k < n; k += TILE) {
-    const uint2 x = sorted[k];
-    const int dg = (x.x >> d.pb_lb) & 255u;
-    d.pb_buf2[off[dg] + (k - first[dg])] = x;
+  for (int k = tid; k < n; k += PB_S2_THREADS) {
+    const uint2 y = sorted[k];
+    const int dg = (y.x >> d.pb_lb) & 255u;
+    d.pb_buf2[off[dg] + (k - first[dg])] = y;
   }
 }
 
 // ---- P5: per leaf, sort by (destination, network, initiator) in LDS ------------------
+// The LDS holds pb_leaf_cap entries.  A larger leaf is sorted in groups of whole keys
+// that each fit, the leaf's entries being read once more per extra group; only a
+// single (destination, network) run longer than the cap is an error.
 __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
   extern __shared__ uint32_t lds[];
   if (*d.flags) return;
   const int L = blockIdx.x;
   const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
   const int n = hi - lo;
-  if (n > d.pb_leaf_cap) {
-    if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
-    return;
-  }
+  const int cap = d.pb_leaf_cap;
   const int nkeys = 2 << d.pb_lb;             // (destination offset, network)
-  uint32_t* sorted = lds;                     // [leaf_cap]
-  int* cnt = (int*)(lds + d.pb_leaf_cap);     // [nkeys + 1]
+  uint32_t* sorted = lds;                     // [cap]
+  int* cnt = (int*)(lds + cap);               // [nkeys + 1]
   __shared__ int wsum[TILE / 64];
-  __shared__ int carry;
+  __shared__ int carry, grp_end;
   for (int k = threadIdx.x; k <= nkeys; k += TILE) cnt[k] = 0;
   __syncthreads();
   const uint32_t dmask = (1u << d.pb_lb) - 1u;
@@ -416,41 +491,64 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
   }
   if (threadIdx.x == 0) cnt[nkeys] = n;
   __syncthreads();
-  // key runs are [cnt[k], cnt[k+1]); place with a cursor copy kept in the key's slot
-  // of a second pass: use atomics on a shifted copy, then restore starts from the runs.
-  for (int e = lo + threadIdx.x; e < hi; e += TILE) {
-    const uint2 v = d.pb_buf2[e];
-    const int k = ((v.x & dmask) << 1) | (v.y >> 31);
-    const int pos = atomicAdd(&cnt[k], 1);
-    sorted[pos] = v.y & 0x7FFFFFFFu;
-  }
-  __syncthreads();
-  // after placement cnt[k] = end of run k = start of run k+1; run k is [cnt[k-1], cnt[k])
-  for (int k = threadIdx.x; k < nkeys; k += TILE) {
-    const int a = k ? cnt[k - 1] : 0, b = cnt[k];
-    for (int x = a + 1; x < b; ++x) {
-      const uint32_t v = sorted[x];
-      int y = x - 1;
-      while (y >= a && sorted[y] > v) {
-        sorted[y + 1] = sorted[y];
-        --y;
+  // cnt[k] is the start of run k; placing run k's entries advances cnt[k] to its end,
+  // which is the start of run k + 1, so after a group run k is [cnt[k-1], cnt[k]).
+  for (int ka = 0; ka < nkeys;) {
+    const int o_lo = cnt[ka];
+    if (threadIdx.x == 0) {
+      int a = ka, b = nkeys;                  // largest kb with cnt[kb] - o_lo <= cap
+      while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (cnt[m] - o_lo <= cap) a = m; else b = m - 1;
       }
-      sorted[y + 1] = v;
+      grp_end = a;
     }
+    __syncthreads();
+    const int kb = grp_end;
+    if (kb == ka) {                           // one run longer than the LDS
+      if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
+      return;
+    }
+    const int o_hi = cnt[kb];
+    __syncthreads();                          // everyone has read cnt[kb] before placement
+    for (int e = lo + threadIdx.x; e < hi; e += TILE) {
+      const uint2 v = d.pb_buf2[e];
+      const int k = ((v.x & dmask) << 1) | (v.y >> 31);
+      if (k >= ka && k < kb) sorted[atomicAdd(&cnt[k], 1) - o_lo] = v.y & 0x7FFFFFFFu;
+    }
+    __syncthreads();
+    for (int k = ka + threadIdx.x; k < kb; k += TILE) {
+      const int a = (k > ka ? cnt[k - 1] : o_lo) - o_lo, b = cnt[k] - o_lo;
+      for (int x = a + 1; x < b; ++x) {
+        const uint32_t v = sorted[x];
+        int y = x - 1;
+        while (y >= a && sorted[y] > v) {
+          sorted[y + 1] = sorted[y];
+          --y;
+        }
+        sorted[y + 1] = v;
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < o_hi - o_lo; k += TILE) d.pb_rsrc[lo + o_lo + k] = sorted[k];
+    __syncthreads();
+    ka = kb;
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < n; k += TILE) d.pb_rsrc[lo + k] = sorted[k];
 }
 
 // ---- P6: assemble each row --------------------------------------------------------
-// Rows of a tile are contiguous in the CSR; each lane fills its row in LDS (source id
-// and network), then the tile's edge range is written with consecutive lanes on
-// consecutive addresses.  A tile with more than PB_ASM_CAP edges writes directly.
-__device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* scol, uint8_t* snet,
-                                         int base, int pos, int src, int net) {
+// Rows of a tile are contiguous in the CSR.  Each lane lays out its row (household,
+// own occupation draws, received occupation, own random draws, received random) and
+// fills the parts it generates itself; the received parts of all the tile's rows are
+// one contiguous range of the sorted received lists, copied by all lanes together with
+// consecutive lanes on consecutive entries.  The row is staged in LDS (source id with
+// the network in the top two bits) and the tile's edge range is written with
+// consecutive lanes on consecutive addresses.  A tile with more edges than the LDS
+// room writes directly.
+__device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* scol, int base, int pos,
+                                         int src, int net) {
   if (staged) {
-    scol[pos - base] = src;
-    snet[pos - base] = (uint8_t)net;
+    scol[pos - base] = src | (net << 30);
   } else {
     d.col[pos] = src;
     d.w[pos] = net == 0 ? d.w_h : (net == 1 ? d.w_o : d.w_r);
@@ -458,15 +556,13 @@ __device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* sco
 }
 
 __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
-  __shared__ uint32_t T[NPT * 64];
-  __shared__ int32_t scol[PB_ASM_CAP];
-  __shared__ uint8_t snet[PB_ASM_CAP];
-  load_ptab(d, T);
-  __syncthreads();
+  extern __shared__ int32_t scol[];                  // [pb_asm_cap]
+  __shared__ int rsl[TILE], rol[TILE], pol[TILE], prl[TILE];
+  __shared__ int gend;
   if (*d.flags) return;
   const int4 tl = d.tiles[blockIdx.x];
   const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
-  const bool staged = end - base <= PB_ASM_CAP;
+  const bool staged = end - base <= d.pb_asm_cap;
   const int i = tl.y + threadIdx.x;
   if (i < tl.z) {
     const RepInfo& ri = d.rep[tl.x];
@@ -475,26 +571,44 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     const uint32_t loc = (uint32_t)(i - ri.start);
     const uint32_t r = d.recv[i];
     const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
+    const int rs = d.pb_rstart[i];
     int pos = d.row_ptr[i];
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
-      if (m != i) put_edge(d, staged, scol, snet, base, pos++, m, 0);
+      if (m != i) put_edge(d, staged, scol, base, pos++, m, 0);
     Gen go = gen_occ(d, sr, loc, t, ri.stream);
-    const int ko = go.count(T + sr.occ * 64);
-    for (int q = 1; q <= ko; ++q) put_edge(d, staged, scol, snet, base, pos++, go.partner(d, q), 1);
-    const int rs = d.pb_rstart[i];
-    for (int q = 0; q < ro; ++q) put_edge(d, staged, scol, snet, base, pos++, (int)d.pb_rsrc[rs + q], 1);
+    const int ko = go.count(d.ptab + sr.occ * 64);
+    go.each(d, ko, [&](int, int p) { put_edge(d, staged, scol, base, pos++, p, 1); });
+    pol[threadIdx.x] = pos;
+    pos += ro;
     Gen gr = gen_rand(d, ri, loc, t);
-    const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-    for (int q = 1; q <= kr; ++q) put_edge(d, staged, scol, snet, base, pos++, gr.partner(d, q), 2);
-    for (int q = 0; q < rr; ++q)
-      put_edge(d, staged, scol, snet, base, pos++, (int)d.pb_rsrc[rs + ro + q], 2);
+    const int kr = gr.count(d.ptab + (PT_AGE0 + sr.age) * 64);
+    gr.each(d, kr, [&](int, int p) { put_edge(d, staged, scol, base, pos++, p, 2); });
+    prl[threadIdx.x] = pos;
+    rsl[threadIdx.x] = rs;
+    rol[threadIdx.x] = ro;
+    if (i == tl.z - 1) gend = rs + ro + rr;
+  }
+  __syncthreads();
+  const int nlive = tl.z - tl.y;
+  const int g0 = rsl[0], g1 = gend;
+  for (int g = g0 + threadIdx.x; g < g1; g += TILE) {
+    const int src = (int)d.pb_rsrc[g];
+    int lo = 0, hi = nlive;                          // last row j with rsl[j] <= g
+    while (hi - lo > 1) {
+      const int m = (lo + hi) >> 1;
+      if (rsl[m] <= g) lo = m; else hi = m;
+    }
+    const int off = g - rsl[lo];
+    if (off < rol[lo]) put_edge(d, staged, scol, base, pol[lo] + off, src, 1);
+    else put_edge(d, staged, scol, base, prl[lo] + off - rol[lo], src, 2);
   }
   if (!staged) return;
   __syncthreads();
   const float wt[3] = {d.w_h, d.w_o, d.w_r};
   for (int k = threadIdx.x; k < end - base; k += TILE) {
-    d.col[base + k] = scol[k];
-    d.w[base + k] = wt[snet[k]];
+    const uint32_t v = (uint32_t)scol[k];
+    d.col[base + k] = (int32_t)(v & 0x3FFFFFFFu);
+    d.w[base + k] = wt[v >> 30];
   }
 }
 
@@ -515,9 +629,7 @@ hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)leaf_lds(d));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pb_scatter1, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             PB_S1_PAD);
+  return e;
 }
 
 void launch_build_step(const Dev& d, int k, hipStream_t s) {
@@ -539,15 +651,15 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_pb_s1c, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_buckets, dim3(1), dim3(1024), 0, s, d);
       break;
-    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(PB_THREADS), PB_S1_PAD, s, d); break;
+    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(PB_THREADS), 0, s, d); break;
     case 3:
       hipLaunchKernelGGL(k_pb_hist2, dim3(d.pb_maxch), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
       break;
-    case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(TILE), 0, s, d); break;
+    case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
     case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(TILE), leaf_lds(d), s, d); break;
     case 6: launch_scan(d, s); break;
-    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), 0, s, d); break;
+    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 4, s, d); break;
   }
 }
 

@@ -229,14 +229,21 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 // be one workgroup per tile or a persistent grid striding over the tiles).
 template <int CHUNK, bool LDSMASK>
 __global__ __launch_bounds__(TILE) void k_message(Dev d) {
+  // U edges per lane are loaded before any of them is used, so each lane keeps U
+  // independent HBM loads, then U independent mask lookups, in flight.
+  constexpr int U = CHUNK / TILE < 8 ? CHUNK / TILE : 8;
+  constexpr int NW = CHUNK / 32;
   extern __shared__ unsigned long long scm[];        // super-coarse mask (LDSMASK)
   __shared__ float atab[ATAB];
-  __shared__ float term[CHUNK];
+  __shared__ float term[CHUNK];                      // written only where the source is infectious
+  __shared__ uint32_t nzb[2][NW];                    // which terms of the chunk are written
   __shared__ uint32_t ninf[TILE / 64];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
   if (LDSMASK)
     for (int q = threadIdx.x; q < d.nsc; q += TILE) scm[q] = d.scmask[q];
+  for (int q = threadIdx.x; q < 2 * NW; q += TILE) (&nzb[0][0])[q] = 0u;
+  int par = 0;
   for (int tix = blockIdx.x; tix < d.ntiles; tix += gridDim.x) {
     const int4 tl = d.tiles[tix];
     const int i = tl.y + threadIdx.x;
@@ -246,25 +253,57 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
     float sum = 0.f;
     uint32_t infected_edges = 0;
     __syncthreads();
-    for (int c0 = e0; c0 < e1; c0 += CHUNK) {
+    for (int c0 = e0; c0 < e1; c0 += CHUNK, par ^= 1) {
       const int cn = min(CHUNK, e1 - c0);
-      for (int k = threadIdx.x; k < cn; k += TILE) {
-        const int e = c0 + k;
-        uint32_t src = (uint32_t)__builtin_nontemporal_load(d.col + e);
-        src = src < (uint32_t)d.N ? src : 0u;
-        bool inf = LDSMASK ? ((scm[src >> 14] >> ((src >> 8) & 63u)) & 1ull) != 0 : true;
-        inf = inf && ((d.cmask[src >> 8] >> ((src >> 3) & 31u)) & 1u) &&
-              ((d.imask[src >> 5] >> (src & 31u)) & 1u);
-        float v = 0.f;
-        if (inf) {
-          v = __builtin_nontemporal_load(d.w + e) * atab[d.code[src]];
-          ++infected_edges;
+      uint32_t* nz = nzb[par];
+      for (int kb = 0; kb < cn; kb += TILE * U) {
+        uint32_t src[U];
+        bool hit[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = kb + u * TILE + (int)threadIdx.x;
+          hit[u] = k < cn;
+          src[u] = hit[u] ? (uint32_t)__builtin_nontemporal_load(d.col + c0 + k) : 0u;
+          src[u] = src[u] < (uint32_t)d.N ? src[u] : 0u;
         }
-        term[k] = v;
+        if (LDSMASK) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            hit[u] = hit[u] && ((scm[src[u] >> 14] >> ((src[u] >> 8) & 63u)) & 1ull);
+        }
+        uint32_t cw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cw[u] = hit[u] ? d.cmask[src[u] >> 8] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) hit[u] = (cw[u] >> ((src[u] >> 3) & 31u)) & 1u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) cw[u] = hit[u] ? d.imask[src[u] >> 5] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if ((cw[u] >> (src[u] & 31u)) & 1u) {
+            const int k = kb + u * TILE + (int)threadIdx.x;
+            term[k] = __builtin_nontemporal_load(d.w + c0 + k) * atab[d.code[src[u]]];
+            atomicOr(&nz[k >> 5], 1u << (k & 31));
+            ++infected_edges;
+          }
+        }
       }
       __syncthreads();
-      const int lo = max(rs, c0), hi = min(re, c0 + cn);
-      for (int e = lo; e < hi; ++e) sum += term[e - c0];
+      // Each row adds its written terms left to right.  Unwritten terms are +0 and
+      // every term is >= 0, so skipping them leaves the left-to-right sum unchanged.
+      const int lo = max(rs, c0) - c0, hi = min(re, c0 + cn) - c0;
+      for (int wd = lo >> 5; lo < hi && wd <= (hi - 1) >> 5; ++wd) {
+        uint32_t bits = nz[wd];
+        const int b0 = wd << 5;
+        if (lo > b0) bits &= ~0u << (lo - b0);
+        if (hi < b0 + 32) bits &= (1u << (hi - b0)) - 1u;
+        while (bits) {
+          sum += term[b0 + __builtin_ctz(bits)];
+          bits &= bits - 1u;
+        }
+      }
+      // the other buffer was last read before the previous barrier
+      for (int q = threadIdx.x; q < NW; q += TILE) nzb[par ^ 1][q] = 0u;
       __syncthreads();
     }
     if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
@@ -370,20 +409,21 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
 }
 
 // ---- end of day: tile counts -> per-replicate counts -> trajectory ----------------
-// One workgroup per replicate sums its tiles' rows in a fixed order.
-__global__ __launch_bounds__(1024) void k_finalize(Dev d) {
-  __shared__ unsigned long long part[1024 / 64][ABM_NC];
-  const int r = blockIdx.x;
+// Integer sums, so the grouping does not change them.  Part (s, r) sums every fseg-th
+// block of 256 tile rows of replicate r; one lane per count then adds the parts.
+__global__ __launch_bounds__(TILE) void k_fin_part(Dev d) {
+  __shared__ unsigned long long part[TILE / 64][ABM_NC];
+  const int s = blockIdx.x, r = blockIdx.y;
   const RepInfo& ri = d.rep[r];
-  const int t = *d.day;
-  const bool ok = *d.flags == 0;
   unsigned long long acc[ABM_NC];
 #pragma unroll
   for (int c = 0; c < ABM_NC; ++c) acc[c] = 0ull;
-  for (int k = threadIdx.x; k < ri.ntiles; k += 1024) {
-    const uint32_t* row = d.tile_counts + (size_t)(ri.tile0 + k) * TILE_NC;
+  for (int k = s * TILE + threadIdx.x; k < ri.ntiles; k += d.fseg * TILE) {
+    const uint4* row = (const uint4*)(d.tile_counts + (size_t)(ri.tile0 + k) * TILE_NC);
+    const uint4 a = row[0], b = row[1], c = row[2], e = row[3];
+    const uint32_t v[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x, e.y, e.z, e.w};
 #pragma unroll
-    for (int c = 0; c < ABM_NC; ++c) acc[c] += row[c];
+    for (int q = 0; q < ABM_NC; ++q) acc[q] += v[q];
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -395,8 +435,19 @@ __global__ __launch_bounds__(1024) void k_finalize(Dev d) {
   __syncthreads();
   if (threadIdx.x < ABM_NC) {
     const int c = threadIdx.x;
+    d.fin_part[((size_t)r * d.fseg + s) * TILE_NC + c] = part[0][c] + part[1][c] + part[2][c] + part[3][c];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_finalize(Dev d) {
+  const int r = blockIdx.x;
+  const RepInfo& ri = d.rep[r];
+  const int t = *d.day;
+  const bool ok = *d.flags == 0;
+  if (threadIdx.x < ABM_NC) {
+    const int c = threadIdx.x;
     long long v = 0;
-    for (int q = 0; q < 1024 / 64; ++q) v += (long long)part[q][c];
+    for (int q = 0; q < d.fseg; ++q) v += (long long)d.fin_part[((size_t)r * d.fseg + q) * TILE_NC + c];
     if (c == ABM_C_EDGES) v = ok ? (long long)d.row_ptr[ri.start + ri.n] - d.row_ptr[ri.start] : 0;
     if (c == ABM_C_INF_EDGES && !ok) v = 0;
     if (t < d.T) d.traj[((size_t)t * d.R + r) * ABM_NC + c] = v;
@@ -505,7 +556,8 @@ void launch_fused(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
 void launch_finalize(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(d.R), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_fin_part, dim3(d.fseg, d.R), dim3(TILE), 0, s, d);
+  hipLaunchKernelGGL(k_finalize, dim3(d.R), dim3(64), 0, s, d);
   hipLaunchKernelGGL(k_advance_day, dim3(1), dim3(1), 0, s, d);
 }
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s) {

@@ -26,16 +26,20 @@ class Simulator:
     the arrays of abm_population.  ``profile`` times every kernel with HIP events;
     ``graph=False`` launches the day's kernels eagerly instead of replaying a HIP graph;
     ``claim_builder`` selects the per-edge atomic-claim graph builder; ``autotune`` times
-    the force-of-infection kernel's tilings at create and keeps the fastest.
+    the force-of-infection kernel's tilings at create and keeps the fastest;
+    ``min_lds_room`` (a test aid) gives the graph builder's leaf sort and row assembly
+    their smallest LDS room, which exercises their multi-group and direct-write paths.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
-                 claim_builder: bool = False, autotune: bool = False, stream=None):
+                 claim_builder: bool = False, autotune: bool = False, min_lds_room: bool = False,
+                 stream=None):
         torch = _torch()
         self._lib = L.lib()
         flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
                  | (L.FLAG_CLAIM_BUILDER if claim_builder else 0)
-                 | (L.FLAG_AUTOTUNE if autotune else 0))
+                 | (L.FLAG_AUTOTUNE if autotune else 0)
+                 | (L.FLAG_MIN_LDS_ROOM if min_lds_room else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)

@@ -1,7 +1,14 @@
 """Full-size check at 50 million agents in the configuration the benchmark times
-(partitioned builder, autotuned tiling): sampled rows of day 0's contact graph and
-their force of infection, computed one by one by the oracle, against the GPU, plus
-properties that hold at any size."""
+(partitioned builder, autotuned tiling).
+
+Sampled rows of day 0's contact graph are checked against contacts the oracle draws
+one initiator at a time: the household part and the row's own draws exactly; the
+received workplace contacts exactly (they come from the few members of the row's
+workplace); every received random contact is a real draw of its initiator, with its
+multiplicity, and every infectious agent's draws into the row are present.  The force
+of infection of those rows (eq. 1) then follows from the oracle's infectiousness codes,
+since only infectious sources contribute.  Properties that hold at any size cover the
+rest."""
 import numpy as np
 import pytest
 
@@ -13,56 +20,42 @@ from synthpop import workload
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_rows(pop, p, t, sample, maps):
-    """Canonical rows of the sampled destinations: household members, own draws, and
-    the draws of every initiator whose partner is a sampled agent (scanned in chunks)."""
-    N = pop.n_agents
-    want = np.zeros(N, bool)
-    want[sample] = True
-    own = og.daily_draws(pop, p, t, maps, agents=sample)
-    recv = {"occ": [], "rand": []}
-    step = 4_000_000
-    for a0 in range(0, N, step):
-        dr = og.daily_draws(pop, p, t, maps, agents=np.arange(a0, min(N, a0 + step)))
-        for net in ("occ", "rand"):
-            hit = want[dr[net]["partner"]]
-            recv[net].append(np.stack([dr[net]["partner"][hit], dr[net]["init"][hit],
-                                       dr[net]["draw"][hit]], 1))
-    recv = {k: np.concatenate(v) for k, v in recv.items()}
-    rows = {}
-    for j in sample:
-        row = [m for m in range(int(maps["hh_lo"][j]), int(maps["hh_hi"][j])) if m != j]
-        w = [p["w_household"]] * len(row)
-        for net, wn in (("occ", p["w_occupation"]), ("rand", p["w_random"])):
-            o = own[net]
-            sel = o["init"] == j
-            mine = o["partner"][sel][np.argsort(o["draw"][sel], kind="stable")]
-            r = recv[net]
-            r = r[r[:, 0] == j]
-            r = r[np.lexsort((r[:, 2], r[:, 1]))][:, 1]
-            row += list(mine) + list(r)
-            w += [wn] * (len(mine) + len(r))
-        rows[int(j)] = (np.array(row, np.int64), np.array(w, np.float64))
-    return rows
+def _log(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+def _by_initiator(dr, net):
+    """{initiator: partners in draw order} for one network of a daily_draws result."""
+    x = dr[net]
+    o = np.lexsort((x["draw"], x["init"]))
+    out = {}
+    for i, p in zip(x["init"][o].tolist(), x["partner"][o].tolist()):
+        out.setdefault(i, []).append(p)
+    return out
 
 
 def test_fifty_million_agents_sampled_rows_and_lambda():
     require_gpu()
     from paper_2110_04421_amd.sim import Simulator
     p, pop = workload(2, n_steps=2)
+    _log("population built")
     maps = og.static_maps(pop)
+    _log("static maps built")
+    N = pop.n_agents
+    seeds = np.unique(np.asarray(pop.initial_infected, np.int64))
+    sd = og.daily_draws(pop, p, 0, maps, agents=seeds)
     rng = np.random.default_rng(99)
-    seeds = np.asarray(pop.initial_infected, np.int64)
-    # rows next to an initial infection (nonzero force of infection) plus random rows
-    near = np.unique(np.concatenate([np.arange(maps["hh_lo"][s], maps["hh_hi"][s]) for s in seeds[:300]]))
-    sample = np.unique(np.concatenate([near[:600], rng.choice(pop.n_agents, 600, replace=False)]))
+    near = np.unique(np.concatenate([np.arange(maps["hh_lo"][s], maps["hh_hi"][s]) for s in seeds[:200]]))
+    hit = np.unique(np.concatenate([sd["occ"]["partner"][:300], sd["rand"]["partner"][:300]]))
+    sample = np.unique(np.concatenate([near[:400], hit, rng.choice(N, 600, replace=False)]))
     with Simulator(p, pop, autotune=True) as s:
         counts = s.run(1)
         rp, col, w = s.csr()
         lam = s.lam()
-    N = pop.n_agents
+    _log(f"GPU day done, {sample.size} sampled rows")
+    rp = rp.astype(np.int64)
     E = int(rp[-1])
-    # any-size properties: degrees consistent, edge total near its mean
+    # any-size properties: edge total, household pairs, symmetric contact count
     assert counts[0, 0, ostep.C_EDGES] == E
     hh = np.diff(np.asarray(pop.hh_start, np.int64))
     e_hh = int((hh * (hh - 1)).sum())
@@ -70,16 +63,61 @@ def test_fifty_million_agents_sampled_rows_and_lambda():
     mean_c = N * (4.0 + 13.84) / 2
     assert abs((E - e_hh) / 2 - mean_c) < 6 * np.sqrt(mean_c)
     assert col.min() >= 0 and col.max() < N
-    # sampled rows, exactly
-    rows = _oracle_rows(pop, p, 0, sample, maps)
-    for j, (rc, rw) in rows.items():
+
+    own = og.daily_draws(pop, p, 0, maps, agents=sample)
+    own_o, own_r = _by_initiator(own, "occ"), _by_initiator(own, "rand")
+    # workplace members of the sampled rows: their draws give the received occupation part
+    wp_lo, wp_n = maps["wp_lo"][sample], maps["wp_size"][sample]
+    mem = np.asarray(pop.wp_members, np.int64)
+    cow = np.unique(np.concatenate([mem[a:a + n] for a, n in zip(wp_lo.tolist(), wp_n.tolist())] + [seeds[:0]]))
+    cd = og.daily_draws(pop, p, 0, maps, agents=cow)
+    recv_o = {}
+    for i, q in zip(cd["occ"]["init"].tolist(), cd["occ"]["partner"].tolist()):
+        recv_o.setdefault(q, []).append(i)
+    seed_r = {}
+    for i, q in zip(sd["rand"]["init"].tolist(), sd["rand"]["partner"].tolist()):
+        seed_r.setdefault(q, []).append(i)
+    _log("oracle draws of sampled rows, workplaces and seeds done")
+
+    rows = {}
+    rand_init = []
+    for j in sample.tolist():
         g = col[rp[j]:rp[j + 1]].astype(np.int64)
-        assert np.array_equal(g, rc), j
-        assert np.array_equal(w[rp[j]:rp[j + 1]], rw.astype(np.float32)), j
-    # force of infection of the sampled rows (eq. 1) from the oracle's day-0 state
+        gw = w[rp[j]:rp[j + 1]]
+        hpart = [m for m in range(int(maps["hh_lo"][j]), int(maps["hh_hi"][j])) if m != j]
+        oo, orr = own_o.get(j, []), own_r.get(j, [])
+        ro = sorted(recv_o.get(j, []))
+        head = hpart + oo + ro + orr
+        assert g.size >= len(head), j
+        assert np.array_equal(g[:len(head)], np.array(head, np.int64)), j
+        rr = g[len(head):]
+        assert np.all(np.diff(rr) >= 0), j                       # sorted by initiator
+        wexp = ([p["w_household"]] * len(hpart) + [p["w_occupation"]] * (len(oo) + len(ro))
+                + [p["w_random"]] * (len(orr) + rr.size))
+        assert np.array_equal(gw, np.array(wexp, np.float32)), j
+        # every infectious agent's random draws into row j are there
+        sr = sorted(seed_r.get(j, []))
+        u, c = np.unique(rr, return_counts=True)
+        have = dict(zip(u.tolist(), c.tolist()))
+        for i in set(sr):
+            assert have.get(i, 0) == sr.count(i), (j, i)
+        rows[j] = (g, np.asarray(wexp, np.float64))
+        rand_init.append(rr)
+    # every received random contact is a real draw of its initiator, with multiplicity
+    ri = np.unique(np.concatenate(rand_init))
+    rd = _by_initiator(og.daily_draws(pop, p, 0, maps, agents=ri), "rand")
+    for j, (g, _) in rows.items():
+        nh = len([m for m in range(int(maps["hh_lo"][j]), int(maps["hh_hi"][j])) if m != j])
+        start = nh + len(own_o.get(j, [])) + len(recv_o.get(j, [])) + len(own_r.get(j, []))
+        u, c = np.unique(g[start:], return_counts=True)
+        for i, k in zip(u.tolist(), c.tolist()):
+            assert rd.get(i, []).count(j) == k, (j, i)
+    _log("sampled rows verified")
+    # force of infection of the sampled rows from the oracle's day-0 codes
     m = ostep.Model(pop, p)
     code = m.codes(m.init_state(), 0)
-    lam_o = np.array([m.coef[j] * (rows[j][1] * m.Atab[code[rows[j][0]]]).sum() for j in sample])
+    lam_o = np.array([m.coef[j] * (rows[j][1] * m.Atab[code[rows[j][0]]]).sum() for j in sample.tolist()])
     ok, err = lam_close(lam[sample], lam_o)
     assert ok, err
     assert (lam_o > 0).sum() > 100
+    _log(f"lambda of {sample.size} rows within tolerance (worst {err:.2e})")

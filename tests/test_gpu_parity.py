@@ -208,6 +208,22 @@ def test_csr_bit_exact_several_level1_buckets():
     assert np.array_equal(w, w_o.astype(np.float32))
 
 
+def test_builder_small_lds_room_builds_the_same_graph():
+    # leaves sorted in several groups and tiles assembled by direct writes
+    p, pop = workload(3, n=60000, n_rep=5, n_steps=4)
+    outs = []
+    for small in (False, True):
+        with _sim(p, pop, min_lds_room=small) as s:
+            c = s.run(3)
+            outs.append((c, s.csr(), s.state()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[0][2], outs[1][2])
+    rp_o, col_o, w_o, _ = og.build_graph(pop, p, 2)
+    assert np.array_equal(outs[1][1][1].astype(np.int64), col_o)
+
+
 def test_autotuned_tiling_gives_identical_results():
     p, pop = workload(3, n=50000, n_rep=6, n_steps=12, vacc_trigger=0.001)
     outs = []
