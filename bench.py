@@ -62,14 +62,15 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         # edge; row_ptr, age, lambda per row
         "message": 4.125 * E + 5.0 * Einf + 9.0 * N,
         # partitioned builder
-        "pb_hist1": 18.0 * N + 4.0 * nbt * nb1,    # static record in, own counts + histograms out
+        # draws: static record in; counts, own list and histograms out
+        "pb_gen": 18.0 * N + 4.0 * C + 4.0 * nbt * nb1,
         "pb_scan1": 12.0 * nbt * nb1,              # histograms read twice, offsets written
-        "pb_scatter1": 16.0 * N + 8.0 * C,         # static record in, (dest, src) out
+        "pb_scatter1": 2.0 * N + 12.0 * C,         # counts and own list in, (dest, src) out
         "pb_hist2": 8.0 * C,
         "pb_scatter2": 16.0 * C,
         "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
         "rowptr": 18.0 * N,
-        "pb_assemble": 8.0 * E + 4.0 * C + 28.0 * N,
+        "pb_assemble": 8.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col + w out
         # claim-based builder
         "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 8.0 * E + 8.0 * C + 24.0 * N,
         "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
@@ -83,7 +84,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
 
 KERNEL_SOURCES = {"message": "k_step.hip", "fused": "k_step.hip", "pre": "k_step.hip",
                   "mask": "k_step.hip", "rowptr": "k_graph.hip", "pb_assemble": "k_build.hip",
-                  "pb_hist1": "k_build.hip", "pb_scatter1": "k_build.hip",
+                  "pb_gen": "k_build.hip", "pb_scatter1": "k_build.hip",
                   "pb_hist2": "k_build.hip", "pb_scatter2": "k_build.hip",
                   "pb_leaf": "k_build.hip", "pb_scan1": "k_build.hip"}
 

@@ -85,7 +85,7 @@ struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds;
-  size_t pb_hist1, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
+  size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
       pb_buf2, pb_rsrc, pb_rstart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
       gtheta, gpart, dL;
@@ -95,7 +95,7 @@ struct Sizes {
   int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
-  int64_t pb_on = 0, lb = 0, nb1 = 0, nst = 0, nbatch = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
+  int64_t pb_on = 0, lb = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
   int64_t leaf_cap = 0, asm_cap = 0;
   int64_t fseg = 1;
 };
@@ -289,7 +289,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   const double leaf_mean = rbar * (double)((int64_t)1 << lb);
   z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
-            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31);
+            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576;
   // edges of a tile staged in LDS by the row assembly: 1.25x the mean (+512)
   const double tile_mean = emean * (double)TILE / (double)N;
   z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.25 * tile_mean) + 512 + 255) / 256 * 256));
@@ -297,8 +297,15 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
     z.leaf_cap = 1024;
     z.asm_cap = 2048;
   }
-  z.nst = (z.ntiles + 63) / 64;
   z.nbatch = (z.ntiles + 3) / 4;
+  // batches per generation / level-1 workgroup: up to 16, keeping >= 1024 workgroups
+  z.bpw = std::max<int64_t>(1, std::min<int64_t>(16, z.nbatch / 1024));
+  z.ngrid = (z.nbatch + z.bpw - 1) / z.bpw;
+  // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048)
+  double mo = 0, mr = 0;
+  for (int k = 0; k < ABM_N_OCC; ++k) mo = std::max(mo, p->mu_occupation[k] / 2.0);
+  for (int k = 0; k < ABM_N_AGE; ++k) mr = std::max(mr, p->mu_random[k] / 2.0);
+  z.bcap = ((int64_t)(1.3 * 1024.0 * (mo + mr)) + 2048 + 255) / 256 * 256;
   z.s1_nparts = (z.nb1 * z.nbatch + SCAN_BLOCK - 1) / SCAN_BLOCK;
   z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
   z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;
@@ -346,6 +353,8 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
   if (z.pb_on) {
     o.pb_hist1 = L.take<int32_t>(z.nbatch * z.nb1 + 1);
+    o.pb_own = L.take<uint32_t>(z.nbatch * z.bcap);
+    o.pb_tbase = L.take<int32_t>(z.ntiles);
     o.pb_part = L.take<int64_t>(z.s1_nparts + 1);
     o.pb_bstart = L.take<int32_t>(z.nb1 + 1);
     o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
@@ -615,8 +624,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   if (z.pb_on) {
     d.pb_lb = (int32_t)z.lb;
     d.pb_nb1 = (int32_t)z.nb1;
-    d.pb_nst = (int32_t)z.nst;
     d.pb_nbatch = (int32_t)z.nbatch;
+    d.pb_bpw = (int32_t)z.bpw;
+    d.pb_ngrid = (int32_t)z.ngrid;
+    d.pb_bcap = (int32_t)z.bcap;
     d.pb_s1_nparts = (int32_t)z.s1_nparts;
     d.pb_maxch = (int32_t)z.maxch;
     d.pb_nleaf = (int32_t)z.nleaf;
@@ -624,6 +635,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_asm_cap = (int32_t)z.asm_cap;
     d.pb_ccap = z.ccap;
     d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
+    d.pb_own = (uint32_t*)(ws + o.pb_own);
+    d.pb_tbase = (int32_t*)(ws + o.pb_tbase);
     d.pb_part = (int64_t*)(ws + o.pb_part);
     d.pb_bstart = (int32_t*)(ws + o.pb_bstart);
     d.pb_bchunk = (int32_t*)(ws + o.pb_bchunk);

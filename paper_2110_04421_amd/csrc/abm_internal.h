@@ -111,10 +111,12 @@ struct Dev {
 
   // partitioned graph builder (k_build.hip)
   int32_t msg_chunk, msg_grid, msg_ldsmask;   // message-kernel tiling (autotuned or default)
-  int32_t pb_on, pb_lb, pb_nb1, pb_nst, pb_nbatch, pb_s1_nparts, pb_maxch, pb_nleaf, pb_leaf_cap,
-      pb_asm_cap;
+  int32_t pb_on, pb_lb, pb_nb1, pb_nbatch, pb_bpw, pb_ngrid, pb_bcap, pb_s1_nparts, pb_maxch, pb_nleaf,
+      pb_leaf_cap, pb_asm_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
-  int32_t* pb_hist1;        // [nst][nb1] histogram, then run offsets
+  int32_t* pb_hist1;        // [nb1][nbatch] + 1: histograms, then run offsets
+  uint32_t* pb_own;         // [nbatch][pb_bcap] each batch's own draws, agent order
+  int32_t* pb_tbase;        // [ntiles] a tile's first entry in its batch's own list
   int64_t* pb_part;         // [s1_nparts + 1]
   int32_t* pb_bstart;       // [nb1 + 1]
   int32_t* pb_bchunk;       // [nb1 + 1] first chunk of each bucket

@@ -2,11 +2,13 @@
 // claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
 // global atomics and without random 4-byte scatters:
 //
-//   P1  gen/hist    per batch of 4 tiles: draw every agent's contacts, keep its own
-//                   counts, histogram the partners by level-1 digit (dest >> (LB + 8)).
+//   P1  gen         per batch of 4 tiles: draw every agent's contacts once (Philox, and
+//                   the workplace-member loads), store them in agent order in the
+//                   batch's own list, keep the agent's counts, histogram the partners
+//                   by level-1 digit (dest >> (LB + 8)).
 //   S1  scan        digit-major exclusive scan of the histograms -> each (digit, batch)
 //                   run's offset; level-1 bucket bounds; chunk table.
-//   P2  scatter-1   draw the contacts again, counting-sort the batch's entries
+//   P2  scatter-1   read the batch's own list, counting-sort its entries
 //                   (dest, src | net) by digit in LDS, write each run contiguously.
 //   P3  hist-2      per chunk of a level-1 bucket: histogram by level-2 digit.
 //   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
@@ -15,22 +17,21 @@
 //                   (destination, network) run sorted by initiator; received counts and
 //                   the received-list start of every destination.
 //   row pointers    the prefix scan of k_graph.hip (scan1-3).
-//   P6  assemble    each row: household, own occupation draws, received occupation
-//                   (copied), own random draws, received random (copied).
+//   P6  assemble    each row: household, own occupation draws, received occupation,
+//                   own random draws, received random; the own and received parts of
+//                   a tile are contiguous ranges, copied by all lanes together.
 // Every run written in P2/P4 leaves as consecutive lanes on consecutive addresses, and
 // every random access of a per-edge scatter becomes an LDS access.
 #include "abm_internal.h"
 
 namespace abm {
 
-constexpr int PB_ST = 64;              // tiles per workgroup in P1/P2
-constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles in flight
-constexpr int PB_BT = PB_ST / 4;       // batches per workgroup
+constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles at a time
 constexpr int PB_S1_CAP = 12288;       // entries of a batch staged in LDS by P2
 constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
 
-// Contact generation shared with k_graph.hip (same draws, same order).
+// Contact generation: the same draws, in the same order, as k_graph.hip's.
 struct Gen {
   uint32_t loc, t, stream, purpose, k0, k1, m, pos;
   int base, wp_lo;
@@ -81,47 +82,80 @@ __device__ __forceinline__ Gen gen_rand(const Dev& d, const RepInfo& ri, uint32_
   return g;
 }
 
-__device__ __forceinline__ void load_ptab(const Dev& d, uint32_t* T) {
-  for (int i = threadIdx.x; i < NPT * 64; i += TILE) T[i] = d.ptab[i];
-}
-
-// ---- P1: own counts and level-1 histogram per batch --------------------------------
-// 1024 lanes = one batch of 4 tiles of 256 agents; a workgroup takes PB_BT batches.
-// The histograms are stored digit-major (digit * nbatch + batch), so the scan reads
-// them in order and each digit's PB_BT counts leave as one 64-byte run.
-__global__ __launch_bounds__(PB_THREADS) void k_pb_hist1(Dev d) {
+// ---- P1: draw each batch's contacts once --------------------------------------------
+// 1024 lanes = one batch of 4 tiles of 256 agents; a workgroup takes pb_bpw batches.
+// The batch's draws are staged in LDS in agent order (own workplace draws, then own
+// random draws, each in draw order) and written contiguously to the batch's own list
+// (pb_bcap entries a batch); pb_tbase[tile] is the tile's first entry in it.  The
+// level-1 histograms are stored digit-major (digit * nbatch + batch) for the scan.
+__global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_gen(Dev d) {
+  extern __shared__ uint32_t stage[];        // [pb_bcap]
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int hist[PB_BT][PB_NB1_MAX];
-  for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
-  for (int k = threadIdx.x; k < PB_BT * PB_NB1_MAX; k += PB_THREADS) (&hist[0][0])[k] = 0;
+  __shared__ int hist[PB_NB1_MAX];
+  __shared__ int wsum[PB_THREADS / 64];
+  __shared__ int ntot;
+  for (int k = threadIdx.x; k < NPT * 64; k += PB_THREADS) T[k] = d.ptab[k];
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
-  const int tile0 = blockIdx.x * PB_ST;
-  const int tile_end = min(d.ntiles, tile0 + PB_ST);
-  for (int tix = tile0 + (threadIdx.x >> 8); tix < tile_end; tix += PB_THREADS / TILE) {
-    int* h = hist[(tix - tile0) >> 2];
-    const int4 tl = d.tiles[tix];
-    const int i = tl.y + (threadIdx.x & (TILE - 1));
-    if (i < tl.z) {
-      const RepInfo& ri = d.rep[tl.x];
-      const StaticRec sr = d.srec[i];
-      const uint32_t loc = (uint32_t)(i - ri.start);
-      Gen go = gen_occ(d, sr, loc, t, ri.stream);
-      const int ko = go.count(T + sr.occ * 64);
-      go.each(d, ko, [&](int, int p) { atomicAdd(&h[p >> s1], 1); });
-      Gen gr = gen_rand(d, ri, loc, t);
-      const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-      gr.each(d, kr, [&](int, int p) { atomicAdd(&h[p >> s1], 1); });
-      d.own[i] = (uint16_t)(ko | (kr << 8));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = 0; j < d.pb_bpw; ++j) {
+    const int bt = blockIdx.x * d.pb_bpw + j;
+    if (bt >= d.pb_nbatch) break;
+    for (int k = tid; k < d.pb_nb1; k += PB_THREADS) hist[k] = 0;
+    const int tix = bt * 4 + (tid >> 8);
+    int i = 0, ko = 0, kr = 0;
+    bool live = false;
+    Gen go, gr;
+    if (tix < d.ntiles) {
+      const int4 tl = d.tiles[tix];
+      i = tl.y + (tid & (TILE - 1));
+      live = i < tl.z;
+      if (live) {
+        const RepInfo& ri = d.rep[tl.x];
+        const StaticRec sr = d.srec[i];
+        const uint32_t loc = (uint32_t)(i - ri.start);
+        go = gen_occ(d, sr, loc, t, ri.stream);
+        ko = go.count(T + sr.occ * 64);
+        gr = gen_rand(d, ri, loc, t);
+        kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
+        d.own[i] = (uint16_t)(ko | (kr << 8));
+      }
     }
-  }
-  __syncthreads();
-  const int bt0 = blockIdx.x * PB_BT;
-  const int nb = min(PB_BT, d.pb_nbatch - bt0);
-  for (int k = threadIdx.x; k < d.pb_nb1 * PB_BT; k += PB_THREADS) {
-    const int dg = k / PB_BT, j = k % PB_BT;
-    if (j < nb) d.pb_hist1[(size_t)dg * d.pb_nbatch + bt0 + j] = hist[j][dg];
+    const int c = ko + kr;
+    int inc = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    const int off = wb + inc - c;
+    if (tid == PB_THREADS - 1) ntot = wb + inc;
+    if ((tid & (TILE - 1)) == 0 && tix < d.ntiles) d.pb_tbase[tix] = off;
+    __syncthreads();
+    const int n = ntot;
+    if (n > d.pb_bcap) {                     // more draws than the batch's room
+      if (tid == 0) atomicOr(d.flags, FLAG_CAPACITY);
+      return;
+    }
+    if (live) {
+      go.each(d, ko, [&](int q, int p) {
+        stage[off + q - 1] = (uint32_t)p;
+        atomicAdd(&hist[p >> s1], 1);
+      });
+      gr.each(d, kr, [&](int q, int p) {
+        stage[off + ko + q - 1] = (uint32_t)p;
+        atomicAdd(&hist[p >> s1], 1);
+      });
+    }
+    __syncthreads();
+    uint32_t* dst = d.pb_own + (size_t)bt * d.pb_bcap;
+    for (int k = tid; k < n; k += PB_THREADS) dst[k] = stage[k];
+    for (int k = tid; k < d.pb_nb1; k += PB_THREADS) d.pb_hist1[(size_t)k * d.pb_nbatch + bt] = hist[k];
+    __syncthreads();
   }
 }
 
@@ -236,25 +270,25 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 }
 
 // ---- P2: scatter into level-1 runs ---------------------------------------------------
-// Per batch: its runs' offsets and sizes come from the scanned histograms; the batch's
-// entries are drawn again and counting-sorted by digit into LDS, then each run leaves
-// as consecutive lanes on consecutive addresses.  A batch with more than PB_S1_CAP
-// entries writes each entry directly to its run.  The order inside a run is
-// immaterial: the leaf sort orders fully.
+// Per batch: its runs' offsets and sizes come from the scanned histograms.  The
+// batch's own list is read with consecutive lanes on consecutive entries; an entry's
+// initiator is the last agent whose list starts at or before it (binary search over
+// the batch's 1024 list starts in LDS).  Entries are counting-sorted by digit into
+// LDS and each run leaves as consecutive lanes on consecutive addresses; a batch with
+// more than PB_S1_CAP entries writes each entry directly to its run.  The order inside
+// a run is immaterial: the leaf sort orders fully.
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
-  __shared__ uint32_t T[NPT * 64];
   __shared__ uint2 stage[PB_S1_CAP];
   __shared__ int gofs[PB_NB1_MAX], lst[PB_NB1_MAX], lcur[PB_NB1_MAX];
-  __shared__ int wsum[PB_THREADS / 64];
+  __shared__ int aoff[PB_THREADS], aid[PB_THREADS], ako[PB_THREADS];
+  __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
   __shared__ int nstage;
   if (*d.flags) return;
-  for (int i = threadIdx.x; i < NPT * 64; i += PB_THREADS) T[i] = d.ptab[i];
-  const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
-  for (int j = 0; j < PB_BT; ++j) {
-    const int bt = blockIdx.x * PB_BT + j;
+  for (int j = 0; j < d.pb_bpw; ++j) {
+    const int bt = blockIdx.x * d.pb_bpw + j;
     if (bt >= nbt) break;
     int cntv = 0;
     if (tid < d.pb_nb1) {
@@ -263,53 +297,64 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       gofs[tid] = o;
       cntv = d.pb_hist1[q + 1] - o;
     }
-    int inc = cntv;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
+    const int tix = bt * 4 + (tid >> 8);
+    int i = 0, ko = 0, c = 0;
+    if (tix < d.ntiles) {
+      const int4 tl = d.tiles[tix];
+      i = tl.y + (tid & (TILE - 1));
+      if (i < tl.z) {
+        const uint32_t o = d.own[i];
+        ko = (int)(o & 0xFFu);
+        c = ko + (int)(o >> 8);
+      }
     }
-    if (lane == 63) wsum[wv] = inc;
+    int inc = cntv, inc2 = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o), y2 = __shfl_up(inc2, o);
+      if (lane >= o) {
+        inc += y;
+        inc2 += y2;
+      }
+    }
+    if (lane == 63) {
+      wsum[wv] = inc;
+      wsum2[wv] = inc2;
+    }
     __syncthreads();
-    int wb = 0;
-    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    int wb = 0, wb2 = 0;
+    for (int q = 0; q < wv; ++q) {
+      wb += wsum[q];
+      wb2 += wsum2[q];
+    }
     if (tid < d.pb_nb1) {
       lst[tid] = wb + inc - cntv;
       lcur[tid] = wb + inc - cntv;
     }
+    aoff[tid] = wb2 + inc2 - c;
+    aid[tid] = i;
+    ako[tid] = ko;
     if (tid == PB_THREADS - 1) nstage = wb + inc;
     __syncthreads();
-    const bool staged = nstage <= PB_S1_CAP;
-    const int tix = bt * 4 + (tid >> 8);
-    if (tix < d.ntiles) {
-      const int4 tl = d.tiles[tix];
-      const int i = tl.y + (tid & (TILE - 1));
-      if (i < tl.z) {
-        const RepInfo& ri = d.rep[tl.x];
-        const StaticRec sr = d.srec[i];
-        const uint32_t loc = (uint32_t)(i - ri.start);
-        Gen go = gen_occ(d, sr, loc, t, ri.stream);
-        const int ko = go.count(T + sr.occ * 64);
-        go.each(d, ko, [&](int, int p) {
-          const int dg = p >> s1;
-          const int slot = atomicAdd(&lcur[dg], 1);
-          const uint2 x = make_uint2((uint32_t)p, (uint32_t)i);
-          if (staged) stage[slot] = x;
-          else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
-        });
-        Gen gr = gen_rand(d, ri, loc, t);
-        const int kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-        gr.each(d, kr, [&](int, int p) {
-          const int dg = p >> s1;
-          const int slot = atomicAdd(&lcur[dg], 1);
-          const uint2 x = make_uint2((uint32_t)p, (uint32_t)i | 0x80000000u);
-          if (staged) stage[slot] = x;
-          else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
-        });
+    const int n = nstage;
+    const bool staged = n <= PB_S1_CAP;
+    const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
+    for (int k = tid; k < n; k += PB_THREADS) {
+      const uint32_t p = src[k];
+      int lo = 0, hi = PB_THREADS;                 // last lane with aoff <= k
+      while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (aoff[m] <= k) lo = m; else hi = m;
       }
+      const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
+      const int dg = (int)(p >> s1);
+      const int slot = atomicAdd(&lcur[dg], 1);
+      const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
+      if (staged) stage[slot] = x;
+      else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
     }
     __syncthreads();
     if (staged) {
-      for (int k = tid; k < nstage; k += PB_THREADS) {
+      for (int k = tid; k < n; k += PB_THREADS) {
         const uint2 x = stage[k];
         const int dg = (int)(x.x >> s1);
         d.pb_buf1[gofs[dg] + k - lst[dg]] = x;
@@ -539,12 +584,13 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
 // ---- P6: assemble each row --------------------------------------------------------
 // Rows of a tile are contiguous in the CSR.  Each lane lays out its row (household,
 // own occupation draws, received occupation, own random draws, received random) and
-// fills the parts it generates itself; the received parts of all the tile's rows are
-// one contiguous range of the sorted received lists, copied by all lanes together with
-// consecutive lanes on consecutive entries.  The row is staged in LDS (source id with
-// the network in the top two bits) and the tile's edge range is written with
-// consecutive lanes on consecutive addresses.  A tile with more edges than the LDS
-// room writes directly.
+// writes its household part.  The tile's own draws (one contiguous range of its
+// batch's own list) and its received lists (one contiguous range of the sorted
+// received lists) are copied by all lanes together, consecutive lanes on consecutive
+// entries; a binary search over the rows' list starts places each entry.  The row is
+// staged in LDS (source id with the network in the top two bits) and the tile's edge
+// range is written with consecutive lanes on consecutive addresses.  A tile with more
+// edges than the LDS room writes directly.
 __device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* scol, int base, int pos,
                                          int src, int net) {
   if (staged) {
@@ -555,52 +601,85 @@ __device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* sco
   }
 }
 
+// Last row j < n whose list starts at or before g (starts nondecreasing, s[0] <= g).
+__device__ __forceinline__ int row_of(const int* s, int n, int g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (s[m] <= g) lo = m; else hi = m;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   extern __shared__ int32_t scol[];                  // [pb_asm_cap]
-  __shared__ int rsl[TILE], rol[TILE], pol[TILE], prl[TILE];
-  __shared__ int gend;
+  __shared__ int rsl[TILE], rol[TILE], prol[TILE], prrl[TILE];   // received lists
+  __shared__ int osl[TILE], okl[TILE], pool[TILE], porl[TILE];   // own draws
+  __shared__ int wsum[TILE / 64];
+  __shared__ int gend, oend;
   if (*d.flags) return;
-  const int4 tl = d.tiles[blockIdx.x];
+  const int tix = blockIdx.x;
+  const int4 tl = d.tiles[tix];
   const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
   const bool staged = end - base <= d.pb_asm_cap;
   const int i = tl.y + threadIdx.x;
-  if (i < tl.z) {
-    const RepInfo& ri = d.rep[tl.x];
-    const uint32_t t = (uint32_t)(*d.day);
+  const bool live = i < tl.z;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int ko = 0, kr = 0;
+  if (live) {
+    const uint32_t o = d.own[i];
+    ko = (int)(o & 0xFFu);
+    kr = (int)(o >> 8);
+  }
+  const int c = ko + kr;
+  int inc = c;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int q = 0; q < wv; ++q) wb += wsum[q];
+  if (threadIdx.x == TILE - 1) oend = wb + inc;
+  if (live) {
     const StaticRec sr = d.srec[i];
-    const uint32_t loc = (uint32_t)(i - ri.start);
     const uint32_t r = d.recv[i];
     const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
     const int rs = d.pb_rstart[i];
     int pos = d.row_ptr[i];
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
       if (m != i) put_edge(d, staged, scol, base, pos++, m, 0);
-    Gen go = gen_occ(d, sr, loc, t, ri.stream);
-    const int ko = go.count(d.ptab + sr.occ * 64);
-    go.each(d, ko, [&](int, int p) { put_edge(d, staged, scol, base, pos++, p, 1); });
-    pol[threadIdx.x] = pos;
+    pool[threadIdx.x] = pos;
+    pos += ko;
+    prol[threadIdx.x] = pos;
     pos += ro;
-    Gen gr = gen_rand(d, ri, loc, t);
-    const int kr = gr.count(d.ptab + (PT_AGE0 + sr.age) * 64);
-    gr.each(d, kr, [&](int, int p) { put_edge(d, staged, scol, base, pos++, p, 2); });
-    prl[threadIdx.x] = pos;
+    porl[threadIdx.x] = pos;
+    pos += kr;
+    prrl[threadIdx.x] = pos;
+    osl[threadIdx.x] = wb + inc - c;
+    okl[threadIdx.x] = ko;
     rsl[threadIdx.x] = rs;
     rol[threadIdx.x] = ro;
     if (i == tl.z - 1) gend = rs + ro + rr;
   }
   __syncthreads();
   const int nlive = tl.z - tl.y;
+  const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + d.pb_tbase[tix];
+  for (int k = threadIdx.x; k < oend; k += TILE) {
+    const int src = (int)ob[k];
+    const int a = row_of(osl, nlive, k);
+    const int off = k - osl[a];
+    if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, src, 1);
+    else put_edge(d, staged, scol, base, porl[a] + off - okl[a], src, 2);
+  }
   const int g0 = rsl[0], g1 = gend;
   for (int g = g0 + threadIdx.x; g < g1; g += TILE) {
     const int src = (int)d.pb_rsrc[g];
-    int lo = 0, hi = nlive;                          // last row j with rsl[j] <= g
-    while (hi - lo > 1) {
-      const int m = (lo + hi) >> 1;
-      if (rsl[m] <= g) lo = m; else hi = m;
-    }
-    const int off = g - rsl[lo];
-    if (off < rol[lo]) put_edge(d, staged, scol, base, pol[lo] + off, src, 1);
-    else put_edge(d, staged, scol, base, prl[lo] + off - rol[lo], src, 2);
+    const int a = row_of(rsl, nlive, g);
+    const int off = g - rsl[a];
+    if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, src, 1);
+    else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], src, 2);
   }
   if (!staged) return;
   __syncthreads();
@@ -617,7 +696,7 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
 int build_steps(const Dev& d) { return d.pb_on ? 8 : 5; }
 
 const char* build_step_name(const Dev& d, int k) {
-  static const char* pb[8] = {"pb_hist1", "pb_scan1", "pb_scatter1", "pb_hist2",
+  static const char* pb[8] = {"pb_gen", "pb_scan1", "pb_scatter1", "pb_hist2",
                               "pb_scatter2", "pb_leaf", "rowptr", "pb_assemble"};
   static const char* cl[5] = {"clear", "count", "scan", "fill", "canon"};
   return d.pb_on ? pb[k] : cl[k];
@@ -629,7 +708,9 @@ hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)leaf_lds(d));
-  return e;
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pb_gen, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             d.pb_bcap * 4);
 }
 
 void launch_build_step(const Dev& d, int k, hipStream_t s) {
@@ -644,14 +725,14 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     return;
   }
   switch (k) {
-    case 0: hipLaunchKernelGGL(k_pb_hist1, dim3(d.pb_nst), dim3(PB_THREADS), 0, s, d); break;
+    case 0: hipLaunchKernelGGL(k_pb_gen, dim3(d.pb_ngrid), dim3(PB_THREADS), (size_t)d.pb_bcap * 4, s, d); break;
     case 1:
       hipLaunchKernelGGL(k_pb_s1a, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_part, d.pb_s1_nparts);
       hipLaunchKernelGGL(k_pb_s1c, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_buckets, dim3(1), dim3(1024), 0, s, d);
       break;
-    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_nst), dim3(PB_THREADS), 0, s, d); break;
+    case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_ngrid), dim3(PB_THREADS), 0, s, d); break;
     case 3:
       hipLaunchKernelGGL(k_pb_hist2, dim3(d.pb_maxch), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
