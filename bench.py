@@ -47,6 +47,8 @@ def leaf_bits(N: int, C: float) -> int:
     lb = min(11, max(6, int(np.floor(np.log2(6000.0 / rbar)))))
     while lb < 11 and -(-N // (1 << (lb + 8))) > 1024:
         lb += 1
+    while lb > 6 and (N >> lb) < 1024 and -(-N // (1 << (lb + 7))) <= 1024:
+        lb -= 1
     return lb
 
 

@@ -49,17 +49,21 @@ def sample_theta(n, seed):
 def simulate_curves(params, base_pop, theta, seed, stream0=0, days=180, batch=256, log=None):
     """Daily incidence [n, days] of plain runs of ``base_pop`` at each parameter row,
     ``batch`` runs per launch (replicate r uses Philox stream stream0 + r)."""
+    import dataclasses
     from synthpop import replicate_population
     from .sim import Simulator
     theta = np.asarray(theta, np.float64)
     n = theta.shape[0]
     out = np.zeros((n, days), np.int64)
     p = dict(params, seed=int(seed), n_steps=days, mode=L.HARD)
+    reps = {}                                  # the agents are the same for every batch
     for b0 in range(0, n, batch):
         b1 = min(n, b0 + batch)
-        pop = replicate_population(base_pop, b1 - b0, R=theta[b0:b1, 0].astype(np.float32),
-                                   susceptibility=theta[b0:b1, 1:].astype(np.float32))
-        pop.stream = (stream0 + np.arange(b0, b1)).astype(np.uint32)
+        if b1 - b0 not in reps:
+            reps[b1 - b0] = replicate_population(base_pop, b1 - b0)
+        pop = dataclasses.replace(reps[b1 - b0], R=theta[b0:b1, 0].astype(np.float32),
+                                  susceptibility=theta[b0:b1, 1:].astype(np.float32),
+                                  stream=(stream0 + np.arange(b0, b1)).astype(np.uint32))
         with Simulator(p, pop) as s:
             out[b0:b1] = s.run(days)[:, :, L.C_NEW].T
         if log:

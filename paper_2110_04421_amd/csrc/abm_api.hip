@@ -281,6 +281,8 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   lb = std::min(11, std::max(6, lb));
   auto nb1_of = [&](int b) { return (N + ((int64_t)1 << (b + 8)) - 1) >> (b + 8); };
   while (lb < 11 && nb1_of(lb) > 1024) ++lb;
+  // small populations: smaller leaves, so that there are enough of them to fill the GPU
+  while (lb > 6 && (N >> lb) < 1024 && nb1_of(lb - 1) <= 1024) --lb;
   z.lb = lb;
   z.nb1 = nb1_of(lb);
   // a leaf holds about rbar * 2^lb entries; its LDS room is 1.25x that (+512).  A
@@ -337,7 +339,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.row_ptr = L.take<int32_t>(z.N + 1);
   o.cur_occ = L.take<int32_t>(z.N);
   o.cur_rand = L.take<int32_t>(z.N);
-  o.col = L.take<int32_t>(z.ecap);
+  o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
   o.w = L.take<float>(z.ecap);
   o.scan_part = L.take<int64_t>(z.nscan + 1);
   o.vhist = L.take<int32_t>(z.ntiles * NBUCKET);

@@ -28,6 +28,7 @@ namespace abm {
 
 constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles at a time
 constexpr int PB_S1_CAP = 12288;       // entries of a batch staged in LDS by P2
+constexpr int PB_UNROLL = 8;           // loads a lane issues before using them (P2, P6)
 constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
 
@@ -338,19 +339,30 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
     const int n = nstage;
     const bool staged = n <= PB_S1_CAP;
     const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
-    for (int k = tid; k < n; k += PB_THREADS) {
-      const uint32_t p = src[k];
-      int lo = 0, hi = PB_THREADS;                 // last lane with aoff <= k
-      while (hi - lo > 1) {
-        const int m = (lo + hi) >> 1;
-        if (aoff[m] <= k) lo = m; else hi = m;
+    for (int kb = 0; kb < n; kb += PB_THREADS * PB_UNROLL) {
+      uint32_t pv[PB_UNROLL];                      // all loads first, then their use
+#pragma unroll
+      for (int u = 0; u < PB_UNROLL; ++u) {
+        const int k = kb + u * PB_THREADS + tid;
+        pv[u] = k < n ? src[k] : 0u;
       }
-      const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
-      const int dg = (int)(p >> s1);
-      const int slot = atomicAdd(&lcur[dg], 1);
-      const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
-      if (staged) stage[slot] = x;
-      else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+#pragma unroll
+      for (int u = 0; u < PB_UNROLL; ++u) {
+        const int k = kb + u * PB_THREADS + tid;
+        if (k >= n) break;
+        const uint32_t p = pv[u];
+        int lo = 0, hi = PB_THREADS;               // last lane with aoff <= k
+        while (hi - lo > 1) {
+          const int m = (lo + hi) >> 1;
+          if (aoff[m] <= k) lo = m; else hi = m;
+        }
+        const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
+        const int dg = (int)(p >> s1);
+        const int slot = atomicAdd(&lcur[dg], 1);
+        const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
+        if (staged) stage[slot] = x;
+        else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+      }
     }
     __syncthreads();
     if (staged) {
@@ -478,10 +490,15 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 }
 
 // ---- P5: per leaf, sort by (destination, network, initiator) in LDS ------------------
+// A lane keeps up to PB_LEAF_PER of the leaf's entries in registers, so the leaf is
+// read once (entries beyond PB_LEAF_THREADS * PB_LEAF_PER are read again from memory).
 // The LDS holds pb_leaf_cap entries.  A larger leaf is sorted in groups of whole keys
-// that each fit, the leaf's entries being read once more per extra group; only a
-// single (destination, network) run longer than the cap is an error.
-__global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
+// that each fit; only a single (destination, network) run longer than the cap is an
+// error.
+constexpr int PB_LEAF_THREADS = 512;
+constexpr int PB_LEAF_PER = 16;
+__global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_leaf(Dev d) {
+  constexpr int LT = PB_LEAF_THREADS;
   extern __shared__ uint32_t lds[];
   if (*d.flags) return;
   const int L = blockIdx.x;
@@ -491,19 +508,27 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
   const int nkeys = 2 << d.pb_lb;             // (destination offset, network)
   uint32_t* sorted = lds;                     // [cap]
   int* cnt = (int*)(lds + cap);               // [nkeys + 1]
-  __shared__ int wsum[TILE / 64];
+  __shared__ int wsum[LT / 64];
   __shared__ int carry, grp_end;
-  for (int k = threadIdx.x; k <= nkeys; k += TILE) cnt[k] = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k = tid; k <= nkeys; k += LT) cnt[k] = 0;
   __syncthreads();
   const uint32_t dmask = (1u << d.pb_lb) - 1u;
-  for (int e = lo + threadIdx.x; e < hi; e += TILE) {
-    const uint2 v = d.pb_buf2[e];
-    atomicAdd(&cnt[((v.x & dmask) << 1) | (v.y >> 31)], 1);
+  auto key = [&](const uint2& v) { return (int)(((v.x & dmask) << 1) | (v.y >> 31)); };
+  uint2 x[PB_LEAF_PER];
+#pragma unroll
+  for (int j = 0; j < PB_LEAF_PER; ++j) {
+    const int e = lo + j * LT + tid;
+    x[j] = e < hi ? d.pb_buf2[e] : make_uint2(0u, 0u);
   }
+#pragma unroll
+  for (int j = 0; j < PB_LEAF_PER; ++j)
+    if (lo + j * LT + tid < hi) atomicAdd(&cnt[key(x[j])], 1);
+  for (int e = lo + PB_LEAF_PER * LT + tid; e < hi; e += LT) atomicAdd(&cnt[key(d.pb_buf2[e])], 1);
   __syncthreads();
   // per-destination received counts (before the counts become offsets)
   const int dest0 = L << d.pb_lb;
-  for (int k = threadIdx.x; k <= (int)dmask; k += TILE) {
+  for (int k = tid; k <= (int)dmask; k += LT) {
     const int dest = dest0 + k;
     if (dest < d.N) {
       const int co = cnt[2 * k], cr = cnt[2 * k + 1];
@@ -511,11 +536,10 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
       d.recv[dest] = ((uint32_t)co << 16) | (uint32_t)cr;
     }
   }
-  if (threadIdx.x == 0) carry = 0;
+  if (tid == 0) carry = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k0 = 0; k0 < nkeys; k0 += TILE) {
-    const int k = k0 + threadIdx.x;
+  for (int k0 = 0; k0 < nkeys; k0 += LT) {
+    const int k = k0 + tid;
     const int v = k < nkeys ? cnt[k] : 0;
     int inc = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -531,16 +555,16 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
       if ((k & 1) == 0 && dest0 + (k >> 1) < d.N) d.pb_rstart[dest0 + (k >> 1)] = lo + carry + wb + inc - v;
     }
     __syncthreads();
-    if (threadIdx.x == TILE - 1) carry += wb + inc;
+    if (tid == LT - 1) carry += wb + inc;
     __syncthreads();
   }
-  if (threadIdx.x == 0) cnt[nkeys] = n;
+  if (tid == 0) cnt[nkeys] = n;
   __syncthreads();
   // cnt[k] is the start of run k; placing run k's entries advances cnt[k] to its end,
   // which is the start of run k + 1, so after a group run k is [cnt[k-1], cnt[k]).
   for (int ka = 0; ka < nkeys;) {
     const int o_lo = cnt[ka];
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       int a = ka, b = nkeys;                  // largest kb with cnt[kb] - o_lo <= cap
       while (a < b) {
         const int m = (a + b + 1) >> 1;
@@ -551,22 +575,28 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
     __syncthreads();
     const int kb = grp_end;
     if (kb == ka) {                           // one run longer than the LDS
-      if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
+      if (tid == 0) atomicOr(d.flags, FLAG_CAPACITY);
       return;
     }
     const int o_hi = cnt[kb];
-    __syncthreads();                          // everyone has read cnt[kb] before placement
-    for (int e = lo + threadIdx.x; e < hi; e += TILE) {
+    __syncthreads();                          // everyone has read cnt[ka] before placement
+#pragma unroll
+    for (int j = 0; j < PB_LEAF_PER; ++j) {
+      const int k = key(x[j]);
+      if (lo + j * LT + tid < hi && k >= ka && k < kb)
+        sorted[atomicAdd(&cnt[k], 1) - o_lo] = x[j].y & 0x7FFFFFFFu;
+    }
+    for (int e = lo + PB_LEAF_PER * LT + tid; e < hi; e += LT) {
       const uint2 v = d.pb_buf2[e];
-      const int k = ((v.x & dmask) << 1) | (v.y >> 31);
+      const int k = key(v);
       if (k >= ka && k < kb) sorted[atomicAdd(&cnt[k], 1) - o_lo] = v.y & 0x7FFFFFFFu;
     }
     __syncthreads();
-    for (int k = ka + threadIdx.x; k < kb; k += TILE) {
+    for (int k = ka + tid; k < kb; k += LT) {
       const int a = (k > ka ? cnt[k - 1] : o_lo) - o_lo, b = cnt[k] - o_lo;
-      for (int x = a + 1; x < b; ++x) {
-        const uint32_t v = sorted[x];
-        int y = x - 1;
+      for (int y0 = a + 1; y0 < b; ++y0) {
+        const uint32_t v = sorted[y0];
+        int y = y0 - 1;
         while (y >= a && sorted[y] > v) {
           sorted[y + 1] = sorted[y];
           --y;
@@ -575,7 +605,7 @@ __global__ __launch_bounds__(TILE) void k_pb_leaf(Dev d) {
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < o_hi - o_lo; k += TILE) d.pb_rsrc[lo + o_lo + k] = sorted[k];
+    for (int k = tid; k < o_hi - o_lo; k += LT) d.pb_rsrc[lo + o_lo + k] = sorted[k];
     __syncthreads();
     ka = kb;
   }
@@ -665,21 +695,42 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   }
   __syncthreads();
   const int nlive = tl.z - tl.y;
+  // both copies: a lane issues all its loads of a round before it places any entry
   const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + d.pb_tbase[tix];
-  for (int k = threadIdx.x; k < oend; k += TILE) {
-    const int src = (int)ob[k];
-    const int a = row_of(osl, nlive, k);
-    const int off = k - osl[a];
-    if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, src, 1);
-    else put_edge(d, staged, scol, base, porl[a] + off - okl[a], src, 2);
+  for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
+    int sv[PB_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u) {
+      const int k = kb + u * TILE + (int)threadIdx.x;
+      sv[u] = k < oend ? (int)ob[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u) {
+      const int k = kb + u * TILE + (int)threadIdx.x;
+      if (k >= oend) break;
+      const int a = row_of(osl, nlive, k);
+      const int off = k - osl[a];
+      if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, sv[u], 1);
+      else put_edge(d, staged, scol, base, porl[a] + off - okl[a], sv[u], 2);
+    }
   }
   const int g0 = rsl[0], g1 = gend;
-  for (int g = g0 + threadIdx.x; g < g1; g += TILE) {
-    const int src = (int)d.pb_rsrc[g];
-    const int a = row_of(rsl, nlive, g);
-    const int off = g - rsl[a];
-    if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, src, 1);
-    else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], src, 2);
+  for (int gb = g0; gb < g1; gb += TILE * PB_UNROLL) {
+    int sv[PB_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u) {
+      const int g = gb + u * TILE + (int)threadIdx.x;
+      sv[u] = g < g1 ? (int)d.pb_rsrc[g] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u) {
+      const int g = gb + u * TILE + (int)threadIdx.x;
+      if (g >= g1) break;
+      const int a = row_of(rsl, nlive, g);
+      const int off = g - rsl[a];
+      if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, sv[u], 1);
+      else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], sv[u], 2);
+    }
   }
   if (!staged) return;
   __syncthreads();
@@ -738,7 +789,7 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
       break;
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
-    case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(TILE), leaf_lds(d), s, d); break;
+    case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(PB_LEAF_THREADS), leaf_lds(d), s, d); break;
     case 6: launch_scan(d, s); break;
     default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 4, s, d); break;
   }

@@ -229,9 +229,12 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 // be one workgroup per tile or a persistent grid striding over the tiles).
 template <int CHUNK, bool LDSMASK>
 __global__ __launch_bounds__(TILE) void k_message(Dev d) {
-  // U edges per lane are loaded before any of them is used, so each lane keeps U
-  // independent HBM loads, then U independent mask lookups, in flight.
-  constexpr int U = CHUNK / TILE < 8 ? CHUNK / TILE : 8;
+  // Sources are read four at a time (16-byte loads from a 4-aligned start) and each
+  // lane issues U of those loads, then the mask lookups of all 4U sources, before it
+  // uses any of them, so that many independent loads are in flight.
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  constexpr int U = CHUNK / (TILE * 4) < 4 ? CHUNK / (TILE * 4) : 4;
+  constexpr int NE = 4 * U;
   constexpr int NW = CHUNK / 32;
   extern __shared__ unsigned long long scm[];        // super-coarse mask (LDSMASK)
   __shared__ float atab[ATAB];
@@ -253,36 +256,45 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
     float sum = 0.f;
     uint32_t infected_edges = 0;
     __syncthreads();
-    for (int c0 = e0; c0 < e1; c0 += CHUNK, par ^= 1) {
+    // chunks start at a multiple of 4 at or below e0; positions below e0 are skipped
+    for (int c0 = e0 & ~3; c0 < e1; c0 += CHUNK, par ^= 1) {
       const int cn = min(CHUNK, e1 - c0);
       uint32_t* nz = nzb[par];
-      for (int kb = 0; kb < cn; kb += TILE * U) {
-        uint32_t src[U];
-        bool hit[U];
+      for (int kb = 0; kb < cn; kb += TILE * NE) {
+        v4i v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int k = kb + u * TILE + (int)threadIdx.x;
-          hit[u] = k < cn;
-          src[u] = hit[u] ? (uint32_t)__builtin_nontemporal_load(d.col + c0 + k) : 0u;
-          src[u] = src[u] < (uint32_t)d.N ? src[u] : 0u;
+          const int k = kb + (u * TILE + (int)threadIdx.x) * 4;
+          v[u] = k < cn ? __builtin_nontemporal_load((const v4i*)(d.col + c0 + k)) : v4i{0, 0, 0, 0};
         }
+        uint32_t src[NE];
+        bool hit[NE];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const int k = kb + (u * TILE + (int)threadIdx.x) * 4 + l;
+            const uint32_t x = (uint32_t)v[u][l];
+            src[4 * u + l] = x < (uint32_t)d.N ? x : 0u;
+            hit[4 * u + l] = k < cn && c0 + k >= e0;
+          }
         if (LDSMASK) {
 #pragma unroll
-          for (int u = 0; u < U; ++u)
-            hit[u] = hit[u] && ((scm[src[u] >> 14] >> ((src[u] >> 8) & 63u)) & 1ull);
+          for (int q = 0; q < NE; ++q)
+            hit[q] = hit[q] && ((scm[src[q] >> 14] >> ((src[q] >> 8) & 63u)) & 1ull);
         }
-        uint32_t cw[U];
+        uint32_t cw[NE];
 #pragma unroll
-        for (int u = 0; u < U; ++u) cw[u] = hit[u] ? d.cmask[src[u] >> 8] : 0u;
+        for (int q = 0; q < NE; ++q) cw[q] = hit[q] ? d.cmask[src[q] >> 8] : 0u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) hit[u] = (cw[u] >> ((src[u] >> 3) & 31u)) & 1u;
+        for (int q = 0; q < NE; ++q) hit[q] = (cw[q] >> ((src[q] >> 3) & 31u)) & 1u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) cw[u] = hit[u] ? d.imask[src[u] >> 5] : 0u;
+        for (int q = 0; q < NE; ++q) cw[q] = hit[q] ? d.imask[src[q] >> 5] : 0u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if ((cw[u] >> (src[u] & 31u)) & 1u) {
-            const int k = kb + u * TILE + (int)threadIdx.x;
-            term[k] = __builtin_nontemporal_load(d.w + c0 + k) * atab[d.code[src[u]]];
+        for (int q = 0; q < NE; ++q) {
+          if ((cw[q] >> (src[q] & 31u)) & 1u) {
+            const int k = kb + ((q >> 2) * TILE + (int)threadIdx.x) * 4 + (q & 3);
+            term[k] = __builtin_nontemporal_load(d.w + c0 + k) * atab[d.code[src[q]]];
             atomicOr(&nz[k >> 5], 1u << (k & 31));
             ++infected_edges;
           }
