@@ -87,7 +87,7 @@ enum {
 #define ABM_FLAG_CLAIM_BUILDER 4 /* build the daily graph with per-edge atomic slot claims
                                     (the default partitions contacts by destination)     */
 #define ABM_FLAG_AUTOTUNE 8 /* at create, time the force-of-infection kernel's tilings
-                               (LDS chunk x grid shape) on day 0's graph, keep the fastest;
+                               (LDS chunk x grid x shape) on day 0's graph, keep the fastest;
                                results are bitwise the same for every tiling            */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
                                     assembly their smallest LDS room, so that leaves are
@@ -199,7 +199,9 @@ enum {
   ABM_GET_SOFT_S = 10, /* float[N]: soft susceptible mass                             */
   ABM_GET_COEF = 11,   /* float[R][9]: fl(fl(R*kappa)*S_a)                             */
   ABM_GET_TUNING = 12  /* int32[3]: message-kernel LDS chunk (edges), grid (workgroups),
-                          first mask level in LDS (1) or L2 (0)                        */
+                          shape: 0 one tile per workgroup with the masks in L2, 1 one
+                          tile with the first mask level in LDS, 2 four tiles sharing
+                          that LDS mask                                               */
 };
 /* Copy a device quantity to host (synchronous; h_bytes must be at least its size). */
 int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes);

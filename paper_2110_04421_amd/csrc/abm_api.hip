@@ -356,7 +356,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   if (z.pb_on) {
     o.pb_hist1 = L.take<int32_t>(z.nbatch * z.nb1 + 1);
     o.pb_own = L.take<uint32_t>(z.nbatch * z.bcap);
-    o.pb_tbase = L.take<int32_t>(z.ntiles);
+    o.pb_tbase = L.take<int2>(z.ntiles);
     o.pb_part = L.take<int64_t>(z.s1_nparts + 1);
     o.pb_bstart = L.take<int32_t>(z.nb1 + 1);
     o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
@@ -367,7 +367,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_buf1 = L.take<uint2>(z.ccap);
     o.pb_buf2 = L.take<uint2>(z.ccap);
     o.pb_rsrc = L.take<uint32_t>(z.ccap);
-    o.pb_rstart = L.take<int32_t>(z.N);
+    o.pb_rstart = L.take<int32_t>(z.N + 1);
   }
   if (p.mode == ABM_SOFT) {
     o.s = L.take<float>(z.N);
@@ -459,9 +459,9 @@ int autotune(abm_sim* s) {
   HIPCHK(s, hipEventCreate(&e0));
   HIPCHK(s, hipEventCreate(&e1));
   float best = 1e30f;
-  int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid, best_lds = d.msg_ldsmask;
+  int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid, best_shape = d.msg_shape;
   for (int v = 0; v < message_variants(); ++v) {
-    message_variant(d, v, &d.msg_chunk, &d.msg_grid, &d.msg_ldsmask);
+    message_variant(d, v, &d.msg_chunk, &d.msg_grid, &d.msg_shape);
     launch_message(d, st);                                 // warm-up
     HIPCHK(s, hipEventRecord(e0, st));
     for (int rep = 0; rep < 3; ++rep) launch_message(d, st);
@@ -473,14 +473,14 @@ int autotune(abm_sim* s) {
       best = ms;
       best_chunk = d.msg_chunk;
       best_grid = d.msg_grid;
-      best_lds = d.msg_ldsmask;
+      best_shape = d.msg_shape;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   d.msg_chunk = best_chunk;
   d.msg_grid = best_grid;
-  d.msg_ldsmask = best_lds;
+  d.msg_shape = best_shape;
   HIPCHK(s, hipGetLastError());
   return ABM_OK;
 }
@@ -621,7 +621,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   }
   d.msg_chunk = 4096;
   d.msg_grid = d.ntiles;
-  d.msg_ldsmask = 0;
+  d.msg_shape = 0;
   d.pb_on = (int32_t)z.pb_on;
   if (z.pb_on) {
     d.pb_lb = (int32_t)z.lb;
@@ -638,7 +638,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_ccap = z.ccap;
     d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
     d.pb_own = (uint32_t*)(ws + o.pb_own);
-    d.pb_tbase = (int32_t*)(ws + o.pb_tbase);
+    d.pb_tbase = (int2*)(ws + o.pb_tbase);
     d.pb_part = (int64_t*)(ws + o.pb_part);
     d.pb_bstart = (int32_t*)(ws + o.pb_bstart);
     d.pb_bchunk = (int32_t*)(ws + o.pb_bchunk);
@@ -844,7 +844,7 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
       int32_t* v = (int32_t*)h_dst;
       v[0] = s->d.msg_chunk;
       v[1] = s->d.msg_grid;
-      v[2] = s->d.msg_ldsmask;
+      v[2] = s->d.msg_shape;
       return ABM_OK;
     }
     case ABM_GET_COEF: {

@@ -110,13 +110,15 @@ struct Dev {
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)
-  int32_t msg_chunk, msg_grid, msg_ldsmask;   // message-kernel tiling (autotuned or default)
+  int32_t msg_chunk, msg_grid, msg_shape;     // message-kernel tiling (autotuned or default);
+                                              // shape 0: one tile a workgroup, masks in L2;
+                                              // 1: one tile, mask in LDS; 2: four tiles, mask in LDS
   int32_t pb_on, pb_lb, pb_nb1, pb_nbatch, pb_bpw, pb_ngrid, pb_bcap, pb_s1_nparts, pb_maxch, pb_nleaf,
       pb_leaf_cap, pb_asm_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nb1][nbatch] + 1: histograms, then run offsets
   uint32_t* pb_own;         // [nbatch][pb_bcap] each batch's own draws, agent order
-  int32_t* pb_tbase;        // [ntiles] a tile's first entry in its batch's own list
+  int2* pb_tbase;           // [ntiles] a tile's first entry in its batch's own list, count
   int64_t* pb_part;         // [s1_nparts + 1]
   int32_t* pb_bstart;       // [nb1 + 1]
   int32_t* pb_bchunk;       // [nb1 + 1] first chunk of each bucket
@@ -127,7 +129,7 @@ struct Dev {
   uint2* pb_buf1;           // [ccap] (destination, initiator | network << 31)
   uint2* pb_buf2;           // [ccap]
   uint32_t* pb_rsrc;        // [ccap] received initiators, sorted by (dest, network, initiator)
-  int32_t* pb_rstart;       // [N] first received entry of each destination
+  int32_t* pb_rstart;       // [N + 1] first received entry of each destination; [N] = total
 
   // soft mode
   float* s;            // susceptible mass [N]
@@ -200,7 +202,7 @@ void launch_fill(const Dev& d, hipStream_t s);
 void launch_canon(const Dev& d, hipStream_t s);
 void launch_message(const Dev& d, hipStream_t s);
 int message_variants();
-void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* ldsmask);
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* shape);
 void launch_fused(const Dev& d, hipStream_t s);
 void launch_finalize(const Dev& d, hipStream_t s);
 void launch_init_state(const Dev& d, const int32_t* seeds, int64_t nseeds, hipStream_t s);

@@ -83,11 +83,29 @@ __device__ __forceinline__ Gen gen_rand(const Dev& d, const RepInfo& ri, uint32_
   return g;
 }
 
+// For u < U: a[u] = the last j < n with s[j] <= g0 + u * gs, where s is nondecreasing
+// over [0, n), s[0] <= every query and n <= NMAX (a power of two).  The U searches go
+// in lockstep, so each step's U LDS reads are independent of one another.
+template <int U, int NMAX>
+__device__ __forceinline__ void last_le(const int* s, int n, int g0, int gs, int* a) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = 0;
+#pragma unroll
+  for (int h = NMAX / 2; h > 0; h >>= 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = a[u] + h;
+      if (m < n && s[m] <= g0 + u * gs) a[u] = m;
+    }
+  }
+}
+
 // ---- P1: draw each batch's contacts once --------------------------------------------
 // 1024 lanes = one batch of 4 tiles of 256 agents; a workgroup takes pb_bpw batches.
 // The batch's draws are staged in LDS in agent order (own workplace draws, then own
 // random draws, each in draw order) and written contiguously to the batch's own list
-// (pb_bcap entries a batch); pb_tbase[tile] is the tile's first entry in it.  The
+// (pb_bcap entries a batch); pb_tbase[tile] is the tile's first entry in it and its
+// number of entries.  The
 // level-1 histograms are stored digit-major (digit * nbatch + batch) for the scan.
 __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_gen(Dev d) {
   extern __shared__ uint32_t stage[];        // [pb_bcap]
@@ -135,7 +153,11 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     for (int q = 0; q < wv; ++q) wb += wsum[q];
     const int off = wb + inc - c;
     if (tid == PB_THREADS - 1) ntot = wb + inc;
-    if ((tid & (TILE - 1)) == 0 && tix < d.ntiles) d.pb_tbase[tix] = off;
+    if ((tid & (TILE - 1)) == 0 && tix < d.ntiles) {    // the tile's own-list range
+      int cnt = 0;
+      for (int q = wv; q < wv + TILE / 64; ++q) cnt += wsum[q];
+      d.pb_tbase[tix] = make_int2(off, cnt);
+    }
     __syncthreads();
     const int n = ntot;
     if (n > d.pb_bcap) {                     // more draws than the batch's room
@@ -346,16 +368,14 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
         const int k = kb + u * PB_THREADS + tid;
         pv[u] = k < n ? src[k] : 0u;
       }
+      int lane_of[PB_UNROLL];                      // last lane with aoff <= k
+      last_le<PB_UNROLL, PB_THREADS>(aoff, PB_THREADS, kb + tid, PB_THREADS, lane_of);
 #pragma unroll
       for (int u = 0; u < PB_UNROLL; ++u) {
         const int k = kb + u * PB_THREADS + tid;
         if (k >= n) break;
         const uint32_t p = pv[u];
-        int lo = 0, hi = PB_THREADS;               // last lane with aoff <= k
-        while (hi - lo > 1) {
-          const int m = (lo + hi) >> 1;
-          if (aoff[m] <= k) lo = m; else hi = m;
-        }
+        const int lo = lane_of[u];
         const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
         const int dg = (int)(p >> s1);
         const int slot = atomicAdd(&lcur[dg], 1);
@@ -385,8 +405,17 @@ __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
   hist[threadIdx.x] = 0;
   __syncthreads();
   const int4 ch = d.pb_chunks[c];
-  for (int e = ch.y + threadIdx.x; e < ch.z; e += TILE)
-    atomicAdd(&hist[(d.pb_buf1[e].x >> d.pb_lb) & 255u], 1);
+  for (int eb = ch.y; eb < ch.z; eb += TILE * PB_UNROLL) {
+    uint32_t x[PB_UNROLL];                       // all loads first, then their use
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u) {
+      const int e = eb + u * TILE + (int)threadIdx.x;
+      x[u] = e < ch.z ? d.pb_buf1[e].x : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < PB_UNROLL; ++u)
+      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> d.pb_lb) & 255u], 1);
+  }
   __syncthreads();
   d.pb_hist2[(size_t)c * 256 + threadIdx.x] = hist[threadIdx.x];
 }
@@ -558,7 +587,10 @@ __global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu
     if (tid == LT - 1) carry += wb + inc;
     __syncthreads();
   }
-  if (tid == 0) cnt[nkeys] = n;
+  if (tid == 0) {
+    cnt[nkeys] = n;
+    if (L == d.pb_nleaf - 1) d.pb_rstart[d.N] = hi;   // end of the last destination's list
+  }
   __syncthreads();
   // cnt[k] is the start of run k; placing run k's entries advances cnt[k] to its end,
   // which is the start of run k + 1, so after a group run k is [cnt[k-1], cnt[k]).
@@ -646,10 +678,22 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   __shared__ int rsl[TILE], rol[TILE], prol[TILE], prrl[TILE];   // received lists
   __shared__ int osl[TILE], okl[TILE], pool[TILE], porl[TILE];   // own draws
   __shared__ int wsum[TILE / 64];
-  __shared__ int gend, oend;
   if (*d.flags) return;
   const int tix = blockIdx.x;
   const int4 tl = d.tiles[tix];
+  // the tile's two source ranges are known before any row is laid out, so the first
+  // round of each copy is loaded together with the rows' own data
+  const int2 tb = d.pb_tbase[tix];
+  const int g0 = d.pb_rstart[tl.y], g1 = d.pb_rstart[tl.z];
+  const int oend = tb.y;
+  const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + tb.x;
+  int ov[PB_UNROLL], rv[PB_UNROLL];
+#pragma unroll
+  for (int u = 0; u < PB_UNROLL; ++u) {
+    const int k = u * TILE + (int)threadIdx.x;
+    ov[u] = k < oend ? (int)ob[k] : 0;
+    rv[u] = g0 + k < g1 ? (int)d.pb_rsrc[g0 + k] : 0;
+  }
   const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
   const bool staged = end - base <= d.pb_asm_cap;
   const int i = tl.y + threadIdx.x;
@@ -671,12 +715,10 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   __syncthreads();
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
-  if (threadIdx.x == TILE - 1) oend = wb + inc;
   if (live) {
     const StaticRec sr = d.srec[i];
     const uint32_t r = d.recv[i];
-    const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
-    const int rs = d.pb_rstart[i];
+    const int ro = (int)(r >> 16);
     int pos = d.row_ptr[i];
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
       if (m != i) put_edge(d, staged, scol, base, pos++, m, 0);
@@ -689,20 +731,20 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     prrl[threadIdx.x] = pos;
     osl[threadIdx.x] = wb + inc - c;
     okl[threadIdx.x] = ko;
-    rsl[threadIdx.x] = rs;
+    rsl[threadIdx.x] = d.pb_rstart[i];
     rol[threadIdx.x] = ro;
-    if (i == tl.z - 1) gend = rs + ro + rr;
   }
   __syncthreads();
   const int nlive = tl.z - tl.y;
-  // both copies: a lane issues all its loads of a round before it places any entry
-  const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + d.pb_tbase[tix];
+  // own draws, then received lists; a lane places all entries of a round after their
+  // loads have been issued together
   for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
-    int sv[PB_UNROLL];
+    if (kb > 0) {
 #pragma unroll
-    for (int u = 0; u < PB_UNROLL; ++u) {
-      const int k = kb + u * TILE + (int)threadIdx.x;
-      sv[u] = k < oend ? (int)ob[k] : 0;
+      for (int u = 0; u < PB_UNROLL; ++u) {
+        const int k = kb + u * TILE + (int)threadIdx.x;
+        ov[u] = k < oend ? (int)ob[k] : 0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u) {
@@ -710,17 +752,17 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
       if (k >= oend) break;
       const int a = row_of(osl, nlive, k);
       const int off = k - osl[a];
-      if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, sv[u], 1);
-      else put_edge(d, staged, scol, base, porl[a] + off - okl[a], sv[u], 2);
+      if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, ov[u], 1);
+      else put_edge(d, staged, scol, base, porl[a] + off - okl[a], ov[u], 2);
     }
   }
-  const int g0 = rsl[0], g1 = gend;
   for (int gb = g0; gb < g1; gb += TILE * PB_UNROLL) {
-    int sv[PB_UNROLL];
+    if (gb > g0) {
 #pragma unroll
-    for (int u = 0; u < PB_UNROLL; ++u) {
-      const int g = gb + u * TILE + (int)threadIdx.x;
-      sv[u] = g < g1 ? (int)d.pb_rsrc[g] : 0;
+      for (int u = 0; u < PB_UNROLL; ++u) {
+        const int g = gb + u * TILE + (int)threadIdx.x;
+        rv[u] = g < g1 ? (int)d.pb_rsrc[g] : 0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u) {
@@ -728,8 +770,8 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
       if (g >= g1) break;
       const int a = row_of(rsl, nlive, g);
       const int off = g - rsl[a];
-      if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, sv[u], 1);
-      else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], sv[u], 2);
+      if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, rv[u], 1);
+      else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], rv[u], 2);
     }
   }
   if (!staged) return;

@@ -227,8 +227,9 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
 // Each lane then sums its own row left to right (FP32, canonical order) from LDS, so
 // the result does not depend on CHUNK or on how tiles map to workgroups (the grid may
 // be one workgroup per tile or a persistent grid striding over the tiles).
-template <int CHUNK, bool LDSMASK>
-__global__ __launch_bounds__(TILE) void k_message(Dev d) {
+template <int CHUNK, bool LDSMASK, int G>
+__global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
+  // G tiles per workgroup (one per 256-lane group) share one LDS copy of the mask.
   // Sources are read four at a time (16-byte loads from a 4-aligned start) and each
   // lane issues U of those loads, then the mask lookups of all 4U sources, before it
   // uses any of them, so that many independent loads are in flight.
@@ -238,33 +239,45 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
   constexpr int NW = CHUNK / 32;
   extern __shared__ unsigned long long scm[];        // super-coarse mask (LDSMASK)
   __shared__ float atab[ATAB];
-  __shared__ float term[CHUNK];                      // written only where the source is infectious
-  __shared__ uint32_t nzb[2][NW];                    // which terms of the chunk are written
-  __shared__ uint32_t ninf[TILE / 64];
+  __shared__ float term_[G][CHUNK];                  // written only where the source is infectious
+  __shared__ uint32_t nzb_[G][2][NW];                // which terms of the chunk are written
+  __shared__ uint32_t ninf_[G][TILE / 64];
+  __shared__ int nch_max;
+  const int grp = threadIdx.x / TILE, tid = threadIdx.x % TILE;
+  float* term = term_[grp];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
   if (LDSMASK)
-    for (int q = threadIdx.x; q < d.nsc; q += TILE) scm[q] = d.scmask[q];
-  for (int q = threadIdx.x; q < 2 * NW; q += TILE) (&nzb[0][0])[q] = 0u;
+    for (int q = threadIdx.x; q < d.nsc; q += TILE * G) scm[q] = d.scmask[q];
+  for (int q = threadIdx.x; q < G * 2 * NW; q += TILE * G) (&nzb_[0][0][0])[q] = 0u;
   int par = 0;
-  for (int tix = blockIdx.x; tix < d.ntiles; tix += gridDim.x) {
-    const int4 tl = d.tiles[tix];
-    const int i = tl.y + threadIdx.x;
-    const bool live = i < tl.z;
-    const int e0 = d.row_ptr[tl.y], e1 = d.row_ptr[tl.z];
+  for (int tb = blockIdx.x * G; tb < d.ntiles; tb += gridDim.x * G) {
+    const int tix = tb + grp;
+    const bool tv = tix < d.ntiles;
+    const int4 tl = tv ? d.tiles[tix] : make_int4(0, 0, 0, 0);
+    const int i = tl.y + tid;
+    const bool live = tv && i < tl.z;
+    const int e0 = tv ? d.row_ptr[tl.y] : 0, e1 = tv ? d.row_ptr[tl.z] : 0;
     const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
+    const int a0 = e0 & ~3;
+    const int nch = e1 > a0 ? (e1 - a0 + CHUNK - 1) / CHUNK : 0;
     float sum = 0.f;
     uint32_t infected_edges = 0;
     __syncthreads();
-    // chunks start at a multiple of 4 at or below e0; positions below e0 are skipped
-    for (int c0 = e0 & ~3; c0 < e1; c0 += CHUNK, par ^= 1) {
-      const int cn = min(CHUNK, e1 - c0);
-      uint32_t* nz = nzb[par];
+    if (threadIdx.x == 0) nch_max = 0;
+    __syncthreads();
+    if (tid == 0) atomicMax(&nch_max, nch);
+    __syncthreads();
+    const int nc = nch_max;
+    for (int ci = 0; ci < nc; ++ci, par ^= 1) {
+      const int c0 = a0 + ci * CHUNK;
+      const int cn = ci < nch ? min(CHUNK, e1 - c0) : 0;
+      uint32_t* nz = nzb_[grp][par];
       for (int kb = 0; kb < cn; kb += TILE * NE) {
         v4i v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int k = kb + (u * TILE + (int)threadIdx.x) * 4;
+          const int k = kb + (u * TILE + tid) * 4;
           v[u] = k < cn ? __builtin_nontemporal_load((const v4i*)(d.col + c0 + k)) : v4i{0, 0, 0, 0};
         }
         uint32_t src[NE];
@@ -273,7 +286,7 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int l = 0; l < 4; ++l) {
-            const int k = kb + (u * TILE + (int)threadIdx.x) * 4 + l;
+            const int k = kb + (u * TILE + tid) * 4 + l;
             const uint32_t x = (uint32_t)v[u][l];
             src[4 * u + l] = x < (uint32_t)d.N ? x : 0u;
             hit[4 * u + l] = k < cn && c0 + k >= e0;
@@ -290,19 +303,26 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
         for (int q = 0; q < NE; ++q) hit[q] = (cw[q] >> ((src[q] >> 3) & 31u)) & 1u;
 #pragma unroll
         for (int q = 0; q < NE; ++q) cw[q] = hit[q] ? d.imask[src[q] >> 5] : 0u;
+        float wv[NE];
+        uint32_t cd[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-          if ((cw[q] >> (src[q] & 31u)) & 1u) {
-            const int k = kb + ((q >> 2) * TILE + (int)threadIdx.x) * 4 + (q & 3);
-            term[k] = __builtin_nontemporal_load(d.w + c0 + k) * atab[d.code[src[q]]];
+          hit[q] = (cw[q] >> (src[q] & 31u)) & 1u;
+          const int k = kb + ((q >> 2) * TILE + tid) * 4 + (q & 3);
+          wv[q] = hit[q] ? __builtin_nontemporal_load(d.w + c0 + k) : 0.f;
+          cd[q] = hit[q] ? (uint32_t)d.code[src[q]] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          if (hit[q]) {
+            const int k = kb + ((q >> 2) * TILE + tid) * 4 + (q & 3);
+            term[k] = wv[q] * atab[cd[q]];
             atomicOr(&nz[k >> 5], 1u << (k & 31));
             ++infected_edges;
           }
         }
       }
       __syncthreads();
-      // Each row adds its written terms left to right.  Unwritten terms are +0 and
-      // every term is >= 0, so skipping them leaves the left-to-right sum unchanged.
       const int lo = max(rs, c0) - c0, hi = min(re, c0 + cn) - c0;
       for (int wd = lo >> 5; lo < hi && wd <= (hi - 1) >> 5; ++wd) {
         uint32_t bits = nz[wd];
@@ -314,16 +334,16 @@ __global__ __launch_bounds__(TILE) void k_message(Dev d) {
           bits &= bits - 1u;
         }
       }
-      // the other buffer was last read before the previous barrier
-      for (int q = threadIdx.x; q < NW; q += TILE) nzb[par ^ 1][q] = 0u;
+      for (int q = tid; q < NW; q += TILE) nzb_[grp][par ^ 1][q] = 0u;
       __syncthreads();
     }
     if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
     for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
-    if ((threadIdx.x & 63) == 0) ninf[threadIdx.x >> 6] = infected_edges;
+    if ((tid & 63) == 0) ninf_[grp][tid >> 6] = infected_edges;
     __syncthreads();
-    if (threadIdx.x == 0)
-      d.tile_counts[(size_t)tix * TILE_NC + ABM_C_INF_EDGES] = ninf[0] + ninf[1] + ninf[2] + ninf[3];
+    if (tid == 0 && tv)
+      d.tile_counts[(size_t)tix * TILE_NC + ABM_C_INF_EDGES] =
+          ninf_[grp][0] + ninf_[grp][1] + ninf_[grp][2] + ninf_[grp][3];
   }
 }
 
@@ -535,24 +555,36 @@ void launch_vplan(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
 }
 // Message-kernel variants the autotuner chooses from: LDS chunk x grid shape x where
-// the first mask level lives (L2, or LDS for persistent grids when it fits).
-int message_variants() { return 21; }
+// the first mask level lives (L2, or LDS for persistent grids when it fits) x tiles per
+// workgroup (four 256-lane groups share one LDS copy of the mask).
+int message_variants() { return 27; }
 
-void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* ldsmask) {
+void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* shape) {
   static const int chunks[3] = {1024, 2048, 4096};
-  const int shape = v / 3;                       // 0: a workgroup per tile; 1..6 persistent
+  const bool fits = (size_t)d.nsc * 8 <= SCMASK_LDS_MAX;
+  if (v >= 21) {                                 // four tiles per workgroup, mask in LDS
+    const int w = v - 21;
+    *chunk = chunks[w % 2];
+    *grid = std::min((d.ntiles + 3) / 4, 256 << (w / 2));
+    *shape = fits ? 2 : 0;
+    if (!fits) *grid = d.ntiles;
+    return;
+  }
+  const int sh = v / 3;                          // 0: a workgroup per tile; 1..6 persistent
   const int grids[4] = {d.ntiles, 256 * 4, 256 * 8, 256 * 16};
   *chunk = chunks[v % 3];
-  *grid = std::min(d.ntiles, grids[shape == 0 ? 0 : 1 + (shape - 1) % 3]);
-  *ldsmask = (shape >= 4 && (size_t)d.nsc * 8 <= SCMASK_LDS_MAX) ? 1 : 0;
+  *grid = std::min(d.ntiles, grids[sh == 0 ? 0 : 1 + (sh - 1) % 3]);
+  *shape = (sh >= 4 && fits) ? 1 : 0;
 }
 
 template <int C>
 static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
-  if (d.msg_ldsmask)
-    hipLaunchKernelGGL((k_message<C, true>), g, dim3(TILE), (size_t)d.nsc * 8, s, d);
+  if (d.msg_shape == 2)
+    hipLaunchKernelGGL((k_message<C, true, 4>), g, dim3(TILE * 4), (size_t)d.nsc * 8, s, d);
+  else if (d.msg_shape == 1)
+    hipLaunchKernelGGL((k_message<C, true, 1>), g, dim3(TILE), (size_t)d.nsc * 8, s, d);
   else
-    hipLaunchKernelGGL((k_message<C, false>), g, dim3(TILE), 0, s, d);
+    hipLaunchKernelGGL((k_message<C, false, 1>), g, dim3(TILE), 0, s, d);
 }
 
 void launch_message(const Dev& d, hipStream_t s) {

@@ -150,7 +150,7 @@ class Simulator:
 
     def tuning(self) -> dict:
         v = self._get(L.GET_TUNING, np.int32, 3)
-        return {"message_chunk": int(v[0]), "message_grid": int(v[1]), "mask_in_lds": int(v[2])}
+        return {"message_chunk": int(v[0]), "message_grid": int(v[1]), "message_shape": int(v[2])}
 
     def soft_s(self) -> np.ndarray:
         return self._get(L.GET_SOFT_S, np.float32, self.N)

@@ -93,3 +93,12 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         L.lib()
+
+
+def test_relaxed_incidence_rejects_a_wrong_parameter_shape():
+    import torch
+    from paper_2110_04421_amd.autograd import relaxed_incidence
+    from synthpop import workload
+    p, pop = workload(4, n=1000, n_steps=5)
+    with pytest.raises(ValueError):
+        relaxed_incidence(torch.zeros(1, 9, dtype=torch.float64), p, pop, 5)

@@ -106,3 +106,21 @@ def test_grad_before_run_is_an_error():
         with pytest.raises(AbmError) as e:
             s.grad(np.zeros((1, 10), np.float32))
         assert e.value.code == -6
+
+
+def test_autograd_function_gives_the_adjoint_gradient():
+    require_gpu()
+    import torch
+    from paper_2110_04421_amd.autograd import relaxed_incidence
+    T = 30
+    p, pop = workload(4, n=10000, n_steps=T)
+    dL = np.random.default_rng(9).normal(size=(1, T))
+    th0 = np.concatenate([pop.R, pop.susceptibility[0]])[None, :].astype(np.float64)
+    theta = torch.tensor(th0, requires_grad=True)
+    c = relaxed_incidence(theta, p, pop, T)
+    (c.double() * torch.from_numpy(dL)).sum().backward()
+    c_o, cd_o, _ = SoftModel(pop, p).run(T)
+    ok, err = _close(c.detach().numpy().astype(np.float64), c_o, 1e-4)
+    assert ok, f"relaxed incidence rel err {err}"
+    ok, err = _close(theta.grad.numpy(), gradient(cd_o, dL), 1e-3)
+    assert ok, f"autograd gradient rel err {err}"
