@@ -302,6 +302,8 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.nbatch = (z.ntiles + 3) / 4;
   // batches per generation / level-1 workgroup: up to 16, keeping >= 1024 workgroups
   z.bpw = std::max<int64_t>(1, std::min<int64_t>(16, z.nbatch / 1024));
+  // a level-1 workgroup keeps its batches' run offsets in LDS
+  z.bpw = std::max<int64_t>(1, std::min<int64_t>(z.bpw, PB_HS_MAX / std::max<int64_t>(z.nb1, 1) - 1));
   z.ngrid = (z.nbatch + z.bpw - 1) / z.bpw;
   // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048)
   double mo = 0, mr = 0;

@@ -19,6 +19,7 @@ constexpr int MSG_CHUNK = 4096;    // edges staged in LDS per step of the messag
 constexpr int TILE_NC = 16;       // per-tile count row (ABM_NC slots, padded)
 static_assert(ABM_NC <= TILE_NC, "count slots fit a tile row");
 constexpr size_t SCMASK_LDS_MAX = 48 * 1024;   // largest LDS copy of the super-coarse mask
+constexpr int PB_HS_MAX = 9216;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
 enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };

@@ -106,14 +106,18 @@ __device__ __forceinline__ void last_le(const int* s, int n, int g0, int gs, int
 // random draws, each in draw order) and written contiguously to the batch's own list
 // (pb_bcap entries a batch); pb_tbase[tile] is the tile's first entry in it and its
 // number of entries.  The
-// level-1 histograms are stored digit-major (digit * nbatch + batch) for the scan.
+// level-1 histograms (16-bit counters in LDS for all the workgroup's batches) are
+// stored digit-major (digit * nbatch + batch) for the scan.
 __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_gen(Dev d) {
-  extern __shared__ uint32_t stage[];        // [pb_bcap]
+  extern __shared__ uint32_t stage[];        // [pb_bcap] draws, then [pb_bpw][nh2] histograms
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int hist[PB_NB1_MAX];
   __shared__ int wsum[PB_THREADS / 64];
   __shared__ int ntot;
+  // two 16-bit counters a word (a batch has at most pb_bcap <= 24576 draws)
+  const int nh2 = (d.pb_nb1 + 1) >> 1;
+  uint32_t* hist = stage + d.pb_bcap;
   for (int k = threadIdx.x; k < NPT * 64; k += PB_THREADS) T[k] = d.ptab[k];
+  for (int k = threadIdx.x; k < d.pb_bpw * nh2; k += PB_THREADS) hist[k] = 0u;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
   const int s1 = d.pb_lb + 8;
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   for (int j = 0; j < d.pb_bpw; ++j) {
     const int bt = blockIdx.x * d.pb_bpw + j;
     if (bt >= d.pb_nbatch) break;
-    for (int k = tid; k < d.pb_nb1; k += PB_THREADS) hist[k] = 0;
+    uint32_t* h = hist + j * nh2;
     const int tix = bt * 4 + (tid >> 8);
     int i = 0, ko = 0, kr = 0;
     bool live = false;
@@ -167,18 +171,26 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     if (live) {
       go.each(d, ko, [&](int q, int p) {
         stage[off + q - 1] = (uint32_t)p;
-        atomicAdd(&hist[p >> s1], 1);
+        const int dg = p >> s1;
+        atomicAdd(&h[dg >> 1], 1u << (16 * (dg & 1)));
       });
       gr.each(d, kr, [&](int q, int p) {
         stage[off + ko + q - 1] = (uint32_t)p;
-        atomicAdd(&hist[p >> s1], 1);
+        const int dg = p >> s1;
+        atomicAdd(&h[dg >> 1], 1u << (16 * (dg & 1)));
       });
     }
     __syncthreads();
     uint32_t* dst = d.pb_own + (size_t)bt * d.pb_bcap;
     for (int k = tid; k < n; k += PB_THREADS) dst[k] = stage[k];
-    for (int k = tid; k < d.pb_nb1; k += PB_THREADS) d.pb_hist1[(size_t)k * d.pb_nbatch + bt] = hist[k];
     __syncthreads();
+  }
+  // the workgroup's histograms, digit-major: each digit's batches are consecutive
+  const int bt0 = blockIdx.x * d.pb_bpw;
+  const int nb = min(d.pb_bpw, d.pb_nbatch - bt0);
+  for (int k = threadIdx.x; k < d.pb_nb1 * nb; k += PB_THREADS) {
+    const int dg = k / nb, j = k - dg * nb;
+    d.pb_hist1[(size_t)dg * d.pb_nbatch + bt0 + j] = (int)((hist[j * nh2 + (dg >> 1)] >> (16 * (dg & 1))) & 0xFFFFu);
   }
 }
 
@@ -302,6 +314,7 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 // a run is immaterial: the leaf sort orders fully.
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint2 stage[PB_S1_CAP];
+  __shared__ int hs[PB_HS_MAX];                // run offsets: [digit][batch of the workgroup + 1]
   __shared__ int gofs[PB_NB1_MAX], lst[PB_NB1_MAX], lcur[PB_NB1_MAX];
   __shared__ int aoff[PB_THREADS], aid[PB_THREADS], ako[PB_THREADS];
   __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
@@ -310,15 +323,22 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
-  for (int j = 0; j < d.pb_bpw; ++j) {
-    const int bt = blockIdx.x * d.pb_bpw + j;
-    if (bt >= nbt) break;
+  // each digit's offsets for this workgroup's batches (and the next run's start) are
+  // consecutive in the digit-major scan: read them once, nearly contiguously
+  const int bt0 = blockIdx.x * d.pb_bpw;
+  const int nb = min(d.pb_bpw, nbt - bt0), nb1w = nb + 1;
+  for (int k = tid; k < d.pb_nb1 * nb1w; k += PB_THREADS) {
+    const int dg = k / nb1w, j = k - dg * nb1w;
+    hs[k] = d.pb_hist1[(size_t)dg * nbt + bt0 + j];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const int bt = bt0 + j;
     int cntv = 0;
     if (tid < d.pb_nb1) {
-      const size_t q = (size_t)tid * nbt + bt;
-      const int o = d.pb_hist1[q];
+      const int o = hs[tid * nb1w + j];
       gofs[tid] = o;
-      cntv = d.pb_hist1[q + 1] - o;
+      cntv = hs[tid * nb1w + j + 1] - o;
     }
     const int tix = bt * 4 + (tid >> 8);
     int i = 0, ko = 0, c = 0;
@@ -796,6 +816,9 @@ const char* build_step_name(const Dev& d, int k) {
 }
 
 static size_t leaf_lds(const Dev& d) { return (size_t)(d.pb_leaf_cap + (2u << d.pb_lb) + 1) * 4; }
+static size_t gen_lds(const Dev& d) {
+  return ((size_t)d.pb_bcap + (size_t)d.pb_bpw * ((d.pb_nb1 + 1) / 2)) * 4;
+}
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
@@ -803,7 +826,7 @@ hipError_t prepare_build(const Dev& d) {
                                      (int)leaf_lds(d));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_pb_gen, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             d.pb_bcap * 4);
+                             (int)gen_lds(d));
 }
 
 void launch_build_step(const Dev& d, int k, hipStream_t s) {
@@ -818,7 +841,7 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     return;
   }
   switch (k) {
-    case 0: hipLaunchKernelGGL(k_pb_gen, dim3(d.pb_ngrid), dim3(PB_THREADS), (size_t)d.pb_bcap * 4, s, d); break;
+    case 0: hipLaunchKernelGGL(k_pb_gen, dim3(d.pb_ngrid), dim3(PB_THREADS), gen_lds(d), s, d); break;
     case 1:
       hipLaunchKernelGGL(k_pb_s1a, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_part, d.pb_s1_nparts);

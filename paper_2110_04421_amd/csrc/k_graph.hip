@@ -125,14 +125,15 @@ __device__ __forceinline__ uint32_t degree_of(const Dev& d, int i) {
   return (uint32_t)d.hhn[i] - 1u + (o & 0xFFu) + (o >> 8) + (r >> 16) + (r & 0xFFFFu);
 }
 
-// Phase 1: per-block sums of the degrees.
+// Phase 1: per-block sums of the degrees (a block is SCAN_BLOCK agents; the loads go
+// with consecutive lanes on consecutive agents).
 __global__ __launch_bounds__(TILE) void k_scan1(Dev d) {
   __shared__ uint32_t red[TILE / 64];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t i = base + k;
+    const int64_t i = base + (int64_t)k * TILE;
     if (i < d.N) {
       const uint32_t r = d.recv[i];
       if ((r & 0xFFFFu) == 0xFFFFu || (r >> 16) == 0xFFFFu) atomicOr(d.flags, FLAG_RECV_OVERFLOW);
@@ -177,45 +178,46 @@ __global__ __launch_bounds__(1024) void k_scan2(Dev d) {
   }
 }
 
-// Phase 3: row pointers and the claim cursors of the two received blocks.
+// Phase 3: row pointers and the claim cursors of the two received blocks.  Wave w of a
+// block takes SCAN_ITEMS rounds of 64 consecutive agents: a wave scan per round, the
+// round's total carried to the next, so loads and stores stay coalesced.
 __global__ __launch_bounds__(TILE) void k_scan3(Dev d) {
   __shared__ uint32_t wsum[TILE / 64];
   if (*d.flags) return;
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
-  uint32_t deg[SCAN_ITEMS];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t i = base + k;
-    deg[k] = i < d.N ? degree_of(d, (int)i) : 0u;
-    s += deg[k];
-  }
-  // inclusive scan of the thread sums across the wave, then across waves
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t inc = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == 63) wsum[wv] = inc;
-  __syncthreads();
-  uint32_t wbase = 0;
-  for (int k = 0; k < wv; ++k) wbase += wsum[k];
-  int64_t run = d.scan_part[blockIdx.x] + (int64_t)(wbase + inc - s);
+  const int64_t wbase = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)wv * 64 * SCAN_ITEMS;
+  uint32_t deg[SCAN_ITEMS];
+  uint32_t tot = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t i = base + k;
+    const int64_t i = wbase + k * 64 + lane;
+    deg[k] = i < d.N ? degree_of(d, (int)i) : 0u;
+    tot += deg[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+  if (lane == 0) wsum[wv] = tot;
+  __syncthreads();
+  int64_t run = d.scan_part[blockIdx.x];
+  for (int q = 0; q < wv; ++q) run += wsum[q];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    uint32_t inc = deg[k];
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    const int64_t i = wbase + k * 64 + lane;
     if (i < d.N) {
-      const int rp = (int)run;
-      const uint32_t o = d.own[i], r = d.recv[i];
+      const int rp = (int)(run + inc - deg[k]);
       d.row_ptr[i] = rp;
       if (!d.pb_on) {            // claim cursors of the claim-based builder
+        const uint32_t o = d.own[i], r = d.recv[i];
         const int co = rp + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
         d.cur_occ[i] = co;
         d.cur_rand[i] = co + (int)(r >> 16) + (int)(o >> 8);
       }
-      run += deg[k];
     }
+    run += __shfl(inc, 63);
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) d.row_ptr[d.N] = (int)d.scan_part[d.nscan];
 }
