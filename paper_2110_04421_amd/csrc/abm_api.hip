@@ -292,9 +292,9 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
             leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576;
-  // edges of a tile staged in LDS by the row assembly: 1.25x the mean (+512)
+  // edges of a tile staged in LDS by the row assembly: 1.1x the mean (+512)
   const double tile_mean = emean * (double)TILE / (double)N;
-  z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.25 * tile_mean) + 512 + 255) / 256 * 256));
+  z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.1 * tile_mean) + 512 + 255) / 256 * 256));
   if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {
     z.leaf_cap = 1024;
     z.asm_cap = 2048;

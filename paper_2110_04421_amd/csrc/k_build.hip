@@ -311,7 +311,9 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 // the batch's 1024 list starts in LDS).  Entries are counting-sorted by digit into
 // LDS and each run leaves as consecutive lanes on consecutive addresses; a batch with
 // more than PB_S1_CAP entries writes each entry directly to its run.  The order inside
-// a run is immaterial: the leaf sort orders fully.
+// a run is immaterial: the leaf sort orders fully.  The next batch's agent counts and
+// the first rounds of its own list are loaded while the current batch is placed.
+constexpr int PB_S1_PF = 10;           // own-list entries a lane loads for the next batch
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint2 stage[PB_S1_CAP];
   __shared__ int hs[PB_HS_MAX];                // run offsets: [digit][batch of the workgroup + 1]
@@ -323,10 +325,32 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
-  // each digit's offsets for this workgroup's batches (and the next run's start) are
-  // consecutive in the digit-major scan: read them once, nearly contiguously
   const int bt0 = blockIdx.x * d.pb_bpw;
   const int nb = min(d.pb_bpw, nbt - bt0), nb1w = nb + 1;
+  // a batch's agent counts and the first PB_S1_PF rounds of its own list are loaded
+  // one batch ahead, while the previous batch is sorted and written
+  auto fetch = [&](int bt, int& i, uint32_t& o, uint32_t* pv) {
+    const int tix = bt * 4 + (tid >> 8);
+    i = -1;
+    o = 0u;
+    if (tix < d.ntiles) {
+      const int4 tl = d.tiles[tix];
+      const int a = tl.y + (tid & (TILE - 1));
+      if (a < tl.z) {
+        i = a;
+        o = d.own[a];
+      }
+    }
+    const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
+#pragma unroll
+    for (int u = 0; u < PB_S1_PF; ++u) {
+      const int k = u * PB_THREADS + tid;
+      pv[u] = k < d.pb_bcap ? src[k] : 0u;
+    }
+  };
+  int inx;
+  uint32_t onx, pvn[PB_S1_PF];
+  fetch(bt0, inx, onx, pvn);
   for (int k = tid; k < d.pb_nb1 * nb1w; k += PB_THREADS) {
     const int dg = k / nb1w, j = k - dg * nb1w;
     hs[k] = d.pb_hist1[(size_t)dg * nbt + bt0 + j];
@@ -334,27 +358,23 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     const int bt = bt0 + j;
+    const int i = inx;
+    const uint32_t o = onx;
+    uint32_t pv[PB_S1_PF];
+#pragma unroll
+    for (int u = 0; u < PB_S1_PF; ++u) pv[u] = pvn[u];
     int cntv = 0;
     if (tid < d.pb_nb1) {
-      const int o = hs[tid * nb1w + j];
-      gofs[tid] = o;
-      cntv = hs[tid * nb1w + j + 1] - o;
+      const int g = hs[tid * nb1w + j];
+      gofs[tid] = g;
+      cntv = hs[tid * nb1w + j + 1] - g;
     }
-    const int tix = bt * 4 + (tid >> 8);
-    int i = 0, ko = 0, c = 0;
-    if (tix < d.ntiles) {
-      const int4 tl = d.tiles[tix];
-      i = tl.y + (tid & (TILE - 1));
-      if (i < tl.z) {
-        const uint32_t o = d.own[i];
-        ko = (int)(o & 0xFFu);
-        c = ko + (int)(o >> 8);
-      }
-    }
+    const int ko = i >= 0 ? (int)(o & 0xFFu) : 0;
+    const int c = i >= 0 ? ko + (int)(o >> 8) : 0;
     int inc = cntv, inc2 = c;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(inc, o), y2 = __shfl_up(inc2, o);
-      if (lane >= o) {
+    for (int q = 1; q < 64; q <<= 1) {
+      const int y = __shfl_up(inc, q), y2 = __shfl_up(inc2, q);
+      if (lane >= q) {
         inc += y;
         inc2 += y2;
       }
@@ -374,34 +394,46 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       lcur[tid] = wb + inc - cntv;
     }
     aoff[tid] = wb2 + inc2 - c;
-    aid[tid] = i;
+    aid[tid] = i < 0 ? 0 : i;
     ako[tid] = ko;
     if (tid == PB_THREADS - 1) nstage = wb + inc;
     __syncthreads();
+    if (j + 1 < nb) fetch(bt + 1, inx, onx, pvn);
     const int n = nstage;
     const bool staged = n <= PB_S1_CAP;
+    auto place = [&](int k, uint32_t p, int lo) {
+      const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
+      const int dg = (int)(p >> s1);
+      const int slot = atomicAdd(&lcur[dg], 1);
+      const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
+      if (staged) stage[slot] = x;
+      else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+    };
+    {
+      int lane_of[PB_S1_PF];                       // last lane with aoff <= k
+      last_le<PB_S1_PF, PB_THREADS>(aoff, PB_THREADS, tid, PB_THREADS, lane_of);
+#pragma unroll
+      for (int u = 0; u < PB_S1_PF; ++u) {
+        const int k = u * PB_THREADS + tid;
+        if (k >= n) break;
+        place(k, pv[u], lane_of[u]);
+      }
+    }
     const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
-    for (int kb = 0; kb < n; kb += PB_THREADS * PB_UNROLL) {
-      uint32_t pv[PB_UNROLL];                      // all loads first, then their use
+    for (int kb = PB_S1_PF * PB_THREADS; kb < n; kb += PB_THREADS * PB_UNROLL) {
+      uint32_t qv[PB_UNROLL];
 #pragma unroll
       for (int u = 0; u < PB_UNROLL; ++u) {
         const int k = kb + u * PB_THREADS + tid;
-        pv[u] = k < n ? src[k] : 0u;
+        qv[u] = k < n ? src[k] : 0u;
       }
-      int lane_of[PB_UNROLL];                      // last lane with aoff <= k
+      int lane_of[PB_UNROLL];
       last_le<PB_UNROLL, PB_THREADS>(aoff, PB_THREADS, kb + tid, PB_THREADS, lane_of);
 #pragma unroll
       for (int u = 0; u < PB_UNROLL; ++u) {
         const int k = kb + u * PB_THREADS + tid;
         if (k >= n) break;
-        const uint32_t p = pv[u];
-        const int lo = lane_of[u];
-        const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
-        const int dg = (int)(p >> s1);
-        const int slot = atomicAdd(&lcur[dg], 1);
-        const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
-        if (staged) stage[slot] = x;
-        else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+        place(k, qv[u], lane_of[u]);
       }
     }
     __syncthreads();
@@ -665,40 +697,21 @@ __global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu
 
 // ---- P6: assemble each row --------------------------------------------------------
 // Rows of a tile are contiguous in the CSR.  Each lane lays out its row (household,
-// own occupation draws, received occupation, own random draws, received random) and
-// writes its household part.  The tile's own draws (one contiguous range of its
-// batch's own list) and its received lists (one contiguous range of the sorted
-// received lists) are copied by all lanes together, consecutive lanes on consecutive
-// entries; a binary search over the rows' list starts places each entry.  The row is
-// staged in LDS (source id with the network in the top two bits) and the tile's edge
-// range is written with consecutive lanes on consecutive addresses.  A tile with more
-// edges than the LDS room writes directly.
-__device__ __forceinline__ void put_edge(const Dev& d, bool staged, int32_t* scol, int base, int pos,
-                                         int src, int net) {
-  if (staged) {
-    scol[pos - base] = src | (net << 30);
-  } else {
-    d.col[pos] = src;
-    d.w[pos] = net == 0 ? d.w_h : (net == 1 ? d.w_o : d.w_r);
-  }
-}
-
-// Last row j < n whose list starts at or before g (starts nondecreasing, s[0] <= g).
-__device__ __forceinline__ int row_of(const int* s, int n, int g) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int m = (lo + hi) >> 1;
-    if (s[m] <= g) lo = m; else hi = m;
-  }
-  return lo;
-}
-
+// own workplace draws, received workplace, own random draws, received random), writes
+// its household part to the LDS copy of the tile's edge range, and writes into a 16-bit
+// LDS table the position of every entry of its own and received lists.  The tile's own
+// draws (one contiguous range of its batch's own list) and its received lists (one
+// contiguous range of the sorted received lists) are then read with consecutive lanes
+// on consecutive entries, and each entry goes to its tabled position.  The staged row
+// holds the source id with the network in the top two bits; the tile's edge range is
+// written with consecutive lanes on consecutive addresses.  A tile with more edges
+// than the LDS room writes directly.
 __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
-  extern __shared__ int32_t scol[];                  // [pb_asm_cap]
-  __shared__ int rsl[TILE], rol[TILE], prol[TILE], prrl[TILE];   // received lists
-  __shared__ int osl[TILE], okl[TILE], pool[TILE], porl[TILE];   // own draws
+  extern __shared__ int32_t scol[];                  // [pb_asm_cap] staged row, then [pb_asm_cap] u16 positions
   __shared__ int wsum[TILE / 64];
   if (*d.flags) return;
+  const int cap = d.pb_asm_cap;
+  uint16_t* pos_of = reinterpret_cast<uint16_t*>(scol + cap);
   const int tix = blockIdx.x;
   const int4 tl = d.tiles[tix];
   // the tile's two source ranges are known before any row is laid out, so the first
@@ -715,7 +728,7 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     rv[u] = g0 + k < g1 ? (int)d.pb_rsrc[g0 + k] : 0;
   }
   const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
-  const bool staged = end - base <= d.pb_asm_cap;
+  const bool staged = end - base <= cap;
   const int i = tl.y + threadIdx.x;
   const bool live = i < tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -735,29 +748,43 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   __syncthreads();
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
+  // each row's lane writes its household part and, for every entry of its own and
+  // received lists, that entry's position in the tile (network in the top bits)
   if (live) {
     const StaticRec sr = d.srec[i];
     const uint32_t r = d.recv[i];
-    const int ro = (int)(r >> 16);
+    const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
+    const int rs = d.pb_rstart[i] - g0;
     int pos = d.row_ptr[i];
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
-      if (m != i) put_edge(d, staged, scol, base, pos++, m, 0);
-    pool[threadIdx.x] = pos;
-    pos += ko;
-    prol[threadIdx.x] = pos;
-    pos += ro;
-    porl[threadIdx.x] = pos;
-    pos += kr;
-    prrl[threadIdx.x] = pos;
-    osl[threadIdx.x] = wb + inc - c;
-    okl[threadIdx.x] = ko;
-    rsl[threadIdx.x] = d.pb_rstart[i];
-    rol[threadIdx.x] = ro;
+      if (m != i) {
+        if (staged) scol[pos - base] = m;
+        else { d.col[pos] = m; d.w[pos] = d.w_h; }
+        ++pos;
+      }
+    const int os = wb + inc - c;
+    if (staged) {
+      for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q - base) | (1 << 14));
+      pos += ko;
+      for (int q = 0; q < ro; ++q) pos_of[oend + rs + q] = (uint16_t)((pos + q - base) | (1 << 14));
+      pos += ro;
+      for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q - base) | (2 << 14));
+      pos += kr;
+      for (int q = 0; q < rr; ++q) pos_of[oend + rs + ro + q] = (uint16_t)((pos + q - base) | (2 << 14));
+    } else {                                   // direct writes
+      for (int q = 0; q < ko; ++q) { d.col[pos + q] = (int)ob[os + q]; d.w[pos + q] = d.w_o; }
+      pos += ko;
+      for (int q = 0; q < ro; ++q) { d.col[pos + q] = (int)d.pb_rsrc[g0 + rs + q]; d.w[pos + q] = d.w_o; }
+      pos += ro;
+      for (int q = 0; q < kr; ++q) { d.col[pos + q] = (int)ob[os + ko + q]; d.w[pos + q] = d.w_r; }
+      pos += kr;
+      for (int q = 0; q < rr; ++q) { d.col[pos + q] = (int)d.pb_rsrc[g0 + rs + ro + q]; d.w[pos + q] = d.w_r; }
+    }
   }
+  if (!staged) return;
   __syncthreads();
-  const int nlive = tl.z - tl.y;
-  // own draws, then received lists; a lane places all entries of a round after their
-  // loads have been issued together
+  // both lists: consecutive lanes on consecutive entries, each placed by its position
+  const int nr = g1 - g0;
   for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
     if (kb > 0) {
 #pragma unroll
@@ -769,32 +796,29 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u) {
       const int k = kb + u * TILE + (int)threadIdx.x;
-      if (k >= oend) break;
-      const int a = row_of(osl, nlive, k);
-      const int off = k - osl[a];
-      if (off < okl[a]) put_edge(d, staged, scol, base, pool[a] + off, ov[u], 1);
-      else put_edge(d, staged, scol, base, porl[a] + off - okl[a], ov[u], 2);
+      if (k < oend) {
+        const uint32_t p = pos_of[k];
+        scol[p & 0x1FFFu] = ov[u] | (int)((p >> 14) << 30);
+      }
     }
   }
-  for (int gb = g0; gb < g1; gb += TILE * PB_UNROLL) {
-    if (gb > g0) {
+  for (int kb = 0; kb < nr; kb += TILE * PB_UNROLL) {
+    if (kb > 0) {
 #pragma unroll
       for (int u = 0; u < PB_UNROLL; ++u) {
-        const int g = gb + u * TILE + (int)threadIdx.x;
-        rv[u] = g < g1 ? (int)d.pb_rsrc[g] : 0;
+        const int k = kb + u * TILE + (int)threadIdx.x;
+        rv[u] = k < nr ? (int)d.pb_rsrc[g0 + k] : 0;
       }
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u) {
-      const int g = gb + u * TILE + (int)threadIdx.x;
-      if (g >= g1) break;
-      const int a = row_of(rsl, nlive, g);
-      const int off = g - rsl[a];
-      if (off < rol[a]) put_edge(d, staged, scol, base, prol[a] + off, rv[u], 1);
-      else put_edge(d, staged, scol, base, prrl[a] + off - rol[a], rv[u], 2);
+      const int k = kb + u * TILE + (int)threadIdx.x;
+      if (k < nr) {
+        const uint32_t p = pos_of[oend + k];
+        scol[p & 0x1FFFu] = rv[u] | (int)((p >> 14) << 30);
+      }
     }
   }
-  if (!staged) return;
   __syncthreads();
   const float wt[3] = {d.w_h, d.w_o, d.w_r};
   for (int k = threadIdx.x; k < end - base; k += TILE) {
@@ -856,7 +880,7 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
     case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(PB_LEAF_THREADS), leaf_lds(d), s, d); break;
     case 6: launch_scan(d, s); break;
-    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 4, s, d); break;
+    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
   }
 }
 

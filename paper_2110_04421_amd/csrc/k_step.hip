@@ -236,6 +236,7 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
   typedef int v4i __attribute__((ext_vector_type(4)));
   constexpr int U = CHUNK / (TILE * 4) < 4 ? CHUNK / (TILE * 4) : 4;
   constexpr int NE = 4 * U;
+  static_assert(CHUNK == TILE * NE, "a chunk is one round of loads");
   constexpr int NW = CHUNK / 32;
   extern __shared__ unsigned long long scm[];        // super-coarse mask (LDSMASK)
   __shared__ float atab[ATAB];
@@ -269,17 +270,31 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
     if (tid == 0) atomicMax(&nch_max, nch);
     __syncthreads();
     const int nc = nch_max;
+    // a chunk is one round of loads (CHUNK = TILE * NE); the next chunk's sources are
+    // loaded before the current chunk's mask lookups
+    v4i vn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = (u * TILE + tid) * 4;
+      vn[u] = 0 < nch && k < min(CHUNK, e1 - a0) ? __builtin_nontemporal_load((const v4i*)(d.col + a0 + k))
+                                               : v4i{0, 0, 0, 0};
+    }
     for (int ci = 0; ci < nc; ++ci, par ^= 1) {
       const int c0 = a0 + ci * CHUNK;
       const int cn = ci < nch ? min(CHUNK, e1 - c0) : 0;
       uint32_t* nz = nzb_[grp][par];
-      for (int kb = 0; kb < cn; kb += TILE * NE) {
-        v4i v[U];
+      v4i v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = vn[u];
+      if (ci + 1 < nch) {
+        const int c1 = c0 + CHUNK, cn1 = min(CHUNK, e1 - c1);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int k = kb + (u * TILE + tid) * 4;
-          v[u] = k < cn ? __builtin_nontemporal_load((const v4i*)(d.col + c0 + k)) : v4i{0, 0, 0, 0};
+          const int k = (u * TILE + tid) * 4;
+          vn[u] = k < cn1 ? __builtin_nontemporal_load((const v4i*)(d.col + c1 + k)) : v4i{0, 0, 0, 0};
         }
+      }
+      for (int kb = 0; kb < cn; kb += TILE * NE) {
         uint32_t src[NE];
         bool hit[NE];
 #pragma unroll
