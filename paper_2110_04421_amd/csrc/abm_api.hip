@@ -96,7 +96,7 @@ struct Sizes {
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
   int64_t pb_on = 0, lb = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
-  int64_t leaf_cap = 0, asm_cap = 0;
+  int64_t leaf_cap = 0, asm_cap = 0, s1_cap = PB_S1_CAP;
   int64_t fseg = 1;
 };
 
@@ -298,6 +298,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {
     z.leaf_cap = 1024;
     z.asm_cap = 2048;
+    z.s1_cap = 0;
   }
   z.nbatch = (z.ntiles + 3) / 4;
   // batches per generation / level-1 workgroup: up to 16, keeping >= 1024 workgroups
@@ -637,6 +638,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_nleaf = (int32_t)z.nleaf;
     d.pb_leaf_cap = (int32_t)z.leaf_cap;
     d.pb_asm_cap = (int32_t)z.asm_cap;
+    d.pb_s1_cap = (int32_t)z.s1_cap;
     d.pb_ccap = z.ccap;
     d.pb_hist1 = (int32_t*)(ws + o.pb_hist1);
     d.pb_own = (uint32_t*)(ws + o.pb_own);

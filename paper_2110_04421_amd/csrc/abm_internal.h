@@ -19,7 +19,8 @@ constexpr int MSG_CHUNK = 4096;    // edges staged in LDS per step of the messag
 constexpr int TILE_NC = 16;       // per-tile count row (ABM_NC slots, padded)
 static_assert(ABM_NC <= TILE_NC, "count slots fit a tile row");
 constexpr size_t SCMASK_LDS_MAX = 48 * 1024;   // largest LDS copy of the super-coarse mask
-constexpr int PB_HS_MAX = 9216;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
+constexpr int PB_S1_CAP = 12288;  // entries of a batch staged in LDS by the level-1 scatter
+constexpr int PB_HS_MAX = 4608;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
 enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };
@@ -115,7 +116,7 @@ struct Dev {
                                               // shape 0: one tile a workgroup, masks in L2;
                                               // 1: one tile, mask in LDS; 2: four tiles, mask in LDS
   int32_t pb_on, pb_lb, pb_nb1, pb_nbatch, pb_bpw, pb_ngrid, pb_bcap, pb_s1_nparts, pb_maxch, pb_nleaf,
-      pb_leaf_cap, pb_asm_cap;
+      pb_leaf_cap, pb_asm_cap, pb_s1_cap;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nb1][nbatch] + 1: histograms, then run offsets
   uint32_t* pb_own;         // [nbatch][pb_bcap] each batch's own draws, agent order

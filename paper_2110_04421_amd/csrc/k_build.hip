@@ -27,7 +27,6 @@
 namespace abm {
 
 constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles at a time
-constexpr int PB_S1_CAP = 12288;       // entries of a batch staged in LDS by P2
 constexpr int PB_UNROLL = 8;           // loads a lane issues before using them (P2, P6)
 constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
@@ -307,8 +306,8 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 // ---- P2: scatter into level-1 runs ---------------------------------------------------
 // Per batch: its runs' offsets and sizes come from the scanned histograms.  The
 // batch's own list is read with consecutive lanes on consecutive entries; an entry's
-// initiator is the last agent whose list starts at or before it (binary search over
-// the batch's 1024 list starts in LDS).  Entries are counting-sorted by digit into
+// initiator and network come from a 16-bit LDS tag that the initiator's lane wrote
+// for each of its entries.  Entries are counting-sorted by digit into
 // LDS and each run leaves as consecutive lanes on consecutive addresses; a batch with
 // more than PB_S1_CAP entries writes each entry directly to its run.  The order inside
 // a run is immaterial: the leaf sort orders fully.  The next batch's agent counts and
@@ -316,9 +315,10 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 constexpr int PB_S1_PF = 10;           // own-list entries a lane loads for the next batch
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint2 stage[PB_S1_CAP];
+  __shared__ uint16_t tag[PB_S1_CAP];          // own-list entry -> initiator lane | network << 15
   __shared__ int hs[PB_HS_MAX];                // run offsets: [digit][batch of the workgroup + 1]
   __shared__ int gofs[PB_NB1_MAX], lst[PB_NB1_MAX], lcur[PB_NB1_MAX];
-  __shared__ int aoff[PB_THREADS], aid[PB_THREADS], ako[PB_THREADS];
+  __shared__ int aid[PB_THREADS];
   __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
   __shared__ int nstage;
   if (*d.flags) return;
@@ -393,52 +393,59 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       lst[tid] = wb + inc - cntv;
       lcur[tid] = wb + inc - cntv;
     }
-    aoff[tid] = wb2 + inc2 - c;
     aid[tid] = i < 0 ? 0 : i;
-    ako[tid] = ko;
     if (tid == PB_THREADS - 1) nstage = wb + inc;
     __syncthreads();
+    const int nb_n = nstage;
+    const bool staged = nb_n <= d.pb_s1_cap;
+    // each agent's lane tags its own-list entries with its lane and their network
+    if (staged) {
+      const int ao = wb2 + inc2 - c;
+      for (int q = 0; q < c; ++q) tag[ao + q] = (uint16_t)(tid | (q >= ko ? 0x8000 : 0));
+    }
+    __syncthreads();
     if (j + 1 < nb) fetch(bt + 1, inx, onx, pvn);
-    const int n = nstage;
-    const bool staged = n <= PB_S1_CAP;
-    auto place = [&](int k, uint32_t p, int lo) {
-      const uint32_t net = (k - aoff[lo]) < ako[lo] ? 0u : 0x80000000u;
+    auto place = [&](int k, uint32_t p) {
+      const uint32_t tg = tag[k];
+      const uint32_t net = (tg & 0x8000u) << 16;
       const int dg = (int)(p >> s1);
       const int slot = atomicAdd(&lcur[dg], 1);
-      const uint2 x = make_uint2(p, (uint32_t)aid[lo] | net);
-      if (staged) stage[slot] = x;
-      else d.pb_buf1[gofs[dg] + slot - lst[dg]] = x;
+      stage[slot] = make_uint2(p, (uint32_t)aid[tg & 0x3FFu] | net);
     };
-    {
-      int lane_of[PB_S1_PF];                       // last lane with aoff <= k
-      last_le<PB_S1_PF, PB_THREADS>(aoff, PB_THREADS, tid, PB_THREADS, lane_of);
+    if (staged) {
 #pragma unroll
       for (int u = 0; u < PB_S1_PF; ++u) {
         const int k = u * PB_THREADS + tid;
-        if (k >= n) break;
-        place(k, pv[u], lane_of[u]);
+        if (k >= nb_n) break;
+        place(k, pv[u]);
       }
-    }
-    const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
-    for (int kb = PB_S1_PF * PB_THREADS; kb < n; kb += PB_THREADS * PB_UNROLL) {
-      uint32_t qv[PB_UNROLL];
+      const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
+      for (int kb = PB_S1_PF * PB_THREADS; kb < nb_n; kb += PB_THREADS * PB_UNROLL) {
+        uint32_t qv[PB_UNROLL];
 #pragma unroll
-      for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * PB_THREADS + tid;
-        qv[u] = k < n ? src[k] : 0u;
+        for (int u = 0; u < PB_UNROLL; ++u) {
+          const int k = kb + u * PB_THREADS + tid;
+          qv[u] = k < nb_n ? src[k] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < PB_UNROLL; ++u) {
+          const int k = kb + u * PB_THREADS + tid;
+          if (k >= nb_n) break;
+          place(k, qv[u]);
+        }
       }
-      int lane_of[PB_UNROLL];
-      last_le<PB_UNROLL, PB_THREADS>(aoff, PB_THREADS, kb + tid, PB_THREADS, lane_of);
-#pragma unroll
-      for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * PB_THREADS + tid;
-        if (k >= n) break;
-        place(k, qv[u], lane_of[u]);
+    } else if (i >= 0) {                           // a batch beyond the LDS room: direct
+      const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap + (wb2 + inc2 - c);
+      for (int q = 0; q < c; ++q) {
+        const uint32_t p = src[q];
+        const int dg = (int)(p >> s1);
+        const int slot = atomicAdd(&lcur[dg], 1);
+        d.pb_buf1[gofs[dg] + slot - lst[dg]] = make_uint2(p, (uint32_t)i | (q >= ko ? 0x80000000u : 0u));
       }
     }
     __syncthreads();
     if (staged) {
-      for (int k = tid; k < n; k += PB_THREADS) {
+      for (int k = tid; k < nb_n; k += PB_THREADS) {
         const uint2 x = stage[k];
         const int dg = (int)(x.x >> s1);
         d.pb_buf1[gofs[dg] + k - lst[dg]] = x;
