@@ -67,9 +67,9 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         # draws: static record in; counts, own list and histograms out
         "pb_gen": 18.0 * N + 4.0 * C + 4.0 * nbt * nb1,
         "pb_scan1": 12.0 * nbt * nb1,              # histograms read twice, offsets written
-        "pb_scatter1": 2.0 * N + 12.0 * C,         # counts and own list in, (dest, src) out
-        "pb_hist2": 8.0 * C,
-        "pb_scatter2": 16.0 * C,
+        "pb_scatter1": 2.0 * N + 10.0 * C,         # counts and own list in, 6-byte entries out
+        "pb_hist2": 2.0 * C,                       # the 16-bit destination parts
+        "pb_scatter2": 14.0 * C,                   # 6-byte entries in, 8-byte leaf entries out
         "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
         "rowptr": 18.0 * N,
         "pb_assemble": 8.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col + w out

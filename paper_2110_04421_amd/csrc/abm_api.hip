@@ -85,8 +85,8 @@ struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds;
-  size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_buf1,
-      pb_buf2, pb_rsrc, pb_rstart;
+  size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
+      pb_b1w, pb_buf2, pb_rsrc, pb_rstart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
       gtheta, gpart, dL;
 };
@@ -291,7 +291,8 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   const double leaf_mean = rbar * (double)((int64_t)1 << lb);
   z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
-            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576;
+            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
+            N < ((int64_t)1 << 27);   // initiators fit the 27 low bits of a partition word
   // edges of a tile staged in LDS by the row assembly: 1.1x the mean (+512)
   const double tile_mean = emean * (double)TILE / (double)N;
   z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.1 * tile_mean) + 512 + 255) / 256 * 256));
@@ -367,7 +368,8 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_chunks = L.take<int4>(z.maxch);
     o.pb_hist2 = L.take<int32_t>(z.maxch * 256);
     o.pb_leaf = L.take<int32_t>(z.nb1 * 256 + 1);
-    o.pb_buf1 = L.take<uint2>(z.ccap);
+    o.pb_b1h = L.take<uint16_t>(z.ccap);
+    o.pb_b1w = L.take<uint32_t>(z.ccap);
     o.pb_buf2 = L.take<uint2>(z.ccap);
     o.pb_rsrc = L.take<uint32_t>(z.ccap);
     o.pb_rstart = L.take<int32_t>(z.N + 1);
@@ -650,8 +652,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_chunks = (int4*)(ws + o.pb_chunks);
     d.pb_hist2 = (int32_t*)(ws + o.pb_hist2);
     d.pb_leaf = (int32_t*)(ws + o.pb_leaf);
-    d.pb_buf1 = (uint2*)(ws + o.pb_buf1);
+    d.pb_b1h = (uint16_t*)(ws + o.pb_b1h);
+    d.pb_b1w = (uint32_t*)(ws + o.pb_b1w);
     d.pb_buf2 = (uint2*)(ws + o.pb_buf2);
+    d.pb_sh = (int32_t)std::max<int64_t>(0, z.lb - 8);
     d.pb_rsrc = (uint32_t*)(ws + o.pb_rsrc);
     d.pb_rstart = (int32_t*)(ws + o.pb_rstart);
   }

@@ -128,8 +128,14 @@ struct Dev {
   int4* pb_chunks;          // [maxch] {bucket, begin, end, 0}
   int32_t* pb_hist2;        // [maxch][256] histogram, then run offsets
   int32_t* pb_leaf;         // [nb1 * 256 + 1] leaf starts
-  uint2* pb_buf1;           // [ccap] (destination, initiator | network << 31)
+  // level-1 partition, 6 bytes an entry: with dib = destination within its level-1
+  // bucket (lb + 8 bits) and sh = max(0, lb - 8): b1h = dib >> sh,
+  // b1w = initiator | (dib & (2^sh - 1)) << 27 | network << 31
+  uint16_t* pb_b1h;         // [ccap]
+  uint32_t* pb_b1w;         // [ccap]
+  // leaves: (destination within its leaf (lb bits) | network << 15, initiator)
   uint2* pb_buf2;           // [ccap]
+  int32_t pb_sh;
   uint32_t* pb_rsrc;        // [ccap] received initiators, sorted by (dest, network, initiator)
   int32_t* pb_rstart;       // [N + 1] first received entry of each destination; [N] = total
 

@@ -9,7 +9,8 @@
 //   S1  scan        digit-major exclusive scan of the histograms -> each (digit, batch)
 //                   run's offset; level-1 bucket bounds; chunk table.
 //   P2  scatter-1   read the batch's own list, counting-sort its entries
-//                   (dest, src | net) by digit in LDS, write each run contiguously.
+//                   (dest, src | net) by digit in LDS, write each run contiguously
+//                   as 6-byte entries (16-bit destination part, 32-bit source word).
 //   P3  hist-2      per chunk of a level-1 bucket: histogram by level-2 digit.
 //   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
 //   P4  scatter-2   entries into leaves of 2^LB destinations.
@@ -99,6 +100,24 @@ __device__ __forceinline__ void last_le(const int* s, int n, int g0, int gs, int
   }
 }
 
+// The generation pass streams the static records in and its own lists out with
+// nontemporal accesses, so that they do not displace the workplace member lists that
+// its partner draws read at random.
+__device__ __forceinline__ StaticRec load_srec_nt(const StaticRec* p) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const v4i v = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p));
+  StaticRec r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+// Level-1 partition entry of (destination p, initiator | network << 31).
+__device__ __forceinline__ void put_b1(const Dev& d, int pos, uint32_t p, uint32_t w) {
+  const uint32_t dib = p & ((1u << (d.pb_lb + 8)) - 1u);
+  d.pb_b1h[pos] = (uint16_t)(dib >> d.pb_sh);
+  d.pb_b1w[pos] = w | ((dib & ((1u << d.pb_sh) - 1u)) << 27);
+}
+
 // ---- P1: draw each batch's contacts once --------------------------------------------
 // 1024 lanes = one batch of 4 tiles of 256 agents; a workgroup takes pb_bpw batches.
 // The batch's draws are staged in LDS in agent order (own workplace draws, then own
@@ -126,22 +145,28 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     if (bt >= d.pb_nbatch) break;
     uint32_t* h = hist + j * nh2;
     const int tix = bt * 4 + (tid >> 8);
-    int i = 0, ko = 0, kr = 0;
+    // across the barriers a lane keeps only its static record, replicate and the two
+    // count blocks; the generators are rebuilt from them for the partner draws
+    int i = 0, ko = 0, kr = 0, rep = 0;
     bool live = false;
-    Gen go, gr;
+    StaticRec sr{};
+    uint4 bo = make_uint4(0u, 0u, 0u, 0u), br = bo;
     if (tix < d.ntiles) {
       const int4 tl = d.tiles[tix];
       i = tl.y + (tid & (TILE - 1));
       live = i < tl.z;
+      rep = tl.x;
       if (live) {
-        const RepInfo& ri = d.rep[tl.x];
-        const StaticRec sr = d.srec[i];
+        const RepInfo& ri = d.rep[rep];
+        sr = load_srec_nt(d.srec + i);
         const uint32_t loc = (uint32_t)(i - ri.start);
-        go = gen_occ(d, sr, loc, t, ri.stream);
+        Gen go = gen_occ(d, sr, loc, t, ri.stream);
         ko = go.count(T + sr.occ * 64);
-        gr = gen_rand(d, ri, loc, t);
+        bo = go.blk;
+        Gen gr = gen_rand(d, ri, loc, t);
         kr = gr.count(T + (PT_AGE0 + sr.age) * 64);
-        d.own[i] = (uint16_t)(ko | (kr << 8));
+        br = gr.blk;
+        __builtin_nontemporal_store((uint16_t)(ko | (kr << 8)), d.own + i);
       }
     }
     const int c = ko + kr;
@@ -168,6 +193,12 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       return;
     }
     if (live) {
+      const RepInfo& ri = d.rep[rep];
+      const uint32_t loc = (uint32_t)(i - ri.start);
+      Gen go = gen_occ(d, sr, loc, t, ri.stream);
+      go.blk = bo;
+      Gen gr = gen_rand(d, ri, loc, t);
+      gr.blk = br;
       go.each(d, ko, [&](int q, int p) {
         stage[off + q - 1] = (uint32_t)p;
         const int dg = p >> s1;
@@ -181,7 +212,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     }
     __syncthreads();
     uint32_t* dst = d.pb_own + (size_t)bt * d.pb_bcap;
-    for (int k = tid; k < n; k += PB_THREADS) dst[k] = stage[k];
+    for (int k = tid; k < n; k += PB_THREADS) __builtin_nontemporal_store(stage[k], dst + k);
     __syncthreads();
   }
   // the workgroup's histograms, digit-major: each digit's batches are consecutive
@@ -440,7 +471,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
         const uint32_t p = src[q];
         const int dg = (int)(p >> s1);
         const int slot = atomicAdd(&lcur[dg], 1);
-        d.pb_buf1[gofs[dg] + slot - lst[dg]] = make_uint2(p, (uint32_t)i | (q >= ko ? 0x80000000u : 0u));
+        put_b1(d, gofs[dg] + slot - lst[dg], p, (uint32_t)i | (q >= ko ? 0x80000000u : 0u));
       }
     }
     __syncthreads();
@@ -448,7 +479,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       for (int k = tid; k < nb_n; k += PB_THREADS) {
         const uint2 x = stage[k];
         const int dg = (int)(x.x >> s1);
-        d.pb_buf1[gofs[dg] + k - lst[dg]] = x;
+        put_b1(d, gofs[dg] + k - lst[dg], x.x, x.y);
       }
       __syncthreads();
     }
@@ -469,11 +500,11 @@ __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u) {
       const int e = eb + u * TILE + (int)threadIdx.x;
-      x[u] = e < ch.z ? d.pb_buf1[e].x : 0u;
+      x[u] = e < ch.z ? (uint32_t)d.pb_b1h[e] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u)
-      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> d.pb_lb) & 255u], 1);
+      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> (d.pb_lb - d.pb_sh)) & 255u], 1);
   }
   __syncthreads();
   d.pb_hist2[(size_t)c * 256 + threadIdx.x] = hist[threadIdx.x];
@@ -536,17 +567,18 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
   const int tid = threadIdx.x;
   if (tid < 256) cnt[tid] = 0;
   __syncthreads();
-  uint2 x[PB_S2_PER];
+  const int d2s = d.pb_lb - d.pb_sh;          // level-2 digit = (b1h >> d2s) & 255
+  uint2 x[PB_S2_PER];                         // (b1h, b1w)
   int rank[PB_S2_PER];
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    x[j] = k < n ? d.pb_buf1[ch.y + k] : make_uint2(0u, 0u);
+    x[j] = k < n ? make_uint2((uint32_t)d.pb_b1h[ch.y + k], d.pb_b1w[ch.y + k]) : make_uint2(0u, 0u);
   }
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d.pb_lb) & 255u], 1) : 0;
+    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d2s) & 255u], 1) : 0;
   }
   __syncthreads();
   const int v = tid < 256 ? cnt[tid] : 0;
@@ -566,14 +598,17 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    if (k < n) sorted[first[(x[j].x >> d.pb_lb) & 255u] + rank[j]] = x[j];
+    if (k < n) sorted[first[(x[j].x >> d2s) & 255u] + rank[j]] = x[j];
   }
   __syncthreads();
   const int* off = d.pb_hist2 + (size_t)c * 256;
+  const uint32_t lmask = (1u << d.pb_sh) - 1u, dmask = (1u << d.pb_lb) - 1u;
   for (int k = tid; k < n; k += PB_S2_THREADS) {
     const uint2 y = sorted[k];
-    const int dg = (y.x >> d.pb_lb) & 255u;
-    d.pb_buf2[off[dg] + (k - first[dg])] = y;
+    const int dg = (y.x >> d2s) & 255u;
+    const int pos = off[dg] + (k - first[dg]);
+    const uint32_t dib = (y.x << d.pb_sh) | ((y.y >> 27) & lmask);
+    d.pb_buf2[pos] = make_uint2((dib & dmask) | ((y.y >> 31) << 15), y.y & 0x07FFFFFFu);
   }
 }
 
@@ -584,7 +619,7 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 // that each fit; only a single (destination, network) run longer than the cap is an
 // error.
 constexpr int PB_LEAF_THREADS = 512;
-constexpr int PB_LEAF_PER = 16;
+constexpr int PB_LEAF_PER = 12;
 __global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_leaf(Dev d) {
   constexpr int LT = PB_LEAF_THREADS;
   extern __shared__ uint32_t lds[];
@@ -602,7 +637,8 @@ __global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu
   for (int k = tid; k <= nkeys; k += LT) cnt[k] = 0;
   __syncthreads();
   const uint32_t dmask = (1u << d.pb_lb) - 1u;
-  auto key = [&](const uint2& v) { return (int)(((v.x & dmask) << 1) | (v.y >> 31)); };
+  // x = (destination within the leaf | network << 15, initiator)
+  auto key = [&](const uint2& v) { return (int)(((v.x & dmask) << 1) | (v.x >> 15)); };
   uint2 x[PB_LEAF_PER];
 #pragma unroll
   for (int j = 0; j < PB_LEAF_PER; ++j) {
@@ -675,12 +711,12 @@ __global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu
     for (int j = 0; j < PB_LEAF_PER; ++j) {
       const int k = key(x[j]);
       if (lo + j * LT + tid < hi && k >= ka && k < kb)
-        sorted[atomicAdd(&cnt[k], 1) - o_lo] = x[j].y & 0x7FFFFFFFu;
+        sorted[atomicAdd(&cnt[k], 1) - o_lo] = x[j].y;
     }
     for (int e = lo + PB_LEAF_PER * LT + tid; e < hi; e += LT) {
       const uint2 v = d.pb_buf2[e];
       const int k = key(v);
-      if (k >= ka && k < kb) sorted[atomicAdd(&cnt[k], 1) - o_lo] = v.y & 0x7FFFFFFFu;
+      if (k >= ka && k < kb) sorted[atomicAdd(&cnt[k], 1) - o_lo] = v.y;
     }
     __syncthreads();
     for (int k = ka + tid; k < kb; k += LT) {

@@ -594,9 +594,13 @@ void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t
 
 template <int C>
 static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
-  if (d.msg_shape == 2)
-    hipLaunchKernelGGL((k_message<C, true, 4>), g, dim3(TILE * 4), (size_t)d.nsc * 8, s, d);
-  else if (d.msg_shape == 1)
+  if constexpr (C <= 2048) {
+    if (d.msg_shape == 2) {
+      hipLaunchKernelGGL((k_message<C, true, 4>), g, dim3(TILE * 4), (size_t)d.nsc * 8, s, d);
+      return;
+    }
+  }
+  if (d.msg_shape >= 1)
     hipLaunchKernelGGL((k_message<C, true, 1>), g, dim3(TILE), (size_t)d.nsc * 8, s, d);
   else
     hipLaunchKernelGGL((k_message<C, false, 1>), g, dim3(TILE), 0, s, d);
