@@ -201,7 +201,8 @@ enum {
   ABM_GET_TUNING = 12  /* int32[3]: message-kernel LDS chunk (edges), grid (workgroups),
                           shape: 0 one tile per workgroup with the masks in L2, 1 one
                           tile with the first mask level in LDS, 2 four tiles sharing
-                          that LDS mask                                               */
+                          that LDS mask, 3 four tiles with each wave streaming the
+                          edges of 64 rows through its own LDS chunk               */
 };
 /* Copy a device quantity to host (synchronous; h_bytes must be at least its size). */
 int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes);

@@ -52,3 +52,6 @@ def relaxed_incidence(theta, params: dict, pop, days: int):
     """Relaxed daily incidence [R, days] of ``pop`` at parameters ``theta`` [R, 10];
     differentiable in theta through the library's adjoint."""
     return RelaxedIncidence.apply(theta, params, pop, days)
+
+
+ABMFunction = RelaxedIncidence

@@ -362,6 +362,117 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
   }
 }
 
+// Wave-private variant: a workgroup of 16 waves takes 4 tiles, each wave the 64 rows
+// of a quarter tile, whose edges are one contiguous range.  A wave streams its range
+// in WCH-edge chunks through its own LDS terms and bitmap, so only the wave itself
+// touches them and no workgroup barrier is needed until the tiles' counts.
+template <int WCH>
+__global__ __launch_bounds__(1024) void k_message_w(Dev d) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  constexpr int U = WCH / 256;                      // 16-byte loads a lane per chunk
+  constexpr int NE = 4 * U;
+  constexpr int NW = WCH / 32;
+  extern __shared__ unsigned long long scm[];       // super-coarse mask
+  __shared__ float atab[ATAB];
+  __shared__ float term_[16][WCH];
+  __shared__ uint32_t nzb_[16][NW];
+  __shared__ uint32_t ninf_[4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* term = term_[wv];
+  uint32_t* nz = nzb_[wv];
+  if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
+  if (*d.flags) return;
+  for (int q = threadIdx.x; q < d.nsc; q += 1024) scm[q] = d.scmask[q];
+  __syncthreads();
+  for (int tb = blockIdx.x * 4; tb < d.ntiles; tb += gridDim.x * 4) {
+    const int tix = tb + (wv >> 2);
+    if (threadIdx.x < 4) ninf_[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t infected_edges = 0;
+    if (tix < d.ntiles) {
+      const int4 tl = d.tiles[tix];
+      const int r0 = tl.y + 64 * (wv & 3), r1 = min(tl.z, r0 + 64);
+      if (r0 < r1) {
+        const int i = r0 + lane;
+        const bool live = i < r1;
+        const int e0 = d.row_ptr[r0], e1 = d.row_ptr[r1];
+        const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
+        float sum = 0.f;
+        for (int c0 = e0 & ~3; c0 < e1; c0 += WCH) {
+          const int cn = min(WCH, e1 - c0);
+          for (int q = lane; q < NW; q += 64) nz[q] = 0u;
+          v4i v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = (u * 64 + lane) * 4;
+            v[u] = k < cn ? __builtin_nontemporal_load((const v4i*)(d.col + c0 + k)) : v4i{0, 0, 0, 0};
+          }
+          uint32_t src[NE];
+          bool hit[NE];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              const int k = (u * 64 + lane) * 4 + l;
+              const uint32_t x = (uint32_t)v[u][l];
+              src[4 * u + l] = x < (uint32_t)d.N ? x : 0u;
+              hit[4 * u + l] = k < cn && c0 + k >= e0 &&
+                               ((scm[src[4 * u + l] >> 14] >> ((src[4 * u + l] >> 8) & 63u)) & 1ull);
+            }
+          uint32_t cw[NE];
+#pragma unroll
+          for (int q = 0; q < NE; ++q) cw[q] = hit[q] ? d.cmask[src[q] >> 8] : 0u;
+#pragma unroll
+          for (int q = 0; q < NE; ++q) hit[q] = (cw[q] >> ((src[q] >> 3) & 31u)) & 1u;
+#pragma unroll
+          for (int q = 0; q < NE; ++q) cw[q] = hit[q] ? d.imask[src[q] >> 5] : 0u;
+          float wvv[NE];
+          uint32_t cd[NE];
+#pragma unroll
+          for (int q = 0; q < NE; ++q) {
+            hit[q] = (cw[q] >> (src[q] & 31u)) & 1u;
+            const int k = ((q >> 2) * 64 + lane) * 4 + (q & 3);
+            wvv[q] = hit[q] ? __builtin_nontemporal_load(d.w + c0 + k) : 0.f;
+            cd[q] = hit[q] ? (uint32_t)d.code[src[q]] : 0u;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int q = 0; q < NE; ++q) {
+            if (hit[q]) {
+              const int k = ((q >> 2) * 64 + lane) * 4 + (q & 3);
+              term[k] = wvv[q] * atab[cd[q]];
+              atomicOr(&nz[k >> 5], 1u << (k & 31));
+              ++infected_edges;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const int lo = max(rs, c0) - c0, hi = min(re, c0 + cn) - c0;
+          for (int wd = lo >> 5; lo < hi && wd <= (hi - 1) >> 5; ++wd) {
+            uint32_t bits = nz[wd];
+            const int b0 = wd << 5;
+            if (lo > b0) bits &= ~0u << (lo - b0);
+            if (hi < b0 + 32) bits &= (1u << (hi - b0)) - 1u;
+            while (bits) {
+              sum += term[b0 + __builtin_ctz(bits)];
+              bits &= bits - 1u;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
+      }
+      for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
+      if (lane == 0) atomicAdd(&ninf_[wv >> 2], infected_edges);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && tb + (int)threadIdx.x < d.ntiles)
+      d.tile_counts[(size_t)(tb + threadIdx.x) * TILE_NC + ABM_C_INF_EDGES] = ninf_[threadIdx.x];
+  }
+}
+
 // ---- fused day step ---------------------------------------------------------------
 __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
   __shared__ int wpre[TILE / 64];
@@ -572,11 +683,19 @@ void launch_vplan(const Dev& d, hipStream_t s) {
 // Message-kernel variants the autotuner chooses from: LDS chunk x grid shape x where
 // the first mask level lives (L2, or LDS for persistent grids when it fits) x tiles per
 // workgroup (four 256-lane groups share one LDS copy of the mask).
-int message_variants() { return 27; }
+int message_variants() { return 33; }
 
 void message_variant(const Dev& d, int v, int32_t* chunk, int32_t* grid, int32_t* shape) {
   static const int chunks[3] = {1024, 2048, 4096};
   const bool fits = (size_t)d.nsc * 8 <= SCMASK_LDS_MAX;
+  if (v >= 27) {                                 // wave-private chunks, four tiles a workgroup
+    const int w = v - 27;
+    *chunk = w % 2 ? 512 : 256;
+    *grid = std::min((d.ntiles + 3) / 4, 256 << (w / 2));
+    *shape = fits ? 3 : 0;
+    if (!fits) *grid = d.ntiles;
+    return;
+  }
   if (v >= 21) {                                 // four tiles per workgroup, mask in LDS
     const int w = v - 21;
     *chunk = chunks[w % 2];
@@ -608,6 +727,13 @@ static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
 
 void launch_message(const Dev& d, hipStream_t s) {
   const dim3 g(d.msg_grid > 0 ? d.msg_grid : d.ntiles);
+  if (d.msg_shape == 3) {
+    if (d.msg_chunk == 256)
+      hipLaunchKernelGGL(k_message_w<256>, g, dim3(1024), (size_t)d.nsc * 8, s, d);
+    else
+      hipLaunchKernelGGL(k_message_w<512>, g, dim3(1024), (size_t)d.nsc * 8, s, d);
+    return;
+  }
   switch (d.msg_chunk) {
     case 1024: launch_msg<1024>(d, g, s); break;
     case 2048: launch_msg<2048>(d, g, s); break;

@@ -234,4 +234,5 @@ def test_autotuned_tiling_gives_identical_results():
     assert np.array_equal(outs[0][1], outs[1][1])
     assert np.array_equal(outs[0][2].view(np.uint32), outs[1][2].view(np.uint32))
     t = outs[1][3]
-    assert t["message_chunk"] in (1024, 2048, 4096) and 1 <= t["message_grid"]
+    assert t["message_chunk"] in (256, 512, 1024, 2048, 4096) and 1 <= t["message_grid"]
+    assert t["message_shape"] in (0, 1, 2, 3)
