@@ -382,21 +382,57 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
   uint32_t* nz = nzb_[wv];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
-  for (int q = threadIdx.x; q < d.nsc; q += 1024) scm[q] = d.scmask[q];
-  __syncthreads();
-  for (int tb = blockIdx.x * 4; tb < d.ntiles; tb += gridDim.x * 4) {
+  // A wave's row bounds, row pointers and coefficient for the next workgroup iteration
+  // (and the tile bounds for the one after) are loaded while the current one runs, and
+  // are taken into registers before its stores: a load used only after a store waits
+  // for that store as well.
+  struct Rows {
+    int r0, r1, e0, e1, rs, re, rep, age;
+  };
+  const int stride = gridDim.x * 4;
+  auto tile_of = [&](int tb) {
     const int tix = tb + (wv >> 2);
+    return tix < d.ntiles ? d.tiles[tix] : make_int4(0, 0, 0, 0);
+  };
+  auto rows_of = [&](const int4& tl) {          // every index clamped into its array
+    Rows r;
+    r.r0 = tl.y + 64 * (wv & 3);
+    r.r1 = min(tl.z, r.r0 + 64);
+    const int i = min(r.r0 + lane, d.N - 1);
+    r.e0 = d.row_ptr[min(r.r0, d.N)];
+    r.e1 = d.row_ptr[min(max(r.r1, 0), d.N)];
+    r.rs = d.row_ptr[i];
+    r.re = d.row_ptr[i + 1];
+    r.rep = tl.x;
+    // the aligned word holding the age byte (the age array is padded to 256 bytes);
+    // the byte is extracted only where it is used
+    r.age = (int)*reinterpret_cast<const uint32_t*>(d.age + (i & ~3));
+    return r;
+  };
+  auto hold = [&](const Rows& r, const int4& t) {
+    asm volatile("" ::"v"(r.r0), "v"(r.r1), "v"(r.e0), "v"(r.e1), "v"(r.rs), "v"(r.re), "v"(r.age));
+    asm volatile("" ::"v"(t.x), "v"(t.y), "v"(t.z));
+  };
+  for (int q = threadIdx.x; q < d.nsc; q += 1024) scm[q] = d.scmask[q];
+  Rows nxt = rows_of(tile_of(blockIdx.x * 4));
+  int4 tln = tile_of(blockIdx.x * 4 + stride);
+  hold(nxt, tln);
+  __syncthreads();
+  for (int tb = blockIdx.x * 4; tb < d.ntiles; tb += stride) {
+    const int tix = tb + (wv >> 2);
+    const Rows R = nxt;
+    nxt = rows_of(tln);
+    tln = tile_of(tb + 2 * stride);
     if (threadIdx.x < 4) ninf_[threadIdx.x] = 0u;
     __syncthreads();
     uint32_t infected_edges = 0;
     if (tix < d.ntiles) {
-      const int4 tl = d.tiles[tix];
-      const int r0 = tl.y + 64 * (wv & 3), r1 = min(tl.z, r0 + 64);
+      const int r0 = R.r0, r1 = R.r1;
       if (r0 < r1) {
         const int i = r0 + lane;
         const bool live = i < r1;
-        const int e0 = d.row_ptr[r0], e1 = d.row_ptr[r1];
-        const int rs = live ? d.row_ptr[i] : 0, re = live ? d.row_ptr[i + 1] : 0;
+        const int e0 = R.e0, e1 = R.e1;
+        const int rs = live ? R.rs : 0, re = live ? R.re : 0;
         float sum = 0.f;
         for (int c0 = e0 & ~3; c0 < e1; c0 += WCH) {
           const int cn = min(WCH, e1 - c0);
@@ -462,11 +498,13 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
           __builtin_amdgcn_wave_barrier();
         }
-        if (live) d.lambda[i] = d.rep[tl.x].coef[d.age[i]] * sum;
+        hold(nxt, tln);
+        if (live) d.lambda[i] = d.rep[R.rep].coef[((uint32_t)R.age >> (8 * (min(i, d.N - 1) & 3))) & 0xFFu] * sum;
       }
       for (int o = 32; o > 0; o >>= 1) infected_edges += __shfl_xor(infected_edges, o);
       if (lane == 0) atomicAdd(&ninf_[wv >> 2], infected_edges);
     }
+    hold(nxt, tln);
     __syncthreads();
     if (threadIdx.x < 4 && tb + (int)threadIdx.x < d.ntiles)
       d.tile_counts[(size_t)(tb + threadIdx.x) * TILE_NC + ABM_C_INF_EDGES] = ninf_[threadIdx.x];
