@@ -77,7 +77,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 8.0 * E + 8.0 * C + 24.0 * N,
         "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
         # agent kernels
-        "pre": (22.0 if vacc else 21.0) * N,       # state in, code + counters out
+        "pre": (18.0 if vacc else 17.0) * N,       # state in, code out (age in with vaccination)
         "mask": 1.125 * N,
         "fused": 37.0 * N,                         # state in/out, lambda, age
     }

@@ -89,7 +89,6 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
     if ((a.stage == ABM_STAGE_E || a.stage == ABM_STAGE_I) && t >= (int)a.q_until)
       c = (uint8_t)(t - (int)a.t_exp);
     d.code[i] = c;
-    d.recv[i] = 0u;
     if (a.flags != a0.flags || a.q_until != a0.q_until) d.state[i] = a;
     if (d.vacc_on) atomicAdd(&hist[vacc_bucket(d, a, t, d.age[i], ri.delay)], 1);
   }
