@@ -185,6 +185,15 @@ int abm_run(abm_sim* s, int32_t n_days, int64_t* h_counts, float* h_soft_inciden
  * checkpoints kept every checkpoint_every days; writes h_dtheta [R][ABM_N_THETA]. */
 int abm_grad(abm_sim* s, const float* h_dL, float* h_dtheta);
 
+/* Soft mode: replace every replicate's parameters theta = (R, S_0..S_8) with
+ * h_theta [R][ABM_N_THETA] (host array, copied; each value finite and > 0, else
+ * ABM_E_ARG) and rewind to day 0 with the initial state, so that the next abm_run
+ * starts over at the new parameters (same population, seeds and Philox streams).
+ * This is what an iterative fit of theta through abm_grad calls between steps
+ * (section 6 of the paper names calibration by gradients as the direction beyond
+ * grid search); it allocates nothing.  ABM_E_STATE in hard mode. */
+int abm_set_theta(abm_sim* s, const float* h_theta);
+
 enum {
   ABM_GET_STATE = 0,   /* abm_agent_state[N]                                          */
   ABM_GET_LAMBDA = 1,  /* float[N]: force of infection of the last day run           */

@@ -81,6 +81,7 @@ def lib():
         "abm_step": (C.c_int, [vp, i32]),
         "abm_run": (C.c_int, [vp, i32, vp, vp]),
         "abm_grad": (C.c_int, [vp, vp, vp]),
+        "abm_set_theta": (C.c_int, [vp, vp]),
         "abm_get": (C.c_int, [vp, i32, vp, sz]),
         "abm_set_state": (C.c_int, [vp, i32, vp, vp, sz]),
         "abm_sync": (C.c_int, [vp]),
@@ -107,7 +108,7 @@ def lib():
 
 def exported_symbols():
     """Names the header declares (checked against the shared library by the tests)."""
-    return ["abm_workspace_size", "abm_create", "abm_step", "abm_run", "abm_grad", "abm_get",
+    return ["abm_workspace_size", "abm_create", "abm_step", "abm_run", "abm_grad", "abm_set_theta", "abm_get",
             "abm_set_state", "abm_sync", "abm_destroy", "abm_error_string", "abm_last_error",
             "abm_profile_kernels", "abm_profile_name", "abm_profile_get", "abm_profile_reset",
             "abm_philox", "abm_mlp_workspace_size", "abm_mlp_forward", "abm_mlp_backward",

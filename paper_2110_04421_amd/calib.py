@@ -6,7 +6,10 @@ The paper leaves calibration from aggregate data as the direction beyond grid se
 the BF16 matrix-core network learns the inverse map; a prediction is judged by
 re-simulating the plain simulator at the predicted parameters (independent Philox
 stream) and measuring the relative L2 distance to the target curve.  Grid search over
-R (S at its reference profile) is the fallback and the baseline.
+R (S at its reference profile), and over R times one susceptibility shared by all age
+groups, is the fallback and the baseline.  Gradient descent through the relaxed
+simulator's adjoint (``gd_fit``), from the training mean and from the network's
+prediction, is the third method.
 
     python -m paper_2110_04421_amd.calib --train 50000 --heldout 1000 --agents 100000
 """
@@ -162,8 +165,81 @@ def grid_fit(grid_curves, grid_theta, targets):
     return grid_theta[np.argmin(d, 1)]
 
 
+def grid2_thetas(n_r=21, n_s=11):
+    """Two-dimensional grid: R over [3, 7] times one susceptibility shared by every age
+    group over [0.35, 1.47]."""
+    R, S = np.meshgrid(np.linspace(R_LO, R_HI, n_r), np.linspace(S_LO, S_HI, n_s), indexing="ij")
+    return np.concatenate([R.reshape(-1, 1), np.repeat(S.reshape(-1, 1), 9, 1)], 1)
+
+
+def curve_loss(c, target):
+    """Per-curve loss mean_t (log1p c - log1p c*)^2 and its derivative in c."""
+    c = np.maximum(np.asarray(c, np.float64), 0.0)
+    dz = np.log1p(c) - np.log1p(np.asarray(target, np.float64))
+    T = c.shape[1]
+    return (dz ** 2).mean(1), 2.0 * dz / (1.0 + c) / T
+
+
+def gd_fit(params, base_pop, targets, theta0, seed, stream0=0, iters=30, lr=0.05, days=180,
+           batch=256, tau=0.1, log=None):
+    """Fit (R, S_0..S_8) to each hard incidence curve by gradient descent through the
+    relaxed simulator's adjoint (abm_grad).
+
+    Target r is fitted on its own Philox stream (seed, stream0 + r), so the relaxed run
+    shares the noise of the run that made the curve.  Adam on the unit scale, projected
+    onto [0, 1], with the step decaying geometrically to a tenth of ``lr`` over the
+    iterations; the loss is ``curve_loss`` of the relaxed incidence.  The relaxation
+    temperature ``tau`` is kept small: the relaxed infection mass of an agent with a
+    small p averages about p * pi tau / sin(pi tau) (1.57 p at tau = 0.5, 1.02 p at
+    tau = 0.1), so a warm relaxation fits a different epidemic.  One soft
+    simulator per batch of targets, rewound with new parameters (abm_set_theta) at
+    every step.  Returns the iterate of lowest loss per target, the mean loss per step
+    and the mean over targets of each one's lowest loss."""
+    import dataclasses
+    from synthpop import replicate_population
+    from .sim import Simulator
+    targets = np.asarray(targets, np.float64)
+    theta0 = np.asarray(theta0, np.float64)
+    n = targets.shape[0]
+    scale = np.array([R_HI - R_LO] + [S_HI - S_LO] * 9)
+    p = dict(params, seed=int(seed), n_steps=days, mode=L.SOFT, gumbel_tau=float(tau))
+    best_th = theta0.copy()
+    best_all = np.zeros(n)
+    hist = np.zeros(iters)
+    for b0 in range(0, n, batch):
+        b1 = min(n, b0 + batch)
+        pop = dataclasses.replace(replicate_population(base_pop, b1 - b0),
+                                  R=theta0[b0:b1, 0].astype(np.float32),
+                                  susceptibility=theta0[b0:b1, 1:].astype(np.float32),
+                                  stream=(stream0 + np.arange(b0, b1)).astype(np.uint32))
+        u = to_unit(theta0[b0:b1])
+        m = np.zeros_like(u)
+        v = np.zeros_like(u)
+        best = np.full(b1 - b0, np.inf)
+        with Simulator(p, pop) as sim:
+            for it in range(iters):
+                th = from_unit(u)
+                sim.set_theta(th)
+                c = sim.run(days)
+                loss, dl = curve_loss(c, targets[b0:b1])
+                better = loss < best
+                best[better] = loss[better]
+                best_th[b0:b1][better] = th[better]
+                hist[it] += loss.sum()
+                g = sim.grad(dl.astype(np.float32)).astype(np.float64) * scale
+                m = 0.9 * m + 0.1 * g
+                v = 0.999 * v + 0.001 * g * g
+                mh, vh = m / (1 - 0.9 ** (it + 1)), v / (1 - 0.999 ** (it + 1))
+                step = lr * 0.1 ** (it / max(1, iters - 1))
+                u = np.clip(u - step * mh / (np.sqrt(vh) + 1e-8), 0.0, 1.0)
+        best_all[b0:b1] = best
+        if log:
+            log(f"gradient fit {b1}/{n}: mean loss {best.mean():.4f}")
+    return best_th, hist / n, float(best_all.mean())
+
+
 def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, batch=256,
-        log=None, tol=None):
+        log=None, tol=None, n_gd=256, gd_iters=30):
     """The whole calibration study; returns a summary dict.
 
     Held-out targets: seed 2, stream words 0..n-1.  Each prediction is re-simulated
@@ -191,11 +267,16 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
     th_grid = grid_fit(c_grid, gt, c_ho)
     t_grid = time.perf_counter() - t0
     th_mean = np.tile(th_tr.mean(0), (n_heldout, 1))
+    g2 = grid2_thetas()
+    t0 = time.perf_counter()
+    th_grid2 = grid_fit(simulate_curves(p, pop, g2, seed=4, days=days, batch=batch), g2, c_ho)
+    t_grid2 = time.perf_counter() - t0
     sim = lambda th, seed: simulate_curves(p, pop, th, seed=seed, days=days, batch=batch)
     e_ind = {k: rel_l2(sim(th, 3), c_ho) for k, th in
-             (("mlp", th_mlp), ("grid", th_grid), ("true_params", th_ho), ("training_mean_params", th_mean))}
+             (("mlp", th_mlp), ("grid", th_grid), ("grid2d", th_grid2), ("true_params", th_ho),
+              ("training_mean_params", th_mean))}
     e_crn = {k: rel_l2(sim(th, 2), c_ho) for k, th in
-             (("mlp", th_mlp), ("grid", th_grid), ("training_mean_params", th_mean))}
+             (("mlp", th_mlp), ("grid", th_grid), ("grid2d", th_grid2), ("training_mean_params", th_mean))}
     unit = lambda th: float(np.sqrt(((to_unit(th) - to_unit(th_ho)) ** 2).mean()))
     rmse_R = lambda th: float(np.sqrt(((th[:, 0] - th_ho[:, 0]) ** 2).mean()))
     summary = dict(
@@ -204,10 +285,37 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
         resim_rel_l2_independent_stream={k: float(v.mean()) for k, v in e_ind.items()},
         resim_rel_l2_same_stream={k: float(v.mean()) for k, v in e_crn.items()},
         resim_rel_l2_same_stream_median={k: float(np.median(v)) for k, v in e_crn.items()},
-        param_rmse_unit=dict(mlp=unit(th_mlp), grid=unit(th_grid), training_mean=unit(th_mean)),
-        R_rmse=dict(mlp=rmse_R(th_mlp), grid=rmse_R(th_grid), training_mean=rmse_R(th_mean)),
+        param_rmse_unit=dict(mlp=unit(th_mlp), grid=unit(th_grid), grid2d=unit(th_grid2),
+                             training_mean=unit(th_mean)),
+        R_rmse=dict(mlp=rmse_R(th_mlp), grid=rmse_R(th_grid), grid2d=rmse_R(th_grid2),
+                    training_mean=rmse_R(th_mean)),
         seconds=dict(training_data=t_data, training=t_train, mlp_predict=t_pred,
-                     grid_search=t_grid))
+                     grid_search=t_grid, grid2d_search=t_grid2))
+    if n_gd > 0:
+        # gradient descent through the adjoint on the first n_gd held-out curves, from
+        # the training mean and from the network's prediction
+        k = min(n_gd, n_heldout)
+        gd = {}
+        for name, th0 in (("gd_from_mean", th_mean[:k]), ("gd_from_mlp", th_mlp[:k]),
+                          ("gd_from_grid2d", th_grid2[:k])):
+            t0 = time.perf_counter()
+            th, h, lbest = gd_fit(p, pop, c_ho[:k], th0, seed=2, iters=gd_iters, days=days, batch=batch,
+                                  log=log)
+            gd[name] = dict(seconds=time.perf_counter() - t0, loss_first=float(h[0]), loss_best=lbest,
+                            theta=th)
+        sub = {"mlp": th_mlp[:k], "grid": th_grid[:k], "grid2d": th_grid2[:k],
+               "training_mean_params": th_mean[:k]}
+        sub.update({n_: v["theta"] for n_, v in gd.items()})
+        e_sub = {n_: rel_l2(simulate_curves(p, pop, th, seed=2, days=days, batch=batch), c_ho[:k])
+                 for n_, th in sub.items()}
+        summary["gradient_descent"] = dict(
+            targets=k, iterations=gd_iters,
+            resim_rel_l2_same_stream={n_: float(v.mean()) for n_, v in e_sub.items()},
+            resim_rel_l2_same_stream_median={n_: float(np.median(v)) for n_, v in e_sub.items()},
+            param_rmse_unit={n_: float(np.sqrt(((to_unit(th) - to_unit(th_ho[:k])) ** 2).mean()))
+                             for n_, th in sub.items()},
+            relaxed_loss_start_and_best={n_: (v["loss_first"], v["loss_best"]) for n_, v in gd.items()},
+            seconds={n_: v["seconds"] for n_, v in gd.items()})
     if tol is not None:
         # fallback: where the network's re-simulation misses the target by more than tol,
         # grid search runs as well and the better of the two fits is kept
@@ -226,10 +334,13 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--days", type=int, default=180)
     ap.add_argument("--tol", type=float, default=0.5)
+    ap.add_argument("--gd-targets", type=int, default=256)
+    ap.add_argument("--gd-iters", type=int, default=30)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(f"[calib {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
-    s = run(a.train, a.heldout, a.agents, a.epochs, a.days, log=log, tol=a.tol)
+    s = run(a.train, a.heldout, a.agents, a.epochs, a.days, log=log, tol=a.tol, n_gd=a.gd_targets,
+            gd_iters=a.gd_iters)
     txt = json.dumps(s, indent=1)
     print(txt)
     if a.out:

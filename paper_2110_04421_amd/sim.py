@@ -110,6 +110,14 @@ class Simulator:
         self._check(self._lib.abm_grad(self._h, dL.ctypes.data, out.ctypes.data))
         return out
 
+    def set_theta(self, theta):
+        """Soft mode: new (R, S_0..S_8) per replicate [R, 10] and a rewind to day 0, so
+        that the next run starts over at these parameters."""
+        th = np.ascontiguousarray(theta, np.float32)
+        if th.shape != (self.R, L.N_THETA):
+            raise ValueError(f"theta must be [{self.R}, {L.N_THETA}], got {th.shape}")
+        self._check(self._lib.abm_set_theta(self._h, th.ctypes.data))
+
     def sync(self):
         self._check(self._lib.abm_sync(self._h))
 

@@ -1,0 +1,100 @@
+"""The paper's vaccination case study (section 5), run on a synthetic population.
+
+Section 5 compares three age-prioritised dosing strategies (Table 1: standard dosing,
+delayed second dose, delayed second dose except the 65+) over 15 replicates of 180
+days of a 100,000-agent population, starting vaccination once 1 % of the population is
+infected, with ten initial infections.  Two sweeps are reported there: first-dose
+efficacy 60-90 % at 0.3 % of the population vaccinated a day, and 0.1 / 0.3 / 1 % a
+day at 80 % first-dose efficacy; the second dose gives 95 %.  The outcome compared is
+cumulative mortality (quartiles over the replicates).
+
+Here each configuration is one batched launch of the 15 replicates (Philox stream
+words 0..14 shared by every configuration, so configurations differ only by the
+parameters: common random numbers), on the plain-100k synthetic population with its
+testing and quarantine settings and R raised so that vaccination starts near day 20.  The disease model is this implementation's SEIRM
+reading, not the paper's eleven-stage model, and the population is synthetic, so the
+numbers are comparable between strategies, not with the paper's figures.
+
+    python -m paper_2110_04421_amd.study --out study.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import _lib as L
+
+STRATEGIES = {0: "standard", 1: "delayed_second_dose", 2: "delayed_except_65plus"}
+
+
+def run_config(params, pop, days):
+    """Cumulative deaths, cumulative infections, doses given and the day vaccination
+    started (-1: never), per replicate."""
+    from .sim import Simulator
+    with Simulator(dict(params, n_steps=days), pop) as s:
+        c = s.run(days)
+    deaths = c[-1, :, L.C_M]
+    infected = pop.sizes() - c[-1, :, L.C_S]
+    d1 = c[:, :, L.C_DOSE1]
+    doses = d1.sum(0) + c[:, :, L.C_DOSE2].sum(0)
+    start = np.where(d1.any(0), d1.argmax(0), -1)
+    return deaths, infected, doses, start
+
+
+def quartiles(x):
+    return [float(v) for v in np.percentile(np.asarray(x, np.float64), [25, 50, 75])]
+
+
+def vaccine_study(n_agents=100_000, reps=15, days=180, effs=(0.6, 0.7, 0.8, 0.9),
+                  rates=(0.001, 0.003, 0.01), base_rate=0.003, base_eff=0.8, R=13.0, log=None):
+    """Both sweeps.  ``R`` is chosen so that, as section 5 states, the 1 % prevalence
+    that starts vaccination is reached around day 20 (median day 20 at R = 13 on this
+    population; at the plain-100k value 5.18 it comes near day 118)."""
+    import dataclasses
+    from synthpop import workload
+    p, pop = workload(1, n=n_agents, n_rep=reps)
+    pop = dataclasses.replace(pop, R=np.full(reps, R, np.float32))
+    p = dict(p, eff2=0.95, vacc_trigger=0.01)
+    out = {"agents": n_agents, "replicates": reps, "days": days, "R": R, "efficacy_sweep": [],
+           "rate_sweep": []}
+    t0 = time.perf_counter()
+    for sweep, values, key in (("efficacy_sweep", effs, "eff1"), ("rate_sweep", rates, "vacc_rate")):
+        for v in values:
+            for strat, name in STRATEGIES.items():
+                q = dict(p, strategy=strat, eff1=base_eff, vacc_rate=base_rate)
+                q[key] = float(v)
+                deaths, infected, doses, start = run_config(q, pop, days)
+                out[sweep].append({"strategy": name, "eff1": q["eff1"], "vacc_rate": q["vacc_rate"],
+                                   "deaths_quartiles": quartiles(deaths),
+                                   "infected_quartiles": quartiles(infected),
+                                   "doses_mean": float(doses.mean()),
+                                   "vaccination_start_day_median": float(np.median(start))})
+                if log:
+                    log(f"{sweep} {key}={v} {name}: deaths median {np.median(deaths):.0f}")
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--agents", type=int, default=100_000)
+    ap.add_argument("--reps", type=int, default=15)
+    ap.add_argument("--days", type=int, default=180)
+    ap.add_argument("--R", type=float, default=13.0)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    log = lambda m: print(f"[study {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
+    s = vaccine_study(a.agents, a.reps, a.days, R=a.R, log=log)
+    txt = json.dumps(s, indent=1)
+    print(txt)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt + "\n")
+
+
+if __name__ == "__main__":
+    main()

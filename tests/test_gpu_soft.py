@@ -124,3 +124,62 @@ def test_autograd_function_gives_the_adjoint_gradient():
     assert ok, f"relaxed incidence rel err {err}"
     ok, err = _close(theta.grad.numpy(), gradient(cd_o, dL), 1e-3)
     assert ok, f"autograd gradient rel err {err}"
+
+
+def test_set_theta_rewinds_to_the_same_run_as_a_fresh_simulator():
+    import dataclasses
+    T = 30
+    p, base = workload(4, n=15000, n_steps=T)
+    pop = replicate_population(base, 3)
+    th = np.array([[4.0 + r] + list(np.linspace(0.4, 1.3, 9) * (1.0 + 0.1 * r)) for r in range(3)],
+                  np.float32)
+    dL = np.random.default_rng(3).normal(size=(3, T)).astype(np.float32)
+    with _sim(p, pop) as s:
+        s.run(T)
+        s.grad(dL)
+        s.set_theta(th)
+        assert s.day() == 0
+        c1 = s.run(T)
+        g1 = s.grad(dL)
+    fresh = dataclasses.replace(pop, R=th[:, 0].copy(), susceptibility=th[:, 1:].copy())
+    with _sim(p, fresh) as s:
+        c2 = s.run(T)
+        g2 = s.grad(dL)
+    assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def test_set_theta_rejects_bad_values_and_hard_mode():
+    from paper_2110_04421_amd._lib import AbmError
+    p, pop = workload(4, n=5000, n_steps=10)
+    with _sim(p, pop) as s:
+        th = np.ones((1, 10), np.float32)
+        th[0, 3] = np.nan
+        with pytest.raises(AbmError):
+            s.set_theta(th)
+    p, pop = workload(0)
+    with _sim(p, pop) as s:
+        with pytest.raises(AbmError):
+            s.set_theta(np.ones((1, 10), np.float32))
+
+
+def test_gradient_descent_fit_moves_toward_the_true_parameters():
+    """Fitting hard incidence curves through the relaxed adjoint: the relaxed loss
+    falls, the transmissibility R * mean(S) (R and the S_a enter only as products, so
+    this is what one curve identifies) moves most of the way to the truth, and the hard
+    re-simulation at the fit, on the target's own stream, is far closer to the target."""
+    from paper_2110_04421_amd import calib, _lib as L
+    T = 60
+    p, base = workload(4, n=20000, n_steps=T)
+    p = dict(p, mode=L.HARD)
+    th_true = np.array([[5.5] + list(np.linspace(0.35, 1.47, 9)), [4.0] + [0.9] * 9])
+    target = calib.simulate_curves(p, base, th_true, seed=2, days=T)
+    th0 = th_true.copy()
+    th0[:, 0] = [3.5, 6.5]                      # R off by 2 and by 2.5
+    th, hist, best = calib.gd_fit(p, base, target, th0, seed=2, iters=15, days=T)
+    eff = lambda x: x[:, 0] * x[:, 1:].mean(1)
+    hard = lambda x: calib.curve_loss(calib.simulate_curves(p, base, x, seed=2, days=T), target)[0]
+    print("relaxed loss per step", np.round(hist, 3), "transmissibility", eff(th), "true", eff(th_true))
+    assert best < 0.3 * hist[0] and hist[-1] < 0.5 * hist[0]
+    assert np.all(np.abs(eff(th) - eff(th_true)) < 0.5 * np.abs(eff(th0) - eff(th_true)))
+    assert np.all(hard(th) < 0.2 * hard(th0))
