@@ -169,7 +169,7 @@ def cpu_baseline(budget_s: float = 15.0):
     m = ostep.Model(pop, p)
     st = m.init_state()
     prev = np.zeros((1, ostep.NC), np.int64)
-    prev[:, :5] = m.counts_of(st)
+    m.put_counts(prev, st)
     edges, days = 0, 0
     t0 = time.perf_counter()
     while days < 2 or (time.perf_counter() - t0 < budget_s and days < 180):

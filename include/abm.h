@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 1
+#define ABM_ABI_VERSION 2
 
 enum {
   ABM_OK = 0,
@@ -60,7 +60,17 @@ enum {
 
 enum { ABM_HARD = 0, ABM_SOFT = 1 };
 enum { ABM_STRATEGY_STANDARD = 0, ABM_STRATEGY_DELAYED = 1, ABM_STRATEGY_DELAYED_EXCEPT_65 = 2 };
-enum { ABM_STAGE_S = 0, ABM_STAGE_E = 1, ABM_STAGE_I = 2, ABM_STAGE_R = 3, ABM_STAGE_M = 4 };
+enum { ABM_STAGE_S = 0, ABM_STAGE_E = 1, ABM_STAGE_I = 2, ABM_STAGE_R = 3, ABM_STAGE_M = 4,
+       /* eleven-stage course (disease_model ABM_DISEASE_COURSE; section 3 "Agent State
+          Definition"): S, R and M above are its susceptible, recovered and dead, and a
+          susceptible agent with vaccine immunity is its "vaccinated" */
+       ABM_STAGE_ASYM = 5, ABM_STAGE_PRE_MILD = 6, ABM_STAGE_PRE_SEVERE = 7, ABM_STAGE_MILD = 8,
+       ABM_STAGE_SEVERE = 9, ABM_STAGE_HOSP = 10, ABM_STAGE_ICU = 11 };
+#define ABM_DISEASE_SEIRM 0   /* fixed E and I durations, death drawn at removal      */
+#define ABM_DISEASE_COURSE 1  /* eleven stages, age-dependent paths, random durations */
+/* stage durations of the course (shift + Poisson(extra) days), in this order */
+enum { ABM_DUR_PRE = 0, ABM_DUR_ASYM, ABM_DUR_MILD, ABM_DUR_SEV_HOSP, ABM_DUR_SEV_R,
+       ABM_DUR_HOSP_ICU, ABM_DUR_HOSP_R, ABM_DUR_ICU_DIE, ABM_DUR_ICU_R, ABM_N_DUR };
 
 /* Daily output slots, counts[day][replicate][ABM_NC] (int64). S..M are counts of the
  * state at the end of the day. */
@@ -73,6 +83,8 @@ enum {
   ABM_C_EDGES,      /* directed edges of the day's contact graph (interactions)    */
   ABM_C_NEAR,       /* susceptible draws with |u - p| <= 1e-6 (rounding-sensitive)  */
   ABM_C_INF_EDGES,  /* edges of the day's graph whose source was infectious        */
+  ABM_C_HOSP,       /* hospitalised agents (course only; 0 otherwise)                */
+  ABM_C_ICU,        /* agents in intensive care (course only; 0 otherwise)           */
   ABM_NC
 };
 
@@ -125,7 +137,18 @@ typedef struct {
   int32_t checkpoint_every;        /* soft mode: days between adjoint checkpoints         */
   int64_t edge_capacity;           /* directed-edge room per day; 0 = mean + 8 sigma      */
   int32_t flags;                   /* ABM_FLAG_*                                          */
-  int32_t reserved;
+  int32_t disease_model;           /* ABM_DISEASE_SEIRM or ABM_DISEASE_COURSE (hard mode)  */
+  /* the course, per age group: asymptomatic share of infections, severe share of the
+   * symptomatic, hospitalised share of the severe, intensive-care share of the
+   * hospitalised, and deaths among those in intensive care (each in [0, 1]) */
+  float p_asym[ABM_N_AGE], p_severe[ABM_N_AGE], p_hosp[ABM_N_AGE], p_icu[ABM_N_AGE],
+      p_die[ABM_N_AGE];
+  double A_asym;                   /* infectiousness of asymptomatic agents; presymptomatic
+                                      ones take A_stage[E], symptomatic ones A_stage[I], and
+                                      hospitalised ones are isolated (0)                 */
+  int32_t dur_shift[ABM_N_DUR];    /* stage durations: shift (1..60) ...                  */
+  int32_t pad_;
+  double dur_extra[ABM_N_DUR];     /* ... + Poisson(extra) days (0..20)                   */
 } abm_params;
 
 /* Population, concatenated over replicates (host arrays, copied at create). */
@@ -155,12 +178,13 @@ typedef struct {
   uint8_t stage;      /* ABM_STAGE_* */
   uint8_t flags;      /* bit 0: test result pending, bit 1: that result is positive */
   uint8_t vacc;       /* doses received (0, 1, 2) */
-  uint8_t reserved;
+  uint8_t course;     /* course path: bits 0-1 0 asymptomatic / 1 mild / 2 severe, bit 2
+                         hospitalised, bit 3 intensive care, bit 4 dies (course only) */
   int16_t t_exp;      /* day of exposure (ABM_NEVER if never) */
   int16_t q_until;    /* quarantined on days < q_until */
   int16_t test_day;   /* day of the pending test */
   int16_t d1, d2;     /* days of dose 1 / dose 2 */
-  int16_t pad;
+  int16_t t_next;     /* day the current stage of the course ends (ABM_NEVER if none) */
 } abm_agent_state;
 
 /* Bytes of device workspace the simulation needs (edge room included). */

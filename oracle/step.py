@@ -28,12 +28,21 @@ import numpy as np
 
 from . import philox
 from .graph import build_graph, static_maps
-from .tables import STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M, infectiousness_table
+from .tables import (STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M, STAGE_ASYM, STAGE_PRE_MILD,
+                     STAGE_PRE_SEVERE, STAGE_MILD, STAGE_SEVERE, STAGE_HOSP, STAGE_ICU,
+                     DUR_PRE, DUR_ASYM, DUR_MILD, DUR_SEV_HOSP, DUR_SEV_R, DUR_HOSP_ICU,
+                     DUR_HOSP_R, DUR_ICU_DIE, DUR_ICU_R, N_DUR, CLASS_ASYM, CLASS_PRE,
+                     CLASS_SYM, infectiousness_table, course_infectiousness_table,
+                     poisson_thresholds, poisson_count)
 
 NEVER = -32768
-NC = 13
+NC = 15
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
- C_INF_EDGES) = range(NC)
+ C_INF_EDGES, C_HOSP, C_ICU) = range(NC)
+# course path bits: 0-1 kind (0 asymptomatic, 1 mild, 2 severe), 2 hospitalised,
+# 3 intensive care, 4 dies
+K_ASYM, K_MILD, K_SEVERE = 0, 1, 2
+B_HOSP, B_ICU, B_DIE = 4, 8, 16
 NEAR_EPS = 1e-6
 
 
@@ -79,9 +88,19 @@ class Model:
         self.nrep = int(pop.agent_offset.size - 1)
         self.sizes = np.diff(np.asarray(pop.agent_offset))
         p = self.p
-        self.Atab = np.array(infectiousness_table(float(p["gamma_shape"]), float(p["gamma_scale"]),
-                                                  int(p["e_days"]), int(p["i_days"]),
-                                                  [float(a) for a in p["A_stage"]]))
+        self.eleven = int(p.get("disease_model", 0)) == 1
+        if self.eleven:
+            A = [float(a) for a in p["A_stage"]]
+            self.Atab = np.array(course_infectiousness_table(
+                float(p["gamma_shape"]), float(p["gamma_scale"]), float(p["A_asym"]),
+                A[STAGE_E], A[STAGE_I]))
+            self.ptab = {k: f32v(p[k]) for k in ("p_asym", "p_severe", "p_hosp", "p_icu", "p_die")}
+            self.dshift = np.asarray(p["dur_shift"], np.int64)
+            self.dthr = [poisson_thresholds(float(x)) for x in p["dur_extra"]]
+        else:
+            self.Atab = np.array(infectiousness_table(float(p["gamma_shape"]), float(p["gamma_scale"]),
+                                                      int(p["e_days"]), int(p["i_days"]),
+                                                      [float(a) for a in p["A_stage"]]))
         self.age = np.asarray(pop.age, np.int64)
         R = f32v(pop.R)
         S = f32v(pop.susceptibility)
@@ -100,17 +119,101 @@ class Model:
                   q_until=np.full(N, NEVER, np.int64), test_day=np.full(N, NEVER, np.int64),
                   pending=np.zeros(N, bool), positive=np.zeros(N, bool),
                   vacc=np.zeros(N, np.int64), d1=np.full(N, NEVER, np.int64),
-                  d2=np.full(N, NEVER, np.int64), latch=np.zeros(self.nrep, bool))
+                  d2=np.full(N, NEVER, np.int64), latch=np.zeros(self.nrep, bool),
+                  course=np.zeros(N, np.int64), t_next=np.full(N, NEVER, np.int64))
         seeds = np.asarray(self.pop.initial_infected, np.int64)
-        st["stage"][seeds] = STAGE_E
         st["t_exp"][seeds] = -1        # exposed the day before day 0: infectious from day 0
+        if self.eleven:
+            self.infect(st, seeds, -1)
+        else:
+            st["stage"][seeds] = STAGE_E
         return st
 
+    # --- eleven-stage course (section 3, "Disease Progression") ------------------
+    def duration(self, ids, t, which):
+        """shift + Poisson(extra) days, from lane 0 of the course's block 1 on day t."""
+        w = philox.draw_words(int(self.p["seed"]), self.loc[ids], t, self.word[ids],
+                              philox.PURPOSE_COURSE, 1)
+        which = np.broadcast_to(np.asarray(which, np.int64), ids.shape)
+        out = np.zeros(ids.size, np.int64)
+        for k in range(N_DUR):
+            sel = which == k
+            if sel.any():
+                out[sel] = self.dshift[k] + poisson_count(w[0][sel], self.dthr[k])
+        return out
+
+    def infect(self, st, ids, t):
+        """The course of agents infected on day t: asymptomatic with p_asym[a], else
+        severe with p_severe[a] (mild otherwise); a severe course is hospitalised with
+        p_hosp[a], and a hospitalised one reaches intensive care with p_icu[a].  Lanes
+        0..3 of the course's block 0 on day t; the first stage's duration from block 1."""
+        if ids.size == 0:
+            return
+        a = self.age[ids]
+        w = philox.draw_words(int(self.p["seed"]), self.loc[ids], t, self.word[ids],
+                              philox.PURPOSE_COURSE, 0)
+        u = [philox.uniform(x) for x in w]
+        asym = u[0] < self.ptab["p_asym"][a]
+        severe = ~asym & (u[1] < self.ptab["p_severe"][a])
+        hosp = severe & (u[2] < self.ptab["p_hosp"][a])
+        icu = hosp & (u[3] < self.ptab["p_icu"][a])
+        kind = np.where(asym, K_ASYM, np.where(severe, K_SEVERE, K_MILD))
+        st["course"][ids] = kind | np.where(hosp, B_HOSP, 0) | np.where(icu, B_ICU, 0)
+        st["stage"][ids] = np.where(asym, STAGE_ASYM, np.where(severe, STAGE_PRE_SEVERE, STAGE_PRE_MILD))
+        st["t_next"][ids] = t + self.duration(ids, t, np.where(asym, DUR_ASYM, DUR_PRE))
+
+    def progress(self, st, new, t):
+        """Transitions of day t (agents whose current stage ends today), read from st,
+        written to new."""
+        due = np.flatnonzero(st["t_next"] == t)
+        if due.size == 0:
+            return
+        s, c = st["stage"][due], st["course"][due]
+        to_r = (s == STAGE_ASYM) | (s == STAGE_MILD) | ((s == STAGE_SEVERE) & (c & B_HOSP == 0)) | \
+            ((s == STAGE_HOSP) & (c & B_ICU == 0)) | ((s == STAGE_ICU) & (c & B_DIE == 0))
+        to_m = (s == STAGE_ICU) & (c & B_DIE != 0)
+        new["stage"][due[to_r]] = STAGE_R
+        new["stage"][due[to_m]] = STAGE_M
+        new["t_next"][due[to_r | to_m]] = NEVER
+        nxt = np.full(due.size, -1, np.int64)
+        stage2 = np.full(due.size, -1, np.int64)
+        m = s == STAGE_PRE_MILD
+        stage2[m], nxt[m] = STAGE_MILD, DUR_MILD
+        m = s == STAGE_PRE_SEVERE
+        stage2[m], nxt[m] = STAGE_SEVERE, np.where(c[m] & B_HOSP != 0, DUR_SEV_HOSP, DUR_SEV_R)
+        m = (s == STAGE_SEVERE) & (c & B_HOSP != 0)
+        stage2[m], nxt[m] = STAGE_HOSP, np.where(c[m] & B_ICU != 0, DUR_HOSP_ICU, DUR_HOSP_R)
+        m = (s == STAGE_HOSP) & (c & B_ICU != 0)
+        if m.any():
+            # whether the stay in intensive care ends in death: lane 1 of block 1 today
+            ids = due[m]
+            w = philox.draw_words(int(self.p["seed"]), self.loc[ids], t, self.word[ids],
+                                  philox.PURPOSE_COURSE, 1)
+            die = philox.uniform(w[1]) < self.ptab["p_die"][self.age[ids]]
+            new["course"][ids] = c[m] | np.where(die, B_DIE, 0)
+            stage2[m], nxt[m] = STAGE_ICU, np.where(die, DUR_ICU_DIE, DUR_ICU_R)
+        go = stage2 >= 0
+        if go.any():
+            ids = due[go]
+            new["stage"][ids] = stage2[go]
+            new["t_next"][ids] = t + self.duration(ids, t, nxt[go])
+
     def counts_of(self, st):
-        c = np.zeros((self.nrep, 5), np.int64)
-        for s in range(5):
-            c[:, s] = np.bincount(self.rep[st["stage"] == s], minlength=self.nrep)
+        """S, E, I, R, M, hospitalised, ICU per replicate.  In the eleven-stage course E
+        counts the infected without symptoms (asymptomatic, presymptomatic) and I the
+        symptomatic ones outside hospital."""
+        g = st["stage"].copy()
+        g[(g == STAGE_ASYM) | (g == STAGE_PRE_MILD) | (g == STAGE_PRE_SEVERE)] = STAGE_E
+        g[(g == STAGE_MILD) | (g == STAGE_SEVERE)] = STAGE_I
+        c = np.zeros((self.nrep, 7), np.int64)
+        for k, s in enumerate((STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M, STAGE_HOSP, STAGE_ICU)):
+            c[:, k] = np.bincount(self.rep[g == s], minlength=self.nrep)
         return c
+
+    def put_counts(self, counts, st):
+        c = self.counts_of(st)
+        counts[:, :5] = c[:, :5]
+        counts[:, C_HOSP], counts[:, C_ICU] = c[:, 5], c[:, 6]
 
     # --- step pieces -------------------------------------------------------------
     def uniforms(self, t, purpose, ids=None, day=None):
@@ -120,8 +223,17 @@ class Model:
         return [philox.uniform(x) for x in w]
 
     def codes(self, st, t):
-        """Days since exposure for infectious (E, I), non-quarantined agents, else 0."""
+        """Days since exposure for infectious (E, I), non-quarantined agents, else 0.
+        Eleven-stage course: 16 * class + days since exposure (1..15) for asymptomatic,
+        presymptomatic and symptomatic agents outside hospital, else 0."""
         tau = t - st["t_exp"]
+        if self.eleven:
+            s = st["stage"]
+            cls = np.where(s == STAGE_ASYM, CLASS_ASYM,
+                           np.where((s == STAGE_PRE_MILD) | (s == STAGE_PRE_SEVERE), CLASS_PRE,
+                                    np.where((s == STAGE_MILD) | (s == STAGE_SEVERE), CLASS_SYM, 0)))
+            inf = (cls > 0) & (tau >= 1) & (tau <= 15) & (t >= st["q_until"])
+            return np.where(inf, 16 * cls + tau, 0)
         inf = ((st["stage"] == STAGE_E) | (st["stage"] == STAGE_I)) & (t >= st["q_until"])
         return np.where(inf, tau, 0)
 
@@ -157,7 +269,8 @@ class Model:
         for r in range(self.nrep):
             n = int(self.sizes[r])
             if not st["latch"][r]:
-                if float(prev_counts[r, C_E] + prev_counts[r, C_I]) >= trig * float(n):
+                infected = prev_counts[r, C_E] + prev_counts[r, C_I] + prev_counts[r, C_HOSP] + prev_counts[r, C_ICU]
+                if float(infected) >= trig * float(n):
                     st["latch"][r] = True
             if not st["latch"][r]:
                 continue
@@ -235,26 +348,31 @@ class Model:
         inf = sus & (u0 < prob)
         counts[:, C_NEAR] = np.bincount(self.rep[sus & (np.abs(u0 - prob) <= NEAR_EPS)],
                                         minlength=self.nrep)
-        new["stage"][inf] = STAGE_E
         new["t_exp"][inf] = t
         counts[:, C_NEW] = np.bincount(self.rep[inf], minlength=self.nrep)
-        ed, idays = int(p["e_days"]), int(p["i_days"])
-        new["stage"][(stage == STAGE_E) & (tau == ed)] = STAGE_I
-        rem = (stage == STAGE_I) & (tau == ed + idays)
-        dies = rem & (u1 < self.p_death[self.age])
-        new["stage"][rem & ~dies] = STAGE_R
-        new["stage"][dies] = STAGE_M
+        if self.eleven:
+            self.progress(st, new, t)
+            self.infect(new, np.flatnonzero(inf), t)
+        else:
+            new["stage"][inf] = STAGE_E
+            ed, idays = int(p["e_days"]), int(p["i_days"])
+            new["stage"][(stage == STAGE_E) & (tau == ed)] = STAGE_I
+            rem = (stage == STAGE_I) & (tau == ed + idays)
+            dies = rem & (u1 < self.p_death[self.age])
+            new["stage"][rem & ~dies] = STAGE_R
+            new["stage"][dies] = STAGE_M
         # 6. testing of eligible agents (alive, not quarantined, no result pending)
         rate = f32(p["test_rate"])
         if rate > 0.0:
             elig = (stage != STAGE_M) & (t >= new["q_until"]) & ~new["pending"]
             tested = elig & (u2 < rate)
-            result = tested & ((stage == STAGE_E) | (stage == STAGE_I)) & (u3 < f32(p["test_sensitivity"]))
+            infected = (stage != STAGE_S) & (stage != STAGE_R) & (stage != STAGE_M)
+            result = tested & infected & (u3 < f32(p["test_sensitivity"]))
             new["pending"][tested] = True
             new["positive"][tested] = result[tested]
             new["test_day"][tested] = t
             counts[:, C_TESTS] = np.bincount(self.rep[tested], minlength=self.nrep)
-        counts[:, :5] = self.counts_of(new)
+        self.put_counts(counts, new)
         return new, dict(lam=lam, sigma=sigma, prob=prob, u0=u0, code=code, immune=immune,
                          counts=counts, graph=graph)
 
@@ -265,7 +383,7 @@ def run(pop, params, n_steps=None, keep=False):
     st = m.init_state()
     T = int(params["n_steps"] if n_steps is None else n_steps)
     prev = np.zeros((m.nrep, NC), np.int64)
-    prev[:, :5] = m.counts_of(st)
+    m.put_counts(prev, st)
     traj = np.zeros((T, m.nrep, NC), np.int64)
     kept = []
     for t in range(T):

@@ -13,6 +13,19 @@ from __future__ import annotations
 import math
 
 STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M = 0, 1, 2, 3, 4
+# eleven-stage course (section 3, "Agent State Definition"): the paper's susceptible,
+# recovered and dead are S, R, M above; its "vaccinated" is a susceptible agent with
+# vaccine immunity
+(STAGE_ASYM, STAGE_PRE_MILD, STAGE_PRE_SEVERE, STAGE_MILD, STAGE_SEVERE, STAGE_HOSP,
+ STAGE_ICU) = 5, 6, 7, 8, 9, 10, 11
+# stage durations of the course, in this order: presymptomatic, asymptomatic -> R,
+# mild -> R, severe -> hospital, severe -> R, hospital -> ICU, hospital -> R,
+# ICU -> death, ICU -> R
+(DUR_PRE, DUR_ASYM, DUR_MILD, DUR_SEV_HOSP, DUR_SEV_R, DUR_HOSP_ICU, DUR_HOSP_R,
+ DUR_ICU_DIE, DUR_ICU_R) = range(9)
+N_DUR = 9
+# infectiousness classes of the course: code = 16 * class + days since exposure
+CLASS_ASYM, CLASS_PRE, CLASS_SYM = 1, 2, 3
 
 
 def gamma_p(a: float, x: float) -> float:
@@ -52,6 +65,18 @@ def infectiousness_table(shape: float, scale: float, e_days: int, i_days: int,
     for tau in range(1, e_days + i_days + 1):
         st = STAGE_E if tau <= e_days else STAGE_I
         tab[tau] = float(A_stage[st]) * phi(tau, shape, scale)
+    return tab
+
+
+def course_infectiousness_table(shape: float, scale: float, A_asym: float, A_pre: float,
+                                A_sym: float, size: int = 64):
+    """Eleven-stage course: Atab[16 c + tau] = A_c * Phi(tau) for the infectious classes
+    c (asymptomatic, presymptomatic, symptomatic) and 1 <= tau <= 15 (eq. 1's A_{s_i}
+    per stage class); hospitalised and ICU agents are isolated and infect nobody."""
+    tab = [0.0] * size
+    for c, A in ((CLASS_ASYM, A_asym), (CLASS_PRE, A_pre), (CLASS_SYM, A_sym)):
+        for tau in range(1, 16):
+            tab[16 * c + tau] = float(A) * phi(tau, shape, scale)
     return tab
 
 

@@ -9,14 +9,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 HARD, SOFT = 0, 1
-NC = 13
-N_AGE, N_OCC, N_THETA = 9, 23, 10
+SEIRM, COURSE = 0, 1
+NC = 15
+N_AGE, N_OCC, N_THETA, N_DUR = 9, 23, 10, 9
 NEVER = -32768
 FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER, FLAG_AUTOTUNE, FLAG_MIN_LDS_ROOM = 1, 2, 4, 8, 16
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
- C_INF_EDGES) = range(NC)
+ C_INF_EDGES, C_HOSP, C_ICU) = range(NC)
 (GET_STATE, GET_LAMBDA, GET_CODE, GET_ROWPTR, GET_COL, GET_W, GET_ATAB, GET_POISSON, GET_DAY,
  GET_LATCH, GET_SOFT_S, GET_COEF, GET_TUNING) = range(13)
 MLP_IN, MLP_H, MLP_OUT = 192, 256, 16
@@ -25,9 +26,9 @@ MLP_NPARAM = 256 * 192 + 256 + 256 * 256 + 256 + 16 * 256 + 16
 ERRORS = {0: "ok", -1: "invalid argument", -2: "ABI mismatch", -3: "workspace too small",
           -4: "edge capacity exceeded", -5: "HIP runtime error", -6: "call out of order"}
 
-STATE_DTYPE = np.dtype([("stage", "u1"), ("flags", "u1"), ("vacc", "u1"), ("reserved", "u1"),
+STATE_DTYPE = np.dtype([("stage", "u1"), ("flags", "u1"), ("vacc", "u1"), ("course", "u1"),
                         ("t_exp", "<i2"), ("q_until", "<i2"), ("test_day", "<i2"),
-                        ("d1", "<i2"), ("d2", "<i2"), ("pad", "<i2")])
+                        ("d1", "<i2"), ("d2", "<i2"), ("t_next", "<i2")])
 assert STATE_DTYPE.itemsize == 16
 
 
@@ -48,7 +49,12 @@ class AbmParams(C.Structure):
         ("eff1", C.c_float), ("eff2", C.c_float),
         ("dose_lag", C.c_int32), ("strategy", C.c_int32),
         ("gumbel_tau", C.c_float), ("checkpoint_every", C.c_int32),
-        ("edge_capacity", C.c_int64), ("flags", C.c_int32), ("reserved", C.c_int32),
+        ("edge_capacity", C.c_int64), ("flags", C.c_int32), ("disease_model", C.c_int32),
+        ("p_asym", C.c_float * N_AGE), ("p_severe", C.c_float * N_AGE), ("p_hosp", C.c_float * N_AGE),
+        ("p_icu", C.c_float * N_AGE), ("p_die", C.c_float * N_AGE),
+        ("A_asym", C.c_double),
+        ("dur_shift", C.c_int32 * N_DUR), ("pad_", C.c_int32),
+        ("dur_extra", C.c_double * N_DUR),
     ]
 
 
@@ -159,6 +165,16 @@ def make_params(cfg: dict, flags: int = 0) -> AbmParams:
     p.checkpoint_every = int(cfg.get("checkpoint_every", 10))
     p.edge_capacity = int(cfg.get("edge_capacity", 0))
     p.flags = int(flags)
+    p.disease_model = int(cfg.get("disease_model", SEIRM))
+    for name in ("p_asym", "p_severe", "p_hosp", "p_icu", "p_die"):
+        v = cfg.get(name, [0.0] * N_AGE)
+        for k in range(N_AGE):
+            getattr(p, name)[k] = float(v[k])
+    p.A_asym = float(cfg.get("A_asym", 0.0))
+    shift, extra = cfg.get("dur_shift", [1] * N_DUR), cfg.get("dur_extra", [0.0] * N_DUR)
+    for k in range(N_DUR):
+        p.dur_shift[k] = int(shift[k])
+        p.dur_extra[k] = float(extra[k])
     return p
 
 

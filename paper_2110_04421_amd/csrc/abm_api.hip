@@ -44,6 +44,20 @@ void build_atab(const abm_params& p, float* out) {
   }
 }
 
+// The course: Atab[16 c + tau] = A_c * Phi(tau) for the infectious classes c = 1
+// (asymptomatic, A_asym), 2 (presymptomatic, A_stage[E]), 3 (symptomatic, A_stage[I])
+// and 1 <= tau <= 15; hospitalised agents are isolated.
+void build_atab_course(const abm_params& p, float* out) {
+  for (int t = 0; t < ATAB; ++t) out[t] = 0.f;
+  const double A[4] = {0.0, p.A_asym, p.A_stage[ABM_STAGE_E], p.A_stage[ABM_STAGE_I]};
+  for (int c = 1; c <= 3; ++c)
+    for (int t = 1; t <= 15; ++t) {
+      const double ph = gamma_lower_reg(p.gamma_shape, t / p.gamma_scale) -
+                        gamma_lower_reg(p.gamma_shape, (t - 1) / p.gamma_scale);
+      out[16 * c + t] = (float)(A[c] * ph);
+    }
+}
+
 // Poisson(m) inverse-CDF thresholds: T_k = min(floor(F_k 2^32), 2^32 - 1), with the CDF
 // accumulated left to right from pmf_0 = e^-m, pmf_k = pmf_{k-1} m / k.
 void build_poisson(double m, uint32_t* T) {
@@ -82,7 +96,7 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
+  size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, dtab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
@@ -181,6 +195,20 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   if (p->mode == ABM_SOFT) {
     if (!(p->gumbel_tau > 0.f)) return bad("gumbel_tau <= 0");
     if (p->checkpoint_every < 1) return bad("checkpoint_every < 1");
+  }
+  if (p->disease_model != ABM_DISEASE_SEIRM && p->disease_model != ABM_DISEASE_COURSE)
+    return bad("disease_model");
+  if (p->disease_model == ABM_DISEASE_COURSE) {
+    if (p->mode != ABM_HARD) return bad("the eleven-stage course runs in hard mode only");
+    const float* tabs[5] = {p->p_asym, p->p_severe, p->p_hosp, p->p_icu, p->p_die};
+    for (const float* t : tabs)
+      for (int a = 0; a < ABM_N_AGE; ++a)
+        if (!(t[a] >= 0.f && t[a] <= 1.f)) return bad("course probability out of [0, 1]");
+    if (!(p->A_asym >= 0)) return bad("A_asym < 0");
+    for (int k = 0; k < ABM_N_DUR; ++k) {
+      if (p->dur_shift[k] < 1 || p->dur_shift[k] > 60) return bad("dur_shift out of [1, 60]");
+      if (!(p->dur_extra[k] >= 0 && p->dur_extra[k] <= 20)) return bad("dur_extra out of [0, 20]");
+    }
   }
   const int R = pop->n_replicates;
   if (pop->agent_offset[0] != 0) return bad("agent_offset[0] != 0");
@@ -332,6 +360,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.wpm = L.take<int32_t>(std::max<int64_t>(z.M, 1));
   o.atab = L.take<float>(ATAB);
   o.ptab = L.take<uint32_t>(NPT * 64);
+  o.dtab = L.take<uint32_t>(ABM_N_DUR * 64);
   o.state = L.take<AgentState>(z.N);
   o.code = L.take<uint8_t>(z.N + 32);
   o.imask = L.take<uint32_t>((z.N + 255) / 256 * 8 + 8);
@@ -554,6 +583,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.vacc_on = p->vacc_rate > 0 ? 1 : 0;
   d.strategy = p->strategy;
   d.mode = p->mode;
+  d.course_on = p->disease_model == ABM_DISEASE_COURSE ? 1 : 0;
+  for (int k = 0; k < ABM_N_DUR; ++k) d.dur_shift[k] = p->dur_shift[k];
   d.w_h = p->w_household;
   d.w_o = p->w_occupation;
   d.w_r = p->w_random;
@@ -568,6 +599,11 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.vacc_trigger = p->vacc_trigger;
   for (int a = 0; a < ABM_N_AGE; ++a) {
     d.p_death[a] = p->p_death[a];
+    d.cprob[0][a] = p->p_asym[a];
+    d.cprob[1][a] = p->p_severe[a];
+    d.cprob[2][a] = p->p_hosp[a];
+    d.cprob[3][a] = p->p_icu[a];
+    d.cprob[4][a] = p->p_die[a];
     d.vrank[0][a] = (int8_t)priority_class(p->strategy, 1, a);
     d.vrank[1][a] = (int8_t)priority_class(p->strategy, 2, a);
   }
@@ -579,6 +615,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.wp_members = (const int32_t*)(ws + o.wpm);
   d.atab = (const float*)(ws + o.atab);
   d.ptab = (const uint32_t*)(ws + o.ptab);
+  d.dtab = (const uint32_t*)(ws + o.dtab);
   d.state = (AgentState*)(ws + o.state);
   d.code = (uint8_t*)(ws + o.code);
   d.imask = (uint32_t*)(ws + o.imask);
@@ -724,7 +761,12 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     }
   }
   float atab[ATAB];
-  build_atab(*p, atab);
+  if (p->disease_model == ABM_DISEASE_COURSE)
+    build_atab_course(*p, atab);
+  else
+    build_atab(*p, atab);
+  std::vector<uint32_t> dtab(ABM_N_DUR * 64);
+  for (int k = 0; k < ABM_N_DUR; ++k) build_poisson(p->dur_extra[k], &dtab[k * 64]);
   std::vector<uint32_t> ptab(NPT * 64);
   for (int k = 0; k < ABM_N_OCC; ++k) build_poisson(p->mu_occupation[k] / 2.0, &ptab[k * 64]);
   for (int a = 0; a < ABM_N_AGE; ++a) build_poisson(p->mu_random[a] / 2.0, &ptab[(PT_AGE0 + a) * 64]);
@@ -739,6 +781,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     HIPCHK(s, hipMemcpyAsync(ws + o.wpm, pop->wp_members, z.M * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(ws + o.atab, atab, sizeof atab, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(ws + o.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(ws + o.dtab, dtab.data(), dtab.size() * 4, hipMemcpyHostToDevice, st));
   if (z.nseeds > 0)
     HIPCHK(s, hipMemcpyAsync(ws + o.seeds, pop->initial_infected, z.nseeds * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));

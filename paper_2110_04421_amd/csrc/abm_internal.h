@@ -23,7 +23,7 @@ constexpr int PB_S1_CAP = 12288;  // entries of a batch staged in LDS by the lev
 constexpr int PB_HS_MAX = 4608;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
-enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4 };
+enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4, P_COURSE = 5 };
 
 enum DevFlag : int32_t { FLAG_CAPACITY = 1, FLAG_RECV_OVERFLOW = 2 };
 
@@ -41,8 +41,8 @@ struct StaticRec {
 static_assert(sizeof(StaticRec) == 16, "StaticRec is 16 bytes");
 
 struct AgentState {
-  uint8_t stage, flags, vacc, reserved;
-  int16_t t_exp, q_until, test_day, d1, d2, pad;
+  uint8_t stage, flags, vacc, course;
+  int16_t t_exp, q_until, test_day, d1, d2, t_next;
 };
 static_assert(sizeof(AgentState) == 16, "AgentState is 16 bytes");
 
@@ -70,6 +70,10 @@ struct Dev {
   double vacc_trigger;
   float p_death[ABM_N_AGE];
   int8_t vrank[2][ABM_N_AGE];   // priority class of (dose 1|2, age group)
+  int32_t course_on;            // eleven-stage course instead of SEIRM
+  float cprob[5][ABM_N_AGE];    // course: p_asym, p_severe, p_hosp, p_icu, p_die
+  int32_t dur_shift[ABM_N_DUR];
+  const uint32_t* dtab;         // [ABM_N_DUR][64] Poisson thresholds of the durations' extra days
 
   const RepInfo* rep;
   const int4* tiles;            // {rep, start, end, tile index}

@@ -59,6 +59,75 @@ __device__ __forceinline__ int vacc_bucket(const Dev& d, const AgentState& a, in
   return NBUCKET;
 }
 
+// ---- eleven-stage course (section 3, "Agent State Definition", "Disease Progression") --
+// An infection on day t draws the whole path from lanes 0..3 of the course's block 0
+// (asymptomatic with p_asym[a], else severe with p_severe[a], else mild; a severe
+// course is hospitalised with p_hosp[a]; a hospitalised one reaches intensive care with
+// p_icu[a]).  Every stage's duration is shift + Poisson(extra) days, from lane 0 of block
+// 1 on the day the stage starts; whether intensive care ends in death is lane 1 of
+// that block on the day it starts (p_die[a]).
+__device__ __forceinline__ int course_days(const Dev& d, int k, uint32_t x) {
+  return d.dur_shift[k] + poisson_k(d.dtab + k * 64, x);
+}
+
+__device__ __forceinline__ void course_infect(const Dev& d, AgentState& a, uint32_t loc, int t,
+                                              uint32_t stream, int age) {
+  const uint4 b0 = philox(loc, (uint32_t)t, stream, P_COURSE << 24, d.key0, d.key1);
+  const uint4 b1 = philox(loc, (uint32_t)t, stream, (P_COURSE << 24) | 1u, d.key0, d.key1);
+  const bool asym = u01(b0.x) < d.cprob[0][age];
+  const bool severe = !asym && u01(b0.y) < d.cprob[1][age];
+  const bool hosp = severe && u01(b0.z) < d.cprob[2][age];
+  const bool icu = hosp && u01(b0.w) < d.cprob[3][age];
+  a.course = (uint8_t)((asym ? 0 : (severe ? 2 : 1)) | (hosp ? 4 : 0) | (icu ? 8 : 0));
+  a.stage = (uint8_t)(asym ? ABM_STAGE_ASYM : (severe ? ABM_STAGE_PRE_SEVERE : ABM_STAGE_PRE_MILD));
+  a.t_next = (int16_t)(t + course_days(d, asym ? ABM_DUR_ASYM : ABM_DUR_PRE, b1.x));
+}
+
+// The transition of an agent whose current stage ends on day t.
+__device__ __forceinline__ void course_step(const Dev& d, AgentState& a, uint32_t loc, int t,
+                                            uint32_t stream, int age) {
+  const int c = a.course;
+  int next = ABM_STAGE_R, k = -1;
+  switch (a.stage) {
+    case ABM_STAGE_PRE_MILD: next = ABM_STAGE_MILD; k = ABM_DUR_MILD; break;
+    case ABM_STAGE_PRE_SEVERE:
+      next = ABM_STAGE_SEVERE;
+      k = (c & 4) ? ABM_DUR_SEV_HOSP : ABM_DUR_SEV_R;
+      break;
+    case ABM_STAGE_SEVERE:
+      if (c & 4) {
+        next = ABM_STAGE_HOSP;
+        k = (c & 8) ? ABM_DUR_HOSP_ICU : ABM_DUR_HOSP_R;
+      }
+      break;
+    case ABM_STAGE_HOSP:
+      if (c & 8) next = ABM_STAGE_ICU;
+      break;
+    case ABM_STAGE_ICU: next = (c & 16) ? ABM_STAGE_M : ABM_STAGE_R; break;
+    default: break;                               // asymptomatic and mild recover
+  }
+  if (k >= 0 || next == ABM_STAGE_ICU) {
+    const uint4 b1 = philox(loc, (uint32_t)t, stream, (P_COURSE << 24) | 1u, d.key0, d.key1);
+    if (next == ABM_STAGE_ICU) {
+      const bool die = u01(b1.y) < d.cprob[4][age];
+      a.course = (uint8_t)(c | (die ? 16 : 0));
+      k = die ? ABM_DUR_ICU_DIE : ABM_DUR_ICU_R;
+    }
+    a.t_next = (int16_t)(t + course_days(d, k, b1.x));
+  } else {
+    a.t_next = (int16_t)ABM_NEVER;
+  }
+  a.stage = (uint8_t)next;
+}
+
+// Count groups: E counts the infected without symptoms, I the symptomatic outside hospital.
+__device__ __forceinline__ bool stage_e(int st) {
+  return st == ABM_STAGE_E || st == ABM_STAGE_ASYM || st == ABM_STAGE_PRE_MILD || st == ABM_STAGE_PRE_SEVERE;
+}
+__device__ __forceinline__ bool stage_i(int st) {
+  return st == ABM_STAGE_I || st == ABM_STAGE_MILD || st == ABM_STAGE_SEVERE;
+}
+
 // ---- pre: results due -> quarantine, dropout, infectiousness codes, vaccine classes --
 __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   __shared__ int hist[NBUCKET + 1];
@@ -86,8 +155,16 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
       if (u01(b.x) < d.dropout) a.q_until = (int16_t)t;
     }
     uint8_t c = 0;
-    if ((a.stage == ABM_STAGE_E || a.stage == ABM_STAGE_I) && t >= (int)a.q_until)
+    if (d.course_on) {
+      // 16 * class + days since exposure: asymptomatic 1, presymptomatic 2, symptomatic 3
+      const int st = a.stage, tau = t - (int)a.t_exp;
+      const int cls = st == ABM_STAGE_ASYM ? 1
+                      : (st == ABM_STAGE_PRE_MILD || st == ABM_STAGE_PRE_SEVERE) ? 2
+                      : (st == ABM_STAGE_MILD || st == ABM_STAGE_SEVERE) ? 3 : 0;
+      if (cls && tau >= 1 && tau <= 15 && t >= (int)a.q_until) c = (uint8_t)(16 * cls + tau);
+    } else if ((a.stage == ABM_STAGE_E || a.stage == ABM_STAGE_I) && t >= (int)a.q_until) {
       c = (uint8_t)(t - (int)a.t_exp);
+    }
     d.code[i] = c;
     if (a.flags != a0.flags || a.q_until != a0.q_until) d.state[i] = a;
     if (d.vacc_on) atomicAdd(&hist[vacc_bucket(d, a, t, d.age[i], ri.delay)], 1);
@@ -153,8 +230,8 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
   if (threadIdx.x == 0) {
     int latched = d.latch[r];
     if (!latched) {
-      const long long ei = d.prev_counts[(size_t)r * ABM_NC + ABM_C_E] +
-                           d.prev_counts[(size_t)r * ABM_NC + ABM_C_I];
+      const long long* pc = d.prev_counts + (size_t)r * ABM_NC;
+      const long long ei = pc[ABM_C_E] + pc[ABM_C_I] + pc[ABM_C_HOSP] + pc[ABM_C_ICU];
       if ((double)ei >= d.vacc_trigger * (double)ri.n) {
         latched = 1;
         d.latch[r] = 1;
@@ -575,12 +652,17 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
         const double p = -expm1(-(double)d.lambda[i] * (double)d.dt);
         const double u = (double)u01(b.x);
         if (u < p) {
-          a.stage = ABM_STAGE_E;
           a.t_exp = (int16_t)t;
           is_new = true;
+          if (d.course_on)
+            course_infect(d, a, loc, t, ri.stream, age);
+          else
+            a.stage = ABM_STAGE_E;
         }
         near = fabs(u - p) <= 1e-6;
       }
+    } else if (d.course_on) {
+      if ((int)a.t_next == t) course_step(d, a, loc, t, ri.stream, age);
     } else if (st0 == ABM_STAGE_E) {
       if (tau == d.e_days) a.stage = ABM_STAGE_I;
     } else if (st0 == ABM_STAGE_I) {
@@ -589,7 +671,8 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
     if (d.test_rate > 0.f && st0 != ABM_STAGE_M && t >= (int)a.q_until && !(a.flags & 1)) {
       if (u01(b.z) < d.test_rate) {
         tested = true;
-        const bool pos = (st0 == ABM_STAGE_E || st0 == ABM_STAGE_I) && u01(b.w) < d.sens;
+        const bool infected = st0 != ABM_STAGE_S && st0 != ABM_STAGE_R && st0 != ABM_STAGE_M;
+        const bool pos = infected && u01(b.w) < d.sens;
         a.flags = (uint8_t)(1 | (pos ? 2 : 0));
         a.test_day = (int16_t)t;
       }
@@ -597,10 +680,11 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
     d.state[i] = a;
   }
   const int st = live ? (int)a.stage : -1;
-  const bool v[10] = {st == 0, st == 1, st == 2, st == 3, st == 4, is_new, tested, dose1, dose2, near};
-  const int sl[10] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_NEW, ABM_C_TESTS,
-                      ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR};
-  block_count_store<10>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
+  const bool v[12] = {st == ABM_STAGE_S, stage_e(st), stage_i(st), st == ABM_STAGE_R, st == ABM_STAGE_M,
+                      st == ABM_STAGE_HOSP, st == ABM_STAGE_ICU, is_new, tested, dose1, dose2, near};
+  const int sl[12] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_HOSP, ABM_C_ICU, ABM_C_NEW,
+                      ABM_C_TESTS, ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR};
+  block_count_store<12>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
 }
 
 // ---- end of day: tile counts -> per-replicate counts -> trajectory ----------------
@@ -660,13 +744,13 @@ __global__ __launch_bounds__(TILE) void k_init_state(Dev d) {
   a.stage = ABM_STAGE_S;
   a.flags = 0;
   a.vacc = 0;
-  a.reserved = 0;
+  a.course = 0;
   a.t_exp = ABM_NEVER;
   a.q_until = ABM_NEVER;
   a.test_day = ABM_NEVER;
   a.d1 = ABM_NEVER;
   a.d2 = ABM_NEVER;
-  a.pad = 0;
+  a.t_next = (int16_t)ABM_NEVER;
   d.state[i] = a;
   d.code[i] = 0;
   d.lambda[i] = 0.f;
@@ -676,8 +760,20 @@ __global__ void k_seed(Dev d, const int32_t* seeds, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int i = seeds[k];
-  d.state[i].stage = ABM_STAGE_E;
-  d.state[i].t_exp = -1;
+  AgentState a = d.state[i];
+  a.t_exp = -1;                          // exposed the day before day 0
+  if (d.course_on) {
+    int lo = 0, hi = d.R - 1;            // the seed's replicate
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (d.rep[mid].start <= i) lo = mid; else hi = mid - 1;
+    }
+    const RepInfo& ri = d.rep[lo];
+    course_infect(d, a, (uint32_t)(i - ri.start), -1, ri.stream, d.age[i]);
+  } else {
+    a.stage = ABM_STAGE_E;
+  }
+  d.state[i] = a;
 }
 
 __global__ void k_zero_counts(Dev d) {
@@ -689,9 +785,10 @@ __global__ __launch_bounds__(TILE) void k_recount(Dev d) {
   const int4 tl = d.tiles[blockIdx.x];
   const int i = tl.y + threadIdx.x;
   const int st = i < tl.z ? (int)d.state[i].stage : -1;
-  const bool v[5] = {st == 0, st == 1, st == 2, st == 3, st == 4};
-  const int sl[5] = {0, 1, 2, 3, 4};
-  block_count_add<5>(v, sl, reinterpret_cast<unsigned long long*>(d.prev_counts) + (size_t)tl.x * ABM_NC);
+  const bool v[7] = {st == ABM_STAGE_S, stage_e(st), stage_i(st), st == ABM_STAGE_R, st == ABM_STAGE_M,
+                     st == ABM_STAGE_HOSP, st == ABM_STAGE_ICU};
+  const int sl[7] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_HOSP, ABM_C_ICU};
+  block_count_add<7>(v, sl, reinterpret_cast<unsigned long long*>(d.prev_counts) + (size_t)tl.x * ABM_NC);
 }
 
 __global__ void k_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {

@@ -32,6 +32,22 @@ BASE = dict(
     vacc_rate=0.0, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12,
     strategy=STRAT_STANDARD,
     mode=MODE_HARD, gumbel_tau=0.5, checkpoint_every=10,
+    # eleven-stage course (disease_model 1; section 3 names the stages, the values are
+    # readings): per age group 0-10 .. 80+, the share of infections that stay
+    # asymptomatic, of symptomatic ones that turn severe, of severe ones hospitalised,
+    # of hospitalised ones in intensive care, and of those in intensive care who die
+    disease_model=0,
+    p_asym=[0.45, 0.45, 0.40, 0.35, 0.30, 0.25, 0.20, 0.20, 0.20],
+    p_severe=[0.01, 0.02, 0.05, 0.08, 0.12, 0.18, 0.28, 0.40, 0.50],
+    p_hosp=[0.30, 0.30, 0.35, 0.40, 0.45, 0.50, 0.60, 0.70, 0.80],
+    p_icu=[0.05, 0.05, 0.08, 0.10, 0.15, 0.20, 0.25, 0.30, 0.30],
+    p_die=[0.10, 0.10, 0.15, 0.20, 0.30, 0.40, 0.50, 0.60, 0.70],
+    A_asym=0.5,                          # asymptomatic infectiousness (A_E, A_I as above)
+    # stage durations = shift + Poisson(extra) days (means 5, 10, 8, 6, 12, 3, 10, 8, 12):
+    # presymptomatic, asymptomatic, mild, severe -> hospital, severe -> recovered,
+    # hospital -> ICU, hospital -> recovered, ICU -> death, ICU -> recovered
+    dur_shift=[1] * 9,
+    dur_extra=[4.0, 9.0, 7.0, 5.0, 11.0, 2.0, 9.0, 7.0, 11.0],
     n_steps=180,
     edge_capacity=0,
 )

@@ -27,6 +27,8 @@ def to_records(st, dtype):
     rec["vacc"] = st["vacc"]
     for k in ("t_exp", "q_until", "test_day", "d1", "d2"):
         rec[k] = st[k]
+    rec["course"] = st["course"]
+    rec["t_next"] = st["t_next"]
     return rec
 
 
@@ -36,11 +38,13 @@ def from_records(rec, latch):
               q_until=rec["q_until"].astype(np.int64), test_day=rec["test_day"].astype(np.int64),
               pending=(rec["flags"] & 1).astype(bool), positive=(rec["flags"] & 2).astype(bool),
               vacc=rec["vacc"].astype(np.int64), d1=rec["d1"].astype(np.int64),
-              d2=rec["d2"].astype(np.int64), latch=np.asarray(latch, bool).copy())
+              d2=rec["d2"].astype(np.int64), latch=np.asarray(latch, bool).copy(),
+              course=rec["course"].astype(np.int64), t_next=rec["t_next"].astype(np.int64))
     return st
 
 
-FIELDS = ("stage", "t_exp", "q_until", "test_day", "pending", "positive", "vacc", "d1", "d2")
+FIELDS = ("stage", "t_exp", "q_until", "test_day", "pending", "positive", "vacc", "d1", "d2",
+          "course", "t_next")
 
 
 def state_mismatch(a, b):

@@ -72,7 +72,7 @@ def _lockstep(p, pop, T, graph=True, allow_near=True, check_csr_every=0):
     m = ostep.Model(pop, p)
     st = m.init_state()
     prev = np.zeros((m.nrep, ostep.NC), np.int64)
-    prev[:, :5] = m.counts_of(st)
+    m.put_counts(prev, st)
     near_total, worst = 0, 0.0
     with _sim(p, pop, graph=graph) as s:
         for t in range(T):

@@ -197,7 +197,7 @@ def test_intervention_marginals():
     m = ostep.Model(pop, p)
     st = m.init_state()
     prev = np.zeros((1, ostep.NC), np.int64)
-    prev[:, :5] = m.counts_of(st)
+    m.put_counts(prev, st)
     hist = []
     cap = math.floor(0.005 * 30000)
     for t in range(40):
