@@ -129,7 +129,8 @@ typedef struct {
   float test_rate;                 /* daily probability an eligible agent is tested; 0 off*/
   float test_sensitivity;          /* P(positive | exposed or infected)                   */
   double vacc_rate;                /* daily doses as a fraction of the replicate; 0 off   */
-  double vacc_trigger;             /* start when (E+I)/N >= trigger (latched)             */
+  double vacc_trigger;             /* start when infected/N >= trigger (latched; E+I, plus the
+                                      hospitalised and ICU agents of the course)         */
   float eff1, eff2;                /* immunity probability after dose 1 / dose 2          */
   int32_t dose_lag;                /* days from a dose to its effect (12)                 */
   int32_t strategy;                /* ABM_STRATEGY_* (priority order of Table 1)          */

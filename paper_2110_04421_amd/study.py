@@ -32,8 +32,9 @@ STRATEGIES = {0: "standard", 1: "delayed_second_dose", 2: "delayed_except_65plus
 
 
 def run_config(params, pop, days):
-    """Cumulative deaths, cumulative infections, doses given and the day vaccination
-    started (-1: never), per replicate."""
+    """Cumulative deaths, cumulative infections, doses given, the day vaccination
+    started (-1: never) and the peak of hospital occupancy (eleven-stage course), per
+    replicate."""
     from .sim import Simulator
     with Simulator(dict(params, n_steps=days), pop) as s:
         c = s.run(days)
@@ -42,7 +43,8 @@ def run_config(params, pop, days):
     d1 = c[:, :, L.C_DOSE1]
     doses = d1.sum(0) + c[:, :, L.C_DOSE2].sum(0)
     start = np.where(d1.any(0), d1.argmax(0), -1)
-    return deaths, infected, doses, start
+    hosp_peak = (c[:, :, L.C_HOSP] + c[:, :, L.C_ICU]).max(0)
+    return deaths, infected, doses, start, hosp_peak
 
 
 def quartiles(x):
@@ -50,7 +52,8 @@ def quartiles(x):
 
 
 def vaccine_study(n_agents=100_000, reps=15, days=180, effs=(0.6, 0.7, 0.8, 0.9),
-                  rates=(0.001, 0.003, 0.01), base_rate=0.003, base_eff=0.8, R=13.0, log=None):
+                  rates=(0.001, 0.003, 0.01), base_rate=0.003, base_eff=0.8, R=13.0,
+                  disease_model=0, log=None):
     """Both sweeps.  ``R`` is chosen so that, as section 5 states, the 1 % prevalence
     that starts vaccination is reached around day 20 (median day 20 at R = 13 on this
     population; at the plain-100k value 5.18 it comes near day 118)."""
@@ -58,8 +61,9 @@ def vaccine_study(n_agents=100_000, reps=15, days=180, effs=(0.6, 0.7, 0.8, 0.9)
     from synthpop import workload
     p, pop = workload(1, n=n_agents, n_rep=reps)
     pop = dataclasses.replace(pop, R=np.full(reps, R, np.float32))
-    p = dict(p, eff2=0.95, vacc_trigger=0.01)
-    out = {"agents": n_agents, "replicates": reps, "days": days, "R": R, "efficacy_sweep": [],
+    p = dict(p, eff2=0.95, vacc_trigger=0.01, disease_model=int(disease_model))
+    out = {"agents": n_agents, "replicates": reps, "days": days, "R": R,
+           "disease_model": "eleven-stage course" if disease_model else "SEIRM", "efficacy_sweep": [],
            "rate_sweep": []}
     t0 = time.perf_counter()
     for sweep, values, key in (("efficacy_sweep", effs, "eff1"), ("rate_sweep", rates, "vacc_rate")):
@@ -67,12 +71,13 @@ def vaccine_study(n_agents=100_000, reps=15, days=180, effs=(0.6, 0.7, 0.8, 0.9)
             for strat, name in STRATEGIES.items():
                 q = dict(p, strategy=strat, eff1=base_eff, vacc_rate=base_rate)
                 q[key] = float(v)
-                deaths, infected, doses, start = run_config(q, pop, days)
+                deaths, infected, doses, start, hosp = run_config(q, pop, days)
                 out[sweep].append({"strategy": name, "eff1": q["eff1"], "vacc_rate": q["vacc_rate"],
                                    "deaths_quartiles": quartiles(deaths),
                                    "infected_quartiles": quartiles(infected),
                                    "doses_mean": float(doses.mean()),
-                                   "vaccination_start_day_median": float(np.median(start))})
+                                   "vaccination_start_day_median": float(np.median(start)),
+                                   "hospital_peak_quartiles": quartiles(hosp)})
                 if log:
                     log(f"{sweep} {key}={v} {name}: deaths median {np.median(deaths):.0f}")
     out["seconds"] = time.perf_counter() - t0
@@ -85,10 +90,11 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=15)
     ap.add_argument("--days", type=int, default=180)
     ap.add_argument("--R", type=float, default=13.0)
+    ap.add_argument("--course", action="store_true", help="the eleven-stage course instead of SEIRM")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(f"[study {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
-    s = vaccine_study(a.agents, a.reps, a.days, R=a.R, log=log)
+    s = vaccine_study(a.agents, a.reps, a.days, R=a.R, disease_model=1 if a.course else 0, log=log)
     txt = json.dumps(s, indent=1)
     print(txt)
     if a.out:

@@ -17,7 +17,7 @@ def test_strategies_agree_without_vaccine_and_efficacy_lowers_infections():
     for s in (1, 2):                            # no doses: the strategy cannot matter
         for a, b in zip(runs[0], runs[s]):
             assert np.array_equal(a, b)
-    assert np.all(runs[0][2] == 0) and np.all(runs[0][3] == -1)
+    assert np.all(runs[0][2] == 0) and np.all(runs[0][3] == -1) and np.all(runs[0][4] == 0)
     # with doses, first-dose efficacy 0.9 against 0.6 under the delayed-second-dose
     # strategy (the same Philox streams, so only the parameters differ)
     lo = study.run_config(dict(p, strategy=1, vacc_rate=0.01, eff1=0.6), pop, 120)
