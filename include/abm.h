@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 2
+#define ABM_ABI_VERSION 3
 
 enum {
   ABM_OK = 0,
@@ -85,6 +85,7 @@ enum {
   ABM_C_INF_EDGES,  /* edges of the day's graph whose source was infectious        */
   ABM_C_HOSP,       /* hospitalised agents (course only; 0 otherwise)                */
   ABM_C_ICU,        /* agents in intensive care (course only; 0 otherwise)           */
+  ABM_C_NOTIFIED,   /* app users notified of an exposure (told to test tomorrow)      */
   ABM_NC
 };
 
@@ -124,7 +125,7 @@ typedef struct {
   float p_death[ABM_N_AGE];        /* death probability at removal, per age group         */
   int32_t e_days, i_days;          /* exposed / infected durations (5, 10); sum <= 63     */
   int32_t quarantine_days;         /* 14; 0 disables quarantine                           */
-  int32_t test_delay;              /* days from test to result (>= 1)                     */
+  int32_t test_delay;              /* days from test to result (>= 1; see test_delay_max)  */
   float quarantine_dropout;        /* daily probability of leaving quarantine early       */
   float test_rate;                 /* daily probability an eligible agent is tested; 0 off*/
   float test_sensitivity;          /* P(positive | exposed or infected)                   */
@@ -150,6 +151,12 @@ typedef struct {
   int32_t dur_shift[ABM_N_DUR];    /* stage durations: shift (1..60) ...                  */
   int32_t pad_;
   double dur_extra[ABM_N_DUR];     /* ... + Poisson(extra) days (0..20)                   */
+  /* testing turnaround and digital exposure notification (section 4) */
+  int32_t test_delay_max;          /* result after test_delay .. test_delay_max days,
+                                      uniform (the RT-PCR test's 3..5); = test_delay: fixed */
+  float app_adoption;              /* share of agents with the notification app; 0 = off  */
+  float den_compliance;            /* notified app users who test the next day             */
+  int32_t den_window;              /* days of contacts a positive result notifies (1..30) */
 } abm_params;
 
 /* Population, concatenated over replicates (host arrays, copied at create). */
@@ -177,7 +184,8 @@ typedef struct abm_sim abm_sim;
 /* Device state of one agent, 16 bytes (abm_get(ABM_GET_STATE) returns N of these). */
 typedef struct {
   uint8_t stage;      /* ABM_STAGE_* */
-  uint8_t flags;      /* bit 0: test result pending, bit 1: that result is positive */
+  uint8_t flags;      /* bit 0: test result pending, bit 1: that result is positive,
+                         bit 2: notified of an exposure yesterday (tests today) */
   uint8_t vacc;       /* doses received (0, 1, 2) */
   uint8_t course;     /* course path: bits 0-1 0 asymptomatic / 1 mild / 2 severe, bit 2
                          hospitalised, bit 3 intensive care, bit 4 dies (course only) */

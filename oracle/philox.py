@@ -19,6 +19,7 @@ import numpy as np
 
 PURPOSE_AGENT, PURPOSE_AGENT2, PURPOSE_VACC, PURPOSE_OCC, PURPOSE_RAND = 0, 1, 2, 3, 4
 PURPOSE_COURSE = 5     # eleven-stage course: block 0 = path at infection, block 1 = durations
+PURPOSE_APP = 6        # exposure-notification app access, drawn once (day 0)
 
 # Philox-4x32 multipliers and Weyl key increments (Salmon et al. 2011, table of constants)
 M4x32 = (0xD2511F53, 0xCD9E8D57)

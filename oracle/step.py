@@ -36,9 +36,9 @@ from .tables import (STAGE_S, STAGE_E, STAGE_I, STAGE_R, STAGE_M, STAGE_ASYM, ST
                      poisson_thresholds, poisson_count)
 
 NEVER = -32768
-NC = 15
+NC = 16
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
- C_INF_EDGES, C_HOSP, C_ICU) = range(NC)
+ C_INF_EDGES, C_HOSP, C_ICU, C_NOTIFIED) = range(NC)
 # course path bits: 0-1 kind (0 asymptomatic, 1 mild, 2 severe), 2 hospitalised,
 # 3 intensive care, 4 dies
 K_ASYM, K_MILD, K_SEVERE = 0, 1, 2
@@ -111,6 +111,15 @@ class Model:
         self.S = S
         self.kappa = kappa
         self.p_death = f32v(p["p_death"])
+        # testing and digital exposure notification (section 4)
+        self.dmin = int(p["test_delay"])
+        self.dmax = int(p.get("test_delay_max", self.dmin))
+        self.den = f32(p.get("app_adoption", 0.0)) > 0.0
+        self.window = int(p.get("den_window", 7))
+        self.history = {}
+        if self.den:
+            w = philox.draw_words(int(p["seed"]), self.loc, 0, self.word, philox.PURPOSE_APP, 0)
+            self.app = philox.uniform(w[0]) < f32(p["app_adoption"])
         self.delay = np.asarray(pop.dose2_delay, np.int64)
 
     def init_state(self):
@@ -120,7 +129,8 @@ class Model:
                   pending=np.zeros(N, bool), positive=np.zeros(N, bool),
                   vacc=np.zeros(N, np.int64), d1=np.full(N, NEVER, np.int64),
                   d2=np.full(N, NEVER, np.int64), latch=np.zeros(self.nrep, bool),
-                  course=np.zeros(N, np.int64), t_next=np.full(N, NEVER, np.int64))
+                  course=np.zeros(N, np.int64), t_next=np.full(N, NEVER, np.int64),
+                  notified=np.zeros(N, bool))
         seeds = np.asarray(self.pop.initial_infected, np.int64)
         st["t_exp"][seeds] = -1        # exposed the day before day 0: infectious from day 0
         if self.eleven:
@@ -128,6 +138,44 @@ class Model:
         else:
             st["stage"][seeds] = STAGE_E
         return st
+
+    # --- testing and exposure notification (section 4) ------------------------------
+    def result_delay(self, ids, test_day):
+        """Days from a test to its result: test_delay, or uniform over test_delay ..
+        test_delay_max from lane 1 of AGENT2 on the test day, k = floor(x * n / 2^32)."""
+        n = self.dmax - self.dmin + 1
+        if n <= 1:
+            return np.full(ids.size, self.dmin, np.int64)
+        w = philox.draw_words(int(self.p["seed"]), self.loc[ids], test_day, self.word[ids],
+                              philox.PURPOSE_AGENT2, 0)
+        return self.dmin + ((w[1].astype(np.uint64) * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+
+    def graph_of(self, d):
+        if d not in self.history:
+            rp, col, _, _ = build_graph(self.pop, self.p, d, self.maps)
+            self.history[d] = (rp, col)
+        return self.history[d]
+
+    def notify(self, st, index, t):
+        """Digital exposure notification: every contact, over the last ``window`` days'
+        graphs, of an app user whose positive result arrives today, when the contact
+        also uses the app and is not in quarantine (``st`` carries today's quarantine)."""
+        out = np.zeros(self.N, bool)
+        idx = np.flatnonzero(index)
+        if idx.size == 0:
+            return out
+        for k in range(1, self.window + 1):
+            d = t - k
+            if d < 0:
+                break
+            rp, col = self.graph_of(d)
+            lo, hi = rp[idx], rp[idx + 1]
+            n = hi - lo
+            if n.sum() == 0:
+                continue
+            pos = np.repeat(lo - np.concatenate([[0], np.cumsum(n)[:-1]]), n) + np.arange(n.sum())
+            out[col[pos]] = True
+        return out & self.app & (t >= st["q_until"])
 
     # --- eleven-stage course (section 3, "Disease Progression") ------------------
     def duration(self, ids, t, which):
@@ -313,7 +361,9 @@ class Model:
         counts = np.zeros((self.nrep, NC), np.int64)
         # 1. pre: test results due today
         qd = int(p["quarantine_days"])
-        due = st["pending"] & (t == st["test_day"] + int(p["test_delay"]))
+        due = np.zeros(self.N, bool)
+        pend = np.flatnonzero(st["pending"])
+        due[pend] = t == st["test_day"][pend] + self.result_delay(pend, st["test_day"][pend])
         pos_due = due & st["positive"]
         counts[:, C_POS] = np.bincount(self.rep[pos_due], minlength=self.nrep)
         if qd > 0:
@@ -326,6 +376,11 @@ class Model:
             if inq.size:
                 u = self.uniforms(t, philox.PURPOSE_AGENT2, inq)[0]
                 new["q_until"][inq[u < drop]] = t
+        # contacts of today's positive app users are told to test tomorrow (if they use
+        # the app and, after today's results, are not in quarantine)
+        new["notified"] = (self.notify({**st, "q_until": new["q_until"]}, pos_due & self.app, t)
+                           if self.den else np.zeros(self.N, bool))
+        counts[:, C_NOTIFIED] = np.bincount(self.rep[new["notified"]], minlength=self.nrep)
         code = self.codes({**st, "q_until": new["q_until"]}, t)
         # 2. vaccination
         d1n, d2n = self.vaccinate(new, t, prev_counts)
@@ -334,6 +389,10 @@ class Model:
         # 3. graph, 4. lambda
         if graph is None:
             graph = build_graph(self.pop, p, t, self.maps)
+        if self.den:
+            self.history[t] = (graph[0], graph[1])
+            for d in [d for d in self.history if d < t - self.window]:
+                del self.history[d]
         lam, sigma = self.force_of_infection(code, graph)
         counts[:, C_EDGES] = np.bincount(self.rep, weights=np.diff(graph[0]),
                                          minlength=self.nrep).astype(np.int64)
@@ -363,9 +422,15 @@ class Model:
             new["stage"][dies] = STAGE_M
         # 6. testing of eligible agents (alive, not quarantined, no result pending)
         rate = f32(p["test_rate"])
-        if rate > 0.0:
+        if rate > 0.0 or self.den:
             elig = (stage != STAGE_M) & (t >= new["q_until"]) & ~new["pending"]
             tested = elig & (u2 < rate)
+            if self.den:
+                # notified yesterday: tested today with the compliance probability
+                cand = np.flatnonzero(elig & st["notified"])
+                if cand.size:
+                    uc = self.uniforms(t, philox.PURPOSE_AGENT2, cand)[2]
+                    tested[cand[uc < f32(p["den_compliance"])]] = True
             infected = (stage != STAGE_S) & (stage != STAGE_R) & (stage != STAGE_M)
             result = tested & infected & (u3 < f32(p["test_sensitivity"]))
             new["pending"][tested] = True

@@ -9,15 +9,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabm.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 HARD, SOFT = 0, 1
 SEIRM, COURSE = 0, 1
-NC = 15
+NC = 16
 N_AGE, N_OCC, N_THETA, N_DUR = 9, 23, 10, 9
 NEVER = -32768
 FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER, FLAG_AUTOTUNE, FLAG_MIN_LDS_ROOM = 1, 2, 4, 8, 16
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
- C_INF_EDGES, C_HOSP, C_ICU) = range(NC)
+ C_INF_EDGES, C_HOSP, C_ICU, C_NOTIFIED) = range(NC)
 (GET_STATE, GET_LAMBDA, GET_CODE, GET_ROWPTR, GET_COL, GET_W, GET_ATAB, GET_POISSON, GET_DAY,
  GET_LATCH, GET_SOFT_S, GET_COEF, GET_TUNING) = range(13)
 MLP_IN, MLP_H, MLP_OUT = 192, 256, 16
@@ -55,6 +55,8 @@ class AbmParams(C.Structure):
         ("A_asym", C.c_double),
         ("dur_shift", C.c_int32 * N_DUR), ("pad_", C.c_int32),
         ("dur_extra", C.c_double * N_DUR),
+        ("test_delay_max", C.c_int32), ("app_adoption", C.c_float), ("den_compliance", C.c_float),
+        ("den_window", C.c_int32),
     ]
 
 
@@ -175,6 +177,10 @@ def make_params(cfg: dict, flags: int = 0) -> AbmParams:
     for k in range(N_DUR):
         p.dur_shift[k] = int(shift[k])
         p.dur_extra[k] = float(extra[k])
+    p.test_delay_max = int(cfg.get("test_delay_max", cfg["test_delay"]))
+    p.app_adoption = float(cfg.get("app_adoption", 0.0))
+    p.den_compliance = float(cfg.get("den_compliance", 0.0))
+    p.den_window = int(cfg.get("den_window", 7))
     return p
 
 

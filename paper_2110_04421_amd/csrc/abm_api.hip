@@ -98,7 +98,7 @@ struct Layout {
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, dtab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
-      traj, day, flags, seeds;
+      traj, day, flags, seeds, ring_rp, ring_col, den_mask;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
       pb_b1w, pb_buf2, pb_rsrc, pb_rstart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
@@ -188,6 +188,14 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   for (int k = 0; k < ABM_N_OCC; ++k)
     if (!(p->mu_occupation[k] >= 0 && p->mu_occupation[k] <= 40)) return bad("mu_occupation out of [0, 40]");
   if (p->test_rate > 0.f && p->test_delay < 1) return bad("test_delay must be >= 1");
+  if (p->test_delay_max < p->test_delay || p->test_delay_max > 30)
+    return bad("test_delay_max must be in [test_delay, 30]");
+  if (!(p->app_adoption >= 0.f && p->app_adoption <= 1.f)) return bad("app_adoption out of [0, 1]");
+  if (!(p->den_compliance >= 0.f && p->den_compliance <= 1.f)) return bad("den_compliance out of [0, 1]");
+  if (p->app_adoption > 0.f) {
+    if (p->den_window < 1 || p->den_window > 30) return bad("den_window out of [1, 30]");
+    if (p->test_delay < 1) return bad("test_delay must be >= 1");
+  }
   if (p->quarantine_days < 0 || p->quarantine_days > 10000) return bad("quarantine_days");
   if (p->dose_lag < 0 || p->dose_lag > 10000) return bad("dose_lag");
   if (p->strategy < 0 || p->strategy > 2) return bad("strategy");
@@ -384,6 +392,11 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
   o.day = L.take<int32_t>(1);
+  if (p.app_adoption > 0.f) {
+    o.ring_rp = L.take<int32_t>((int64_t)p.den_window * (z.N + 1));
+    o.ring_col = L.take<int32_t>((int64_t)p.den_window * z.ecap);
+    o.den_mask = L.take<uint32_t>((z.N + 31) / 32 + 1);
+  }
   o.flags = L.take<int32_t>(1);
   o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
   if (z.pb_on) {
@@ -444,18 +457,24 @@ void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) 
     mark();
     launch_build_step(d, b, st);
   }
+  if (d.den_on) {
+    mark();
+    launch_den_store(d, st);
+  }
   mark();
   launch_message(d, st);
   mark();
   launch_fused(d, st);
   mark();
   launch_finalize(d, st);
+  if (d.den_on) launch_den_clear(d, st);
   if (ev) (void)hipEventRecord((*ev)[k], st);
 }
 
 void name_kernels(abm_sim* s) {
   s->names = {"pre", "mask", "vplan"};
   for (int b = 0; b < build_steps(s->d); ++b) s->names.push_back(build_step_name(s->d, b));
+  if (s->d.den_on) s->names.push_back("den_store");
   for (const char* n : {"message", "fused", "finalize"}) s->names.push_back(n);
   s->nk = (int)s->names.size();
   s->ms.assign(s->nk, 0.0);
@@ -641,6 +660,17 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.prev_counts = (long long*)(ws + o.prev_counts);
   d.traj = (long long*)(ws + o.traj);
   d.day = (int32_t*)(ws + o.day);
+  d.test_dmin = p->test_delay;
+  d.test_dmax = p->test_delay_max;
+  d.den_on = p->app_adoption > 0.f ? 1 : 0;
+  d.den_window = p->den_window;
+  d.den_adoption = p->app_adoption;
+  d.den_compliance = p->den_compliance;
+  if (d.den_on) {
+    d.ring_rp = (int32_t*)(ws + o.ring_rp);
+    d.ring_col = (int32_t*)(ws + o.ring_col);
+    d.den_mask = (uint32_t*)(ws + o.den_mask);
+  }
   d.flags = (int32_t*)(ws + o.flags);
   if (p->mode == ABM_SOFT) {
     d.s = (float*)(ws + o.s);
@@ -786,6 +816,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     HIPCHK(s, hipMemcpyAsync(ws + o.seeds, pop->initial_infected, z.nseeds * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));
   HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 4, st));
+  if (d.den_on) {                          // no graphs before day 0: empty rows
+    HIPCHK(s, hipMemsetAsync(ws + o.ring_rp, 0, (size_t)p->den_window * (N + 1) * 4, st));
+    HIPCHK(s, hipMemsetAsync(ws + o.den_mask, 0, ((N + 31) / 32 + 1) * 4, st));
+  }
   HIPCHK(s, hipMemsetAsync(ws + o.flags, 0, 4, st));
   HIPCHK(s, hipMemsetAsync(ws + o.vplan, 0, 8 * R, st));
   HIPCHK(s, hipMemsetAsync(ws + o.traj, 0, z.T * z.R * ABM_NC * 8, st));
@@ -925,6 +959,16 @@ int abm_set_state(abm_sim* s, int32_t day, const uint8_t* h_latch, const abm_age
   if (day < 0 || day > s->z.T) return s->fail(ABM_E_ARG, "day out of range");
   HIPCHK(s, hipMemcpyAsync(s->d.state, h_state, n_agents * sizeof(AgentState), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(s->d.latch, h_latch, s->z.R, hipMemcpyHostToDevice, s->stream));
+  if (s->d.den_on) {
+    // the notification ring holds the graphs of the den_window days before `day`
+    HIPCHK(s, hipMemsetAsync(s->ws + s->o.ring_rp, 0, (size_t)s->d.den_window * (s->z.N + 1) * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(s->ws + s->o.den_mask, 0, ((s->z.N + 31) / 32 + 1) * 4, s->stream));
+    for (int32_t dd = std::max(0, day - s->d.den_window); dd < day; ++dd) {
+      launch_set_day(s->d, dd, s->stream);
+      for (int b = 0; b < build_steps(s->d); ++b) launch_build_step(s->d, b, s->stream);
+      launch_den_store(s->d, s->stream);
+    }
+  }
   launch_set_day(s->d, day, s->stream);
   launch_recount(s->d, s->stream);
   HIPCHK(s, hipGetLastError());

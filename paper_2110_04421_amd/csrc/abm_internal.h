@@ -23,7 +23,7 @@ constexpr int PB_S1_CAP = 12288;  // entries of a batch staged in LDS by the lev
 constexpr int PB_HS_MAX = 4608;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
-enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4, P_COURSE = 5 };
+enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4, P_COURSE = 5, P_APP = 6 };
 
 enum DevFlag : int32_t { FLAG_CAPACITY = 1, FLAG_RECV_OVERFLOW = 2 };
 
@@ -74,6 +74,12 @@ struct Dev {
   float cprob[5][ABM_N_AGE];    // course: p_asym, p_severe, p_hosp, p_icu, p_die
   int32_t dur_shift[ABM_N_DUR];
   const uint32_t* dtab;         // [ABM_N_DUR][64] Poisson thresholds of the durations' extra days
+  int32_t test_dmin, test_dmax; // result turnaround range (days)
+  int32_t den_on, den_window;   // digital exposure notification
+  float den_adoption, den_compliance;
+  int32_t* ring_rp;             // [den_window][N+1] row pointers of the last days' graphs
+  int32_t* ring_col;            // [den_window][ecap] their columns
+  uint32_t* den_mask;           // [(N+31)/32] contacts of today's positive app users
 
   const RepInfo* rep;
   const int4* tiles;            // {rep, start, end, tile index}
@@ -241,6 +247,8 @@ void launch_adj_zero(const Dev& d, hipStream_t s);
 void launch_adj_day(const Dev& d, int32_t t, int32_t seg_slot, hipStream_t s);
 void launch_adj_ibar(const Dev& d, int32_t t, hipStream_t s);
 void launch_adj_theta(const Dev& d, hipStream_t s);
+void launch_den_store(const Dev& d, hipStream_t s);   // the day's graph into the notification ring
+void launch_den_clear(const Dev& d, hipStream_t s);   // end of day: notification marks consumed
 void launch_set_day(const Dev& d, int32_t day, hipStream_t s);
 
 }  // namespace abm

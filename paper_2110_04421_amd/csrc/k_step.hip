@@ -59,6 +59,20 @@ __device__ __forceinline__ int vacc_bucket(const Dev& d, const AgentState& a, in
   return NBUCKET;
 }
 
+// ---- testing turnaround and digital exposure notification (section 4) ----------------
+// App access: lane 0 of purpose APP on day 0, below the adoption share.
+__device__ __forceinline__ bool app_user(const Dev& d, uint32_t loc, uint32_t stream) {
+  return u01(philox(loc, 0u, stream, P_APP << 24, d.key0, d.key1).x) < d.den_adoption;
+}
+// Days from a test to its result: uniform over test_dmin..test_dmax from lane 1 of
+// AGENT2 on the test day, k = floor(x n / 2^32).
+__device__ __forceinline__ int result_delay(const Dev& d, uint32_t loc, uint32_t stream, int test_day) {
+  const uint32_t n = (uint32_t)(d.test_dmax - d.test_dmin + 1);
+  if (n <= 1u) return d.test_dmin;
+  const uint32_t x = philox(loc, (uint32_t)test_day, stream, P_AGENT2 << 24, d.key0, d.key1).y;
+  return d.test_dmin + (int)(((uint64_t)x * n) >> 32);
+}
+
 // ---- eleven-stage course (section 3, "Agent State Definition", "Disease Progression") --
 // An infection on day t draws the whole path from lanes 0..3 of the course's block 0
 // (asymptomatic with p_asym[a], else severe with p_severe[a], else mild; a severe
@@ -142,12 +156,27 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
     const RepInfo& ri = d.rep[tl.x];
     AgentState a = d.state[i];
     const AgentState a0 = a;
-    if ((a.flags & 1) && t == (int)a.test_day + d.test_delay) {
+    const uint32_t loc = (uint32_t)(i - ri.start);
+    if ((a.flags & 1) && t == (int)a.test_day + result_delay(d, loc, ri.stream, a.test_day)) {
       if (a.flags & 2) {
         pos_due = true;
         if (d.qdays > 0) a.q_until = (int16_t)(t + d.qdays);
       }
-      a.flags = 0;
+      a.flags = (uint8_t)(a.flags & ~3);
+    }
+    // a positive app user notifies every contact of the last den_window days (its rows
+    // of those days' graphs; the graph is symmetric); the contacts check app access and
+    // quarantine themselves in the fused step
+    if (d.den_on && pos_due && app_user(d, loc, ri.stream)) {
+      for (int k = 1; k <= d.den_window && t - k >= 0; ++k) {
+        const int slot = (t - k) % d.den_window;
+        const int32_t* rp = d.ring_rp + (size_t)slot * (d.N + 1);
+        const int32_t* col = d.ring_col + (size_t)slot * d.ecap;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+          const int j = col[e];
+          atomicOr(&d.den_mask[j >> 5], 1u << (j & 31));
+        }
+      }
     }
     if (d.dropout > 0.f && t < (int)a.q_until) {
       const uint4 b = philox((uint32_t)(i - ri.start), (uint32_t)t, ri.stream, P_AGENT2 << 24,
@@ -634,7 +663,7 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
       }
     }
   }
-  bool is_new = false, near = false, tested = false;
+  bool is_new = false, near = false, tested = false, notified = false;
   if (live) {
     const uint32_t loc = (uint32_t)(i - ri.start);
     bool immune = false;
@@ -668,8 +697,17 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
     } else if (st0 == ABM_STAGE_I) {
       if (tau == d.e_days + d.i_days) a.stage = u01(b.y) < d.p_death[age] ? ABM_STAGE_M : ABM_STAGE_R;
     }
-    if (d.test_rate > 0.f && st0 != ABM_STAGE_M && t >= (int)a.q_until && !(a.flags & 1)) {
-      if (u01(b.z) < d.test_rate) {
+    // contacts of today's positive app users that use the app themselves and are not in
+    // quarantine are told to test tomorrow
+    if (d.den_on && ((d.den_mask[i >> 5] >> (i & 31)) & 1u) && t >= (int)a.q_until)
+      notified = app_user(d, loc, ri.stream);
+    if ((d.test_rate > 0.f || d.den_on) && st0 != ABM_STAGE_M && t >= (int)a.q_until && !(a.flags & 1)) {
+      bool sel = u01(b.z) < d.test_rate;
+      if (!sel && d.den_on && (a.flags & 4)) {    // notified yesterday: tests with the compliance
+        const uint4 b2 = philox(loc, (uint32_t)t, ri.stream, P_AGENT2 << 24, d.key0, d.key1);
+        sel = u01(b2.z) < d.den_compliance;
+      }
+      if (sel) {
         tested = true;
         const bool infected = st0 != ABM_STAGE_S && st0 != ABM_STAGE_R && st0 != ABM_STAGE_M;
         const bool pos = infected && u01(b.w) < d.sens;
@@ -677,14 +715,16 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
         a.test_day = (int16_t)t;
       }
     }
+    a.flags = (uint8_t)((a.flags & ~4) | (notified ? 4 : 0));
     d.state[i] = a;
   }
   const int st = live ? (int)a.stage : -1;
-  const bool v[12] = {st == ABM_STAGE_S, stage_e(st), stage_i(st), st == ABM_STAGE_R, st == ABM_STAGE_M,
-                      st == ABM_STAGE_HOSP, st == ABM_STAGE_ICU, is_new, tested, dose1, dose2, near};
-  const int sl[12] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_HOSP, ABM_C_ICU, ABM_C_NEW,
-                      ABM_C_TESTS, ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR};
-  block_count_store<12>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
+  const bool v[13] = {st == ABM_STAGE_S, stage_e(st), stage_i(st), st == ABM_STAGE_R, st == ABM_STAGE_M,
+                      st == ABM_STAGE_HOSP, st == ABM_STAGE_ICU, is_new, tested, dose1, dose2, near,
+                      notified};
+  const int sl[13] = {ABM_C_S, ABM_C_E, ABM_C_I, ABM_C_R, ABM_C_M, ABM_C_HOSP, ABM_C_ICU, ABM_C_NEW,
+                      ABM_C_TESTS, ABM_C_DOSE1, ABM_C_DOSE2, ABM_C_NEAR, ABM_C_NOTIFIED};
+  block_count_store<13>(v, sl, d.tile_counts + (size_t)blockIdx.x * TILE_NC);
 }
 
 // ---- end of day: tile counts -> per-replicate counts -> trajectory ----------------
@@ -804,6 +844,25 @@ __global__ void k_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t
 
 __global__ void k_set_day(Dev d, int32_t day) { *d.day = day; }
 
+// The day's graph (row pointers and columns) into its slot of the notification ring.
+__global__ __launch_bounds__(TILE) void k_den_store(Dev d) {
+  if (*d.flags) return;
+  const int slot = *d.day % d.den_window;
+  int32_t* rp = d.ring_rp + (size_t)slot * (d.N + 1);
+  int32_t* col = d.ring_col + (size_t)slot * d.ecap;
+  const int64_t E = min((int64_t)d.row_ptr[d.N], d.ecap);
+  const int64_t n = max(E, (int64_t)d.N + 1);
+  for (int64_t k = (int64_t)blockIdx.x * TILE + threadIdx.x; k < n; k += (int64_t)gridDim.x * TILE) {
+    if (k <= d.N) rp[k] = d.row_ptr[k];
+    if (k < E) col[k] = d.col[k];
+  }
+}
+
+__global__ __launch_bounds__(TILE) void k_den_clear(Dev d) {
+  const int nw = (d.N + 31) / 32;
+  for (int k = blockIdx.x * TILE + threadIdx.x; k < nw; k += gridDim.x * TILE) d.den_mask[k] = 0u;
+}
+
 void launch_pre(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pre, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
@@ -895,6 +954,12 @@ void launch_recount(const Dev& d, hipStream_t s) {
 void launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, ctr, n, out);
+}
+void launch_den_store(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_den_store, dim3(2048), dim3(TILE), 0, s, d);
+}
+void launch_den_clear(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_den_clear, dim3(256), dim3(TILE), 0, s, d);
 }
 void launch_set_day(const Dev& d, int32_t day, hipStream_t s) {
   hipLaunchKernelGGL(k_set_day, dim3(1), dim3(1), 0, s, d, day);

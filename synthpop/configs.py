@@ -29,6 +29,10 @@ BASE = dict(
     e_days=5, i_days=10,
     quarantine_days=0, test_delay=2, quarantine_dropout=0.0,
     test_rate=0.0, test_sensitivity=0.95,
+    test_delay_max=2,                    # result after test_delay .. test_delay_max days (uniform)
+    app_adoption=0.0,                    # digital exposure notification: app users' share (0 = off)
+    den_compliance=0.8,                  # notified app users who test the next day
+    den_window=7,                        # days of contacts a positive result notifies
     vacc_rate=0.0, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12,
     strategy=STRAT_STANDARD,
     mode=MODE_HARD, gumbel_tau=0.5, checkpoint_every=10,
@@ -51,6 +55,11 @@ BASE = dict(
     n_steps=180,
     edge_capacity=0,
 )
+
+# the three test types of section 4 (accuracy read as sensitivity; turnaround in days)
+TEST_TYPES = {"rt_pcr": dict(test_sensitivity=0.95, test_delay=3, test_delay_max=5),
+              "antigen": dict(test_sensitivity=0.65, test_delay=2, test_delay_max=2),
+              "point_of_care": dict(test_sensitivity=0.85, test_delay=1, test_delay_max=1)}
 
 INTERVENTIONS = dict(quarantine_days=14, test_delay=2, test_rate=0.05, test_sensitivity=0.95,
                      vacc_rate=0.005, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12)

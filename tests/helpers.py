@@ -23,7 +23,8 @@ def to_records(st, dtype):
     N = st["stage"].size
     rec = np.zeros(N, dtype)
     rec["stage"] = st["stage"]
-    rec["flags"] = st["pending"].astype(np.uint8) | (st["positive"].astype(np.uint8) << 1)
+    rec["flags"] = (st["pending"].astype(np.uint8) | (st["positive"].astype(np.uint8) << 1)
+                    | (st["notified"].astype(np.uint8) << 2))
     rec["vacc"] = st["vacc"]
     for k in ("t_exp", "q_until", "test_day", "d1", "d2"):
         rec[k] = st[k]
@@ -39,12 +40,13 @@ def from_records(rec, latch):
               pending=(rec["flags"] & 1).astype(bool), positive=(rec["flags"] & 2).astype(bool),
               vacc=rec["vacc"].astype(np.int64), d1=rec["d1"].astype(np.int64),
               d2=rec["d2"].astype(np.int64), latch=np.asarray(latch, bool).copy(),
-              course=rec["course"].astype(np.int64), t_next=rec["t_next"].astype(np.int64))
+              course=rec["course"].astype(np.int64), t_next=rec["t_next"].astype(np.int64),
+              notified=(rec["flags"] & 4).astype(bool))
     return st
 
 
 FIELDS = ("stage", "t_exp", "q_until", "test_day", "pending", "positive", "vacc", "d1", "d2",
-          "course", "t_next")
+          "course", "t_next", "notified")
 
 
 def state_mismatch(a, b):
