@@ -208,6 +208,34 @@ def course_run(days: int = 40, warmup: int = 5):
             "hospitalised_peak": int(c[:, 0, 13].max()), "icu_peak": int(c[:, 0, 14].max())}
 
 
+def den_run(days: int = 30, warmup: int = 10):
+    """The 50M-agent day with exposure notification on (app adoption 0.3, RT-PCR
+    testing): each day's graph is built into its slot of the 7-day ring, and the
+    pre-pass reads a positive app user's rows of the last seven days."""
+    import torch
+    from paper_2110_04421_amd.sim import Simulator
+    from synthpop import workload
+    from synthpop.configs import TEST_TYPES
+    p, pop = workload(2, n_steps=days + warmup, app_adoption=0.3, den_compliance=0.8,
+                      **TEST_TYPES["rt_pcr"])
+    with Simulator(p, pop, autotune=True) as s:
+        s.run(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = s.run(days)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    with Simulator(p, pop, profile=True, autotune=True) as s:
+        s.run(warmup)
+        s.profile_reset()
+        s.run(5)
+        prof = s.profile()
+    pre = prof["pre"]
+    return {"workload": "plain-50M, exposure notification", "agents": int(pop.n_agents), "days_timed": days,
+            "ms_per_day": wall / days * 1e3, "pre_ms": pre[0] / max(pre[1], 1),
+            "notified_per_day": float(c[:, 0, 15].mean())}
+
+
 def c1_run(reps: int = 3):
     """Full 180-day runs of the 100k-agent workload (HIP-graph day loop)."""
     import torch
@@ -402,6 +430,8 @@ def main():
         line["adjoint"] = adjoint_cost()
         log("eleven-stage course at 50M agents")
         line["course"] = course_run()
+        log("exposure notification at 50M agents")
+        line["notification"] = den_run()
     if not args.no_extras and not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()

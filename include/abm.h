@@ -154,7 +154,8 @@ typedef struct {
   /* testing turnaround and digital exposure notification (section 4) */
   int32_t test_delay_max;          /* result after test_delay .. test_delay_max days,
                                       uniform (the RT-PCR test's 3..5); = test_delay: fixed */
-  float app_adoption;              /* share of agents with the notification app; 0 = off  */
+  float app_adoption;              /* share of agents with the notification app; 0 = off;
+                                      > 0 keeps den_window days of graphs (hard mode only) */
   float den_compliance;            /* notified app users who test the next day             */
   int32_t den_window;              /* days of contacts a positive result notifies (1..30) */
 } abm_params;

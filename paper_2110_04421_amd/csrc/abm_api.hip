@@ -114,6 +114,11 @@ struct Sizes {
   int64_t fseg = 1;
 };
 
+// element strides of the notification ring's slots, rounded to 64 elements so that
+// every slot starts on a 256-byte boundary (the message kernel reads 16-byte groups)
+int64_t ring_rstride(const Sizes& z) { return (z.N + 1 + 63) & ~(int64_t)63; }
+int64_t ring_cstride(const Sizes& z) { return (z.ecap + 63) & ~(int64_t)63; }
+
 }  // namespace
 
 struct abm_sim {
@@ -123,8 +128,10 @@ struct abm_sim {
   Dev d{};
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // one day graph, or one per ring slot when the day's graph is built into the
+  // notification ring (the slot is baked into the captured kernel arguments)
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
   int err = ABM_OK;
   std::string msg;
   int32_t host_day = 0;
@@ -193,6 +200,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   if (!(p->app_adoption >= 0.f && p->app_adoption <= 1.f)) return bad("app_adoption out of [0, 1]");
   if (!(p->den_compliance >= 0.f && p->den_compliance <= 1.f)) return bad("den_compliance out of [0, 1]");
   if (p->app_adoption > 0.f) {
+    if (p->mode != ABM_HARD) return bad("exposure notification runs in hard mode only");
     if (p->den_window < 1 || p->den_window > 30) return bad("den_window out of [1, 30]");
     if (p->test_delay < 1) return bad("test_delay must be >= 1");
   }
@@ -377,10 +385,10 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.lambda = L.take<float>(z.N);
   o.own = L.take<uint16_t>(z.N);
   o.recv = L.take<uint32_t>(z.N);
-  o.row_ptr = L.take<int32_t>(z.N + 1);
+  if (p.app_adoption <= 0.f) o.row_ptr = L.take<int32_t>(z.N + 1);
   o.cur_occ = L.take<int32_t>(z.N);
   o.cur_rand = L.take<int32_t>(z.N);
-  o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
+  if (p.app_adoption <= 0.f) o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
   o.w = L.take<float>(z.ecap);
   o.scan_part = L.take<int64_t>(z.nscan + 1);
   o.vhist = L.take<int32_t>(z.ntiles * NBUCKET);
@@ -393,8 +401,9 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
   o.day = L.take<int32_t>(1);
   if (p.app_adoption > 0.f) {
-    o.ring_rp = L.take<int32_t>((int64_t)p.den_window * (z.N + 1));
-    o.ring_col = L.take<int32_t>((int64_t)p.den_window * z.ecap);
+    // the day's graph lives in slot day % den_window; slots start on 256-byte bounds
+    o.ring_rp = L.take<int32_t>((int64_t)p.den_window * ring_rstride(z));
+    o.ring_col = L.take<int32_t>((int64_t)p.den_window * ring_cstride(z) + 4);
     o.den_mask = L.take<uint32_t>((z.N + 31) / 32 + 1);
   }
   o.flags = L.take<int32_t>(1);
@@ -440,8 +449,21 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
 // The day's kernel chain: interventions, graph build (named steps), force of
 // infection, fused step, bookkeeping.  With `ev`, an event is recorded before every
 // named step and after the last one.
-void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) {
-  const Dev& d = s->d;
+// The kernel arguments of day `day`.  With exposure notification on, that day's graph
+// (row pointers and columns) is built straight into ring slot day % den_window, where
+// the pre-pass of the following den_window days reads it: no copy.
+Dev day_dev(const abm_sim* s, int64_t day) {
+  Dev d = s->d;
+  if (d.den_on) {
+    const int64_t slot = day % d.den_window;
+    d.row_ptr = d.ring_rp + slot * d.ring_rstride;
+    d.col = d.ring_col + slot * d.ring_cstride;
+  }
+  return d;
+}
+
+void enqueue_day(abm_sim* s, int64_t day, hipStream_t st, const std::vector<hipEvent_t>* ev) {
+  const Dev d = day_dev(s, day);
   int k = 0;
   auto mark = [&]() {
     if (ev) (void)hipEventRecord((*ev)[k], st);
@@ -457,10 +479,6 @@ void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) 
     mark();
     launch_build_step(d, b, st);
   }
-  if (d.den_on) {
-    mark();
-    launch_den_store(d, st);
-  }
   mark();
   launch_message(d, st);
   mark();
@@ -474,7 +492,6 @@ void enqueue_day(abm_sim* s, hipStream_t st, const std::vector<hipEvent_t>* ev) 
 void name_kernels(abm_sim* s) {
   s->names = {"pre", "mask", "vplan"};
   for (int b = 0; b < build_steps(s->d); ++b) s->names.push_back(build_step_name(s->d, b));
-  if (s->d.den_on) s->names.push_back("den_store");
   for (const char* n : {"message", "fused", "finalize"}) s->names.push_back(n);
   s->nk = (int)s->names.size();
   s->ms.assign(s->nk, 0.0);
@@ -644,10 +661,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.lambda = (float*)(ws + o.lambda);
   d.own = (uint16_t*)(ws + o.own);
   d.recv = (uint32_t*)(ws + o.recv);
-  d.row_ptr = (int32_t*)(ws + o.row_ptr);
+  if (!d.den_on) d.row_ptr = (int32_t*)(ws + o.row_ptr);
   d.cur_occ = (int32_t*)(ws + o.cur_occ);
   d.cur_rand = (int32_t*)(ws + o.cur_rand);
-  d.col = (int32_t*)(ws + o.col);
+  if (!d.den_on) d.col = (int32_t*)(ws + o.col);
   d.w = (float*)(ws + o.w);
   d.scan_part = (int64_t*)(ws + o.scan_part);
   d.vhist = (int32_t*)(ws + o.vhist);
@@ -669,6 +686,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   if (d.den_on) {
     d.ring_rp = (int32_t*)(ws + o.ring_rp);
     d.ring_col = (int32_t*)(ws + o.ring_col);
+    d.ring_rstride = ring_rstride(z);
+    d.ring_cstride = ring_cstride(z);
+    d.row_ptr = d.ring_rp;                 // slot 0: day 0's graph
+    d.col = d.ring_col;
     d.den_mask = (uint32_t*)(ws + o.den_mask);
   }
   d.flags = (int32_t*)(ws + o.flags);
@@ -817,7 +838,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));
   HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 4, st));
   if (d.den_on) {                          // no graphs before day 0: empty rows
-    HIPCHK(s, hipMemsetAsync(ws + o.ring_rp, 0, (size_t)p->den_window * (N + 1) * 4, st));
+    HIPCHK(s, hipMemsetAsync(ws + o.ring_rp, 0, (size_t)p->den_window * d.ring_rstride * 4, st));
     HIPCHK(s, hipMemsetAsync(ws + o.den_mask, 0, ((N + 31) / 32 + 1) * 4, st));
   }
   HIPCHK(s, hipMemsetAsync(ws + o.flags, 0, 4, st));
@@ -839,10 +860,15 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   const bool use_graph = !(p->flags & (ABM_FLAG_PROFILE | ABM_FLAG_NO_GRAPH)) && p->mode == ABM_HARD;
   if (use_graph) {
     HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-    HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_day(s, s->cap_stream, nullptr);
-    HIPCHK(s, hipStreamEndCapture(s->cap_stream, &s->graph));
-    HIPCHK(s, hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    const int ng = d.den_on ? d.den_window : 1;
+    s->graphs.assign(ng, nullptr);
+    s->execs.assign(ng, nullptr);
+    for (int g = 0; g < ng; ++g) {
+      HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+      enqueue_day(s, g, s->cap_stream, nullptr);
+      HIPCHK(s, hipStreamEndCapture(s->cap_stream, &s->graphs[g]));
+      HIPCHK(s, hipGraphInstantiate(&s->execs[g], s->graphs[g], nullptr, nullptr, 0));
+    }
   }
   return ABM_OK;
 }
@@ -856,8 +882,8 @@ int abm_step(abm_sim* s, int32_t n_days) {
     return s->fail(ABM_E_STATE, "stepping past n_steps (%d)", (int)s->z.T);
   const bool timed = (s->p.flags & ABM_FLAG_PROFILE) != 0;
   for (int k = 0; k < n_days; ++k) {
-    if (s->exec) {
-      HIPCHK(s, hipGraphLaunch(s->exec, s->stream));
+    if (!s->execs.empty()) {
+      HIPCHK(s, hipGraphLaunch(s->execs[s->host_day % s->execs.size()], s->stream));
     } else if (timed) {
       if (s->prof_used == s->prof_sets.size()) {
         std::vector<hipEvent_t> ev(s->nk + 1);
@@ -866,10 +892,10 @@ int abm_step(abm_sim* s, int32_t n_days) {
       }
       const std::vector<hipEvent_t>* ev = &s->prof_sets[s->prof_used];
       ++s->prof_used;
-      enqueue_day(s, s->stream, ev);
+      enqueue_day(s, s->host_day, s->stream, ev);
       HIPCHK(s, hipGetLastError());
     } else {
-      enqueue_day(s, s->stream, nullptr);
+      enqueue_day(s, s->host_day, s->stream, nullptr);
       HIPCHK(s, hipGetLastError());
     }
     ++s->host_day;
@@ -904,15 +930,17 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
   const void* src = nullptr;
   size_t n = 0;
   int32_t E = 0;
+  // the graph of the last day built (day 0's before the first step)
+  const Dev last = day_dev(s, std::max(0, s->host_day - 1));
   if (what == ABM_GET_COL || what == ABM_GET_W) {
-    HIPCHK(s, hipMemcpy(&E, s->d.row_ptr + N, 4, hipMemcpyDeviceToHost));
+    HIPCHK(s, hipMemcpy(&E, last.row_ptr + N, 4, hipMemcpyDeviceToHost));
   }
   switch (what) {
     case ABM_GET_STATE: src = s->d.state; n = N * sizeof(AgentState); break;
     case ABM_GET_LAMBDA: src = s->d.lambda; n = N * 4; break;
     case ABM_GET_CODE: src = s->d.code; n = N; break;
-    case ABM_GET_ROWPTR: src = s->d.row_ptr; n = (N + 1) * 4; break;
-    case ABM_GET_COL: src = s->d.col; n = (size_t)E * 4; break;
+    case ABM_GET_ROWPTR: src = last.row_ptr; n = (N + 1) * 4; break;
+    case ABM_GET_COL: src = last.col; n = (size_t)E * 4; break;
     case ABM_GET_W: src = s->d.w; n = (size_t)E * 4; break;
     case ABM_GET_ATAB: src = s->d.atab; n = ATAB * 4; break;
     case ABM_GET_POISSON: src = s->d.ptab; n = NPT * 64 * 4; break;
@@ -961,12 +989,12 @@ int abm_set_state(abm_sim* s, int32_t day, const uint8_t* h_latch, const abm_age
   HIPCHK(s, hipMemcpyAsync(s->d.latch, h_latch, s->z.R, hipMemcpyHostToDevice, s->stream));
   if (s->d.den_on) {
     // the notification ring holds the graphs of the den_window days before `day`
-    HIPCHK(s, hipMemsetAsync(s->ws + s->o.ring_rp, 0, (size_t)s->d.den_window * (s->z.N + 1) * 4, s->stream));
+    HIPCHK(s, hipMemsetAsync(s->ws + s->o.ring_rp, 0, (size_t)s->d.den_window * s->d.ring_rstride * 4, s->stream));
     HIPCHK(s, hipMemsetAsync(s->ws + s->o.den_mask, 0, ((s->z.N + 31) / 32 + 1) * 4, s->stream));
     for (int32_t dd = std::max(0, day - s->d.den_window); dd < day; ++dd) {
-      launch_set_day(s->d, dd, s->stream);
-      for (int b = 0; b < build_steps(s->d); ++b) launch_build_step(s->d, b, s->stream);
-      launch_den_store(s->d, s->stream);
+      const Dev dv = day_dev(s, dd);
+      launch_set_day(dv, dd, s->stream);
+      for (int b = 0; b < build_steps(dv); ++b) launch_build_step(dv, b, s->stream);
     }
   }
   launch_set_day(s->d, day, s->stream);
@@ -986,8 +1014,10 @@ int abm_sync(abm_sim* s) {
 void abm_destroy(abm_sim* s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  for (auto e : s->execs)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (auto g : s->graphs)
+    if (g) (void)hipGraphDestroy(g);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   for (auto& ev : s->prof_sets)
     for (auto e : ev) (void)hipEventDestroy(e);

@@ -77,8 +77,9 @@ struct Dev {
   int32_t test_dmin, test_dmax; // result turnaround range (days)
   int32_t den_on, den_window;   // digital exposure notification
   float den_adoption, den_compliance;
-  int32_t* ring_rp;             // [den_window][N+1] row pointers of the last days' graphs
-  int32_t* ring_col;            // [den_window][ecap] their columns
+  int32_t* ring_rp;             // [den_window][ring_rstride] row pointers of the last days' graphs
+  int32_t* ring_col;            // [den_window][ring_cstride] their columns
+  int64_t ring_rstride, ring_cstride;  // slot strides (elements); day t's graph is slot t % den_window
   uint32_t* den_mask;           // [(N+31)/32] contacts of today's positive app users
 
   const RepInfo* rep;
@@ -247,7 +248,6 @@ void launch_adj_zero(const Dev& d, hipStream_t s);
 void launch_adj_day(const Dev& d, int32_t t, int32_t seg_slot, hipStream_t s);
 void launch_adj_ibar(const Dev& d, int32_t t, hipStream_t s);
 void launch_adj_theta(const Dev& d, hipStream_t s);
-void launch_den_store(const Dev& d, hipStream_t s);   // the day's graph into the notification ring
 void launch_den_clear(const Dev& d, hipStream_t s);   // end of day: notification marks consumed
 void launch_set_day(const Dev& d, int32_t day, hipStream_t s);
 

@@ -170,8 +170,8 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
     if (d.den_on && pos_due && app_user(d, loc, ri.stream)) {
       for (int k = 1; k <= d.den_window && t - k >= 0; ++k) {
         const int slot = (t - k) % d.den_window;
-        const int32_t* rp = d.ring_rp + (size_t)slot * (d.N + 1);
-        const int32_t* col = d.ring_col + (size_t)slot * d.ecap;
+        const int32_t* rp = d.ring_rp + (size_t)slot * d.ring_rstride;
+        const int32_t* col = d.ring_col + (size_t)slot * d.ring_cstride;
         for (int e = rp[i]; e < rp[i + 1]; ++e) {
           const int j = col[e];
           atomicOr(&d.den_mask[j >> 5], 1u << (j & 31));
@@ -845,19 +845,6 @@ __global__ void k_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t
 __global__ void k_set_day(Dev d, int32_t day) { *d.day = day; }
 
 // The day's graph (row pointers and columns) into its slot of the notification ring.
-__global__ __launch_bounds__(TILE) void k_den_store(Dev d) {
-  if (*d.flags) return;
-  const int slot = *d.day % d.den_window;
-  int32_t* rp = d.ring_rp + (size_t)slot * (d.N + 1);
-  int32_t* col = d.ring_col + (size_t)slot * d.ecap;
-  const int64_t E = min((int64_t)d.row_ptr[d.N], d.ecap);
-  const int64_t n = max(E, (int64_t)d.N + 1);
-  for (int64_t k = (int64_t)blockIdx.x * TILE + threadIdx.x; k < n; k += (int64_t)gridDim.x * TILE) {
-    if (k <= d.N) rp[k] = d.row_ptr[k];
-    if (k < E) col[k] = d.col[k];
-  }
-}
-
 __global__ __launch_bounds__(TILE) void k_den_clear(Dev d) {
   const int nw = (d.N + 31) / 32;
   for (int k = blockIdx.x * TILE + threadIdx.x; k < nw; k += gridDim.x * TILE) d.den_mask[k] = 0u;
@@ -954,9 +941,6 @@ void launch_recount(const Dev& d, hipStream_t s) {
 void launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, ctr, n, out);
-}
-void launch_den_store(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_den_store, dim3(2048), dim3(TILE), 0, s, d);
 }
 void launch_den_clear(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_den_clear, dim3(256), dim3(TILE), 0, s, d);

@@ -16,6 +16,7 @@ reading, not the paper's eleven-stage model, and the population is synthetic, so
 numbers are comparable between strategies, not with the paper's figures.
 
     python -m paper_2110_04421_amd.study --out study.json
+    python -m paper_2110_04421_amd.study --interventions --course --out interventions.json
 """
 from __future__ import annotations
 
@@ -84,6 +85,36 @@ def vaccine_study(n_agents=100_000, reps=15, days=180, effs=(0.6, 0.7, 0.8, 0.9)
     return out
 
 
+def intervention_study(n_agents=100_000, reps=10, days=120, R=13.0, disease_model=1, log=None):
+    """Section 4's sample comparison: no intervention, self-quarantine (testing and 14-day
+    quarantine), self-quarantine + exposure notification (app adoption 0.3, compliance
+    0.8), and the same with the rapid point-of-care test (1-day turnaround, 0.85); 10
+    replicates of 120 days.  RT-PCR is the test otherwise.  Quartiles of cumulative
+    infections and deaths per configuration."""
+    import dataclasses
+    from synthpop import workload
+    from synthpop.configs import TEST_TYPES
+    p, pop = workload(1, n=n_agents, n_rep=reps)
+    pop = dataclasses.replace(pop, R=np.full(reps, R, np.float32))
+    base = dict(p, vacc_rate=0.0, disease_model=int(disease_model), test_rate=0.05, quarantine_days=14)
+    configs = {
+        "no_intervention": dict(base, test_rate=0.0, quarantine_days=0),
+        "self_quarantine": dict(base, **TEST_TYPES["rt_pcr"]),
+        "self_quarantine_den": dict(base, app_adoption=0.3, den_compliance=0.8, **TEST_TYPES["rt_pcr"]),
+        "self_quarantine_den_point_of_care": dict(base, app_adoption=0.3, den_compliance=0.8,
+                                                  **TEST_TYPES["point_of_care"]),
+    }
+    out = {"agents": n_agents, "replicates": reps, "days": days, "R": R,
+           "disease_model": "eleven-stage course" if disease_model else "SEIRM", "configs": {}}
+    for name, q in configs.items():
+        deaths, infected, doses, start, hosp = run_config(q, pop, days)
+        out["configs"][name] = {"infected_quartiles": quartiles(infected), "deaths_quartiles": quartiles(deaths),
+                                "hospital_peak_quartiles": quartiles(hosp)}
+        if log:
+            log(f"{name}: infected median {np.median(infected):.0f}, deaths median {np.median(deaths):.0f}")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--agents", type=int, default=100_000)
@@ -91,10 +122,15 @@ def main(argv=None):
     ap.add_argument("--days", type=int, default=180)
     ap.add_argument("--R", type=float, default=13.0)
     ap.add_argument("--course", action="store_true", help="the eleven-stage course instead of SEIRM")
+    ap.add_argument("--interventions", action="store_true",
+                    help="section 4's comparison of interventions instead of the dosing study")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda m: print(f"[study {time.strftime('%H:%M:%S')}] {m}", file=sys.stderr, flush=True)
-    s = vaccine_study(a.agents, a.reps, a.days, R=a.R, disease_model=1 if a.course else 0, log=log)
+    if a.interventions:
+        s = intervention_study(a.agents, R=a.R, disease_model=1 if a.course else 0, log=log)
+    else:
+        s = vaccine_study(a.agents, a.reps, a.days, R=a.R, disease_model=1 if a.course else 0, log=log)
     txt = json.dumps(s, indent=1)
     print(txt)
     if a.out:
