@@ -60,9 +60,9 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
     lb = leaf_bits(N, C)
     nbt, nb1 = -(-N // 1024), -(-N // (1 << (lb + 8)))
     table = {
-        # force of infection: col + 1 mask bit per edge, w + code byte per infectious
-        # edge; row_ptr, age, lambda per row
-        "message": 4.125 * E + 5.0 * Einf + 9.0 * N,
+        # force of infection: col (source and network) + 1 mask bit per edge, a code
+        # byte per infectious edge; row_ptr, age, lambda per row
+        "message": 4.125 * E + 1.0 * Einf + 9.0 * N,
         # partitioned builder
         # draws: static record in; counts, own list and histograms out
         "pb_gen": 18.0 * N + 4.0 * C + 4.0 * nbt * nb1,
@@ -72,9 +72,9 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         "pb_scatter2": 14.0 * C,                   # 6-byte entries in, 8-byte leaf entries out
         "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
         "rowptr": 18.0 * N,
-        "pb_assemble": 8.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col + w out
+        "pb_assemble": 4.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col out
         # claim-based builder
-        "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 8.0 * E + 8.0 * C + 24.0 * N,
+        "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 4.0 * E + 8.0 * C + 24.0 * N,
         "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
         # agent kernels
         "pre": (18.0 if vacc else 17.0) * N,       # state in, code out (age in with vaccination)

@@ -166,7 +166,8 @@ typedef struct {
   int32_t n_households;            /* H */
   int32_t n_workplaces;            /* W (0 if none) */
   int32_t reserved;
-  const int64_t* agent_offset;     /* [R+1], agent_offset[0] = 0, N = agent_offset[R]   */
+  const int64_t* agent_offset;     /* [R+1], agent_offset[0] = 0, N = agent_offset[R];
+                                      N < 2^30 (a graph column holds a 30-bit agent id)  */
   const uint8_t* age;              /* [N] age group 0..8                                  */
   const int32_t* hh_start;         /* [H+1] household h = agents [hh_start[h], hh_start[h+1]), sizes 1..255 */
   const uint8_t* occupation;       /* [N] occupation 0..22                                */

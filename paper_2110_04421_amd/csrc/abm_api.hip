@@ -97,7 +97,7 @@ struct Layout {
 
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, dtab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
-      cur_occ, cur_rand, col, w, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
+      cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds, ring_rp, ring_col, den_mask;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
       pb_b1w, pb_buf2, pb_rsrc, pb_rstart;
@@ -231,7 +231,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   for (int r = 0; r < R; ++r)
     if (pop->agent_offset[r + 1] <= pop->agent_offset[r]) return bad("empty or decreasing replicate");
   const int64_t N = pop->agent_offset[R];
-  if (N >= (int64_t)1 << 31) return bad("more than 2^31 - 1 agents");
+  if (N >= (int64_t)1 << 30) return bad("more than 2^30 - 1 agents");   // 30-bit column agent ids
   z.N = N;
   z.R = R;
   z.T = p->n_steps;
@@ -389,7 +389,6 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.cur_occ = L.take<int32_t>(z.N);
   o.cur_rand = L.take<int32_t>(z.N);
   if (p.app_adoption <= 0.f) o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
-  o.w = L.take<float>(z.ecap);
   o.scan_part = L.take<int64_t>(z.nscan + 1);
   o.vhist = L.take<int32_t>(z.ntiles * NBUCKET);
   o.vplan = L.take<int32_t>(2 * z.R);
@@ -665,7 +664,6 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.cur_occ = (int32_t*)(ws + o.cur_occ);
   d.cur_rand = (int32_t*)(ws + o.cur_rand);
   if (!d.den_on) d.col = (int32_t*)(ws + o.col);
-  d.w = (float*)(ws + o.w);
   d.scan_part = (int64_t*)(ws + o.scan_part);
   d.vhist = (int32_t*)(ws + o.vhist);
   d.vplan = (int32_t*)(ws + o.vplan);
@@ -941,7 +939,7 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
     case ABM_GET_CODE: src = s->d.code; n = N; break;
     case ABM_GET_ROWPTR: src = last.row_ptr; n = (N + 1) * 4; break;
     case ABM_GET_COL: src = last.col; n = (size_t)E * 4; break;
-    case ABM_GET_W: src = s->d.w; n = (size_t)E * 4; break;
+    case ABM_GET_W: src = last.col; n = (size_t)E * 4; break;   // decoded below
     case ABM_GET_ATAB: src = s->d.atab; n = ATAB * 4; break;
     case ABM_GET_POISSON: src = s->d.ptab; n = NPT * 64 * 4; break;
     case ABM_GET_LATCH: src = s->d.latch; n = s->z.R; break;
@@ -973,6 +971,20 @@ int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes) {
   if (n) {
     HIPCHK(s, hipMemcpyAsync(h_dst, src, n, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  // column words carry the contact network in their top two bits: split into the
+  // source agent (ABM_GET_COL) or the network's weight (ABM_GET_W)
+  if (what == ABM_GET_COL) {
+    uint32_t* c = (uint32_t*)h_dst;
+    for (int32_t e = 0; e < E; ++e) c[e] &= 0x3FFFFFFFu;
+  } else if (what == ABM_GET_W) {
+    const float wt[4] = {s->p.w_household, s->p.w_occupation, s->p.w_random, s->p.w_random};
+    char* b = (char*)h_dst;
+    for (int32_t e = 0; e < E; ++e) {
+      uint32_t c;
+      std::memcpy(&c, b + 4 * (size_t)e, 4);
+      std::memcpy(b + 4 * (size_t)e, &wt[c >> 30], 4);
+    }
   }
   return ABM_OK;
 }

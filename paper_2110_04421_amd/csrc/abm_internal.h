@@ -104,8 +104,7 @@ struct Dev {
   int32_t* row_ptr;             // [N+1]
   int32_t* cur_occ;             // claim cursors into the received blocks
   int32_t* cur_rand;
-  int32_t* col;
-  float* w;
+  int32_t* col;                 // [E] source agent | network << 30 (col_agent, col_weight)
   int64_t* scan_part;           // [nscan + 1]
   int32_t nscan;
 
@@ -194,6 +193,18 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 
 __device__ __forceinline__ uint32_t lane4(const uint4& b, int l) {
   return l == 0 ? b.x : (l == 1 ? b.y : (l == 2 ? b.z : b.w));
+}
+
+// A CSR column word: the source agent in the low 30 bits, its contact network in the
+// top two (0 household, 1 occupation, 2 random).  The edge's weight is its network's
+// factor, so no per-edge weight is stored.
+constexpr uint32_t COL_AGENT = 0x3FFFFFFFu;
+__device__ __forceinline__ uint32_t col_word(uint32_t agent, uint32_t net) { return agent | (net << 30); }
+// (the three factors are passed as values: taken from the kernel arguments once, they
+// stay in registers, and the choice is two selects, not a load)
+__device__ __forceinline__ float col_weight(uint32_t c, float wh, float wo, float wr) {
+  const uint32_t n = c >> 30;
+  return n == 0u ? wh : (n == 1u ? wo : wr);
 }
 
 // (floor(x / 2^9) + 1/2) * 2^-23: odd multiples of 2^-24 in (0, 1), exact in FP32.

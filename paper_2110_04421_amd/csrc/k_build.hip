@@ -802,7 +802,7 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
       if (m != i) {
         if (staged) scol[pos - base] = m;
-        else { d.col[pos] = m; d.w[pos] = d.w_h; }
+        else d.col[pos] = m;
         ++pos;
       }
     const int os = wb + inc - c;
@@ -815,13 +815,13 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
       pos += kr;
       for (int q = 0; q < rr; ++q) pos_of[oend + rs + ro + q] = (uint16_t)((pos + q - base) | (2 << 14));
     } else {                                   // direct writes
-      for (int q = 0; q < ko; ++q) { d.col[pos + q] = (int)ob[os + q]; d.w[pos + q] = d.w_o; }
+      for (int q = 0; q < ko; ++q) d.col[pos + q] = (int)col_word(ob[os + q], 1u);
       pos += ko;
-      for (int q = 0; q < ro; ++q) { d.col[pos + q] = (int)d.pb_rsrc[g0 + rs + q]; d.w[pos + q] = d.w_o; }
+      for (int q = 0; q < ro; ++q) d.col[pos + q] = (int)col_word(d.pb_rsrc[g0 + rs + q], 1u);
       pos += ro;
-      for (int q = 0; q < kr; ++q) { d.col[pos + q] = (int)ob[os + ko + q]; d.w[pos + q] = d.w_r; }
+      for (int q = 0; q < kr; ++q) d.col[pos + q] = (int)col_word(ob[os + ko + q], 2u);
       pos += kr;
-      for (int q = 0; q < rr; ++q) { d.col[pos + q] = (int)d.pb_rsrc[g0 + rs + ro + q]; d.w[pos + q] = d.w_r; }
+      for (int q = 0; q < rr; ++q) d.col[pos + q] = (int)col_word(d.pb_rsrc[g0 + rs + ro + q], 2u);
     }
   }
   if (!staged) return;
@@ -863,12 +863,7 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     }
   }
   __syncthreads();
-  const float wt[3] = {d.w_h, d.w_o, d.w_r};
-  for (int k = threadIdx.x; k < end - base; k += TILE) {
-    const uint32_t v = (uint32_t)scol[k];
-    d.col[base + k] = (int32_t)(v & 0x3FFFFFFFu);
-    d.w[base + k] = wt[v >> 30];
-  }
+  for (int k = threadIdx.x; k < end - base; k += TILE) d.col[base + k] = scol[k];
 }
 
 // Named steps of a day's graph build.  With the partitioned builder off (populations

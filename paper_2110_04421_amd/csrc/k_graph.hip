@@ -82,7 +82,7 @@ __device__ __forceinline__ int count_contacts(const Dev& d, ContactGen& g, const
 // Own block (partners in draw order) and one claimed slot in each partner's received
 // block.  The claims of a batch are independent, so they are all in flight at once.
 __device__ __forceinline__ int fill_contacts(const Dev& d, ContactGen& g, const uint32_t* T,
-                                             int32_t* cursor, int own, int self, float wv) {
+                                             int32_t* cursor, int own, int self, uint32_t net) {
   const int k = g.count(T);
   for (int q0 = 1; q0 <= k; q0 += CLAIM_BATCH) {
     int p[CLAIM_BATCH], slot[CLAIM_BATCH];
@@ -94,9 +94,8 @@ __device__ __forceinline__ int fill_contacts(const Dev& d, ContactGen& g, const 
 #pragma unroll
     for (int b = 0; b < CLAIM_BATCH; ++b)
       if (p[b] >= 0) {
-        d.col[own + q0 + b - 1] = p[b];
-        d.w[own + q0 + b - 1] = wv;
-        d.col[slot[b]] = self;
+        d.col[own + q0 + b - 1] = (int32_t)col_word((uint32_t)p[b], net);
+        d.col[slot[b]] = (int32_t)col_word((uint32_t)self, net);
       }
   }
   return k;
@@ -235,23 +234,21 @@ __global__ __launch_bounds__(TILE) void k_fill(Dev d) {
   const StaticRec sr = d.srec[i];
   const uint32_t loc = (uint32_t)(i - ri.start);
   int pos = d.row_ptr[i];
-  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // received blocks' weights: canon
   for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m) {
     if (m == i) continue;
-    d.col[pos] = m;
-    d.w[pos] = wh;
+    d.col[pos] = m;                               // household: network 0
     ++pos;
   }
   const int own_occ = pos;
   ContactGen go = occ_gen(d, sr, loc, t, ri.stream);
-  const int ko = fill_contacts(d, go, T + sr.occ * 64, d.cur_occ, own_occ, i, wo);
+  const int ko = fill_contacts(d, go, T + sr.occ * 64, d.cur_occ, own_occ, i, 1u);
   const int own_rand = own_occ + ko + (int)(d.recv[i] >> 16);
   ContactGen gr = rand_gen(d, ri, loc, t);
-  fill_contacts(d, gr, T + (PT_AGE0 + sr.age) * 64, d.cur_rand, own_rand, i, wr);
+  fill_contacts(d, gr, T + (PT_AGE0 + sr.age) * 64, d.cur_rand, own_rand, i, 2u);
 }
 
-// Insertion sort of a short received block by initiator id; weights are uniform
-// inside a block so only the ids move.
+// Insertion sort of a short received block by initiator id.  Every word of a block
+// carries the same network bits, so signed order is initiator order.
 __device__ __forceinline__ void sort_block(int32_t* c, int n) {
   for (int a = 1; a < n; ++a) {
     const int32_t v = c[a];
@@ -304,10 +301,8 @@ __global__ __launch_bounds__(TILE) void k_canon(Dev d) {
   const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
   const int a = d.row_ptr[i] + (int)d.hhn[i] - 1 + (int)(o & 0xFFu);
   sort_small(d.col + a, ro);
-  for (int e = a; e < a + ro; ++e) d.w[e] = d.w_o;
   const int b = a + ro + (int)(o >> 8);
   sort_small(d.col + b, rr);
-  for (int e = b; e < b + rr; ++e) d.w[e] = d.w_r;
 }
 
 // In-degree counters start from zero each day (the hard step clears them in k_pre).

@@ -83,9 +83,9 @@ __global__ __launch_bounds__(TILE) void k_soft_message(Dev d, const float* x, fl
     const int cn = min(MSG_CHUNK, e1 - c0);
     for (int k = threadIdx.x; k < cn; k += TILE) {
       const int e = c0 + k;
-      uint32_t src = (uint32_t)d.col[e];
-      src = src < (uint32_t)d.N ? src : 0u;
-      term[k] = d.w[e] * x[src];
+      const uint32_t c = (uint32_t)d.col[e];
+      const uint32_t src = (c & COL_AGENT) < (uint32_t)d.N ? (c & COL_AGENT) : 0u;
+      term[k] = col_weight(c, d.w_h, d.w_o, d.w_r) * x[src];
     }
     __syncthreads();
     const int lo = max(rs, c0), hi = min(re, c0 + cn);

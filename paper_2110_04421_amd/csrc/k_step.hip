@@ -173,7 +173,7 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
         const int32_t* rp = d.ring_rp + (size_t)slot * d.ring_rstride;
         const int32_t* col = d.ring_col + (size_t)slot * d.ring_cstride;
         for (int e = rp[i]; e < rp[i + 1]; ++e) {
-          const int j = col[e];
+          const uint32_t j = (uint32_t)col[e] & COL_AGENT;
           atomicOr(&d.den_mask[j >> 5], 1u << (j & 31));
         }
       }
@@ -353,6 +353,7 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
   float* term = term_[grp];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // network factors, in registers
   if (LDSMASK)
     for (int q = threadIdx.x; q < d.nsc; q += TILE * G) scm[q] = d.scmask[q];
   for (int q = threadIdx.x; q < G * 2 * NW; q += TILE * G) (&nzb_[0][0][0])[q] = 0u;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
 #pragma unroll
           for (int l = 0; l < 4; ++l) {
             const int k = kb + (u * TILE + tid) * 4 + l;
-            const uint32_t x = (uint32_t)v[u][l];
+            const uint32_t x = (uint32_t)v[u][l] & COL_AGENT;
             src[4 * u + l] = x < (uint32_t)d.N ? x : 0u;
             hit[4 * u + l] = k < cn && c0 + k >= e0;
           }
@@ -428,8 +429,7 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           hit[q] = (cw[q] >> (src[q] & 31u)) & 1u;
-          const int k = kb + ((q >> 2) * TILE + tid) * 4 + (q & 3);
-          wv[q] = hit[q] ? __builtin_nontemporal_load(d.w + c0 + k) : 0.f;
+          wv[q] = col_weight((uint32_t)v[q >> 2][q & 3], wh, wo, wr);
           cd[q] = hit[q] ? (uint32_t)d.code[src[q]] : 0u;
         }
 #pragma unroll
@@ -487,6 +487,7 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
   uint32_t* nz = nzb_[wv];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
   if (*d.flags) return;
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // network factors, in registers
   // A wave's row bounds, row pointers and coefficient for the next workgroup iteration
   // (and the tile bounds for the one after) are loaded while the current one runs, and
   // are taken into registers before its stores: a load used only after a store waits
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
               const int k = (u * 64 + lane) * 4 + l;
-              const uint32_t x = (uint32_t)v[u][l];
+              const uint32_t x = (uint32_t)v[u][l] & COL_AGENT;
               src[4 * u + l] = x < (uint32_t)d.N ? x : 0u;
               hit[4 * u + l] = k < cn && c0 + k >= e0 &&
                                ((scm[src[4 * u + l] >> 14] >> ((src[4 * u + l] >> 8) & 63u)) & 1ull);
@@ -572,8 +573,7 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
 #pragma unroll
           for (int q = 0; q < NE; ++q) {
             hit[q] = (cw[q] >> (src[q] & 31u)) & 1u;
-            const int k = ((q >> 2) * 64 + lane) * 4 + (q & 3);
-            wvv[q] = hit[q] ? __builtin_nontemporal_load(d.w + c0 + k) : 0.f;
+            wvv[q] = col_weight((uint32_t)v[q >> 2][q & 3], wh, wo, wr);
             cd[q] = hit[q] ? (uint32_t)d.code[src[q]] : 0u;
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
