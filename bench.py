@@ -157,6 +157,20 @@ def time_days(sim, W: int, K: int):
     return counts, t1 - t0
 
 
+def streaming_run(p, pop, warmup: int, steps: int):
+    """The same days with every edge streamed through the force-of-infection kernel
+    every day (dense_message): the day time and that kernel's, for comparison with the
+    frontier path, which must give the same counts."""
+    from paper_2110_04421_amd.sim import Simulator
+    with Simulator(p, pop, autotune=True, dense_message=True) as sim:
+        counts, wall = time_days(sim, warmup, steps)
+    with Simulator(p, pop, profile=True, autotune=True, dense_message=True) as sim:
+        time_days(sim, warmup, steps)
+        prof = sim.profile()
+    ms, n = prof["message"]
+    return counts, wall, ms / max(n, 1)
+
+
 def sim_profiled(sim) -> bool:
     return bool(sim._p.flags & 1)
 
@@ -378,21 +392,28 @@ def main():
     Einf_mean = float(counts[:, :, 12].sum(axis=1).astype(np.float64).mean())
     C_mean = (E_mean - ehh) / 2.0
     vacc = p["vacc_rate"] > 0
+    # infectious agents a day (exposed or infectious, an upper bound of the agents whose
+    # code is nonzero): at most N/256 on a day, and its force of infection takes the
+    # frontier path, whose bytes depend on which rows hold infectious sources
+    n_inf_max = int((counts[:, :, 1] + counts[:, :, 2]).sum(axis=1).max())
+    frontier = n_inf_max * 256 <= N
     kernels = {}
     for name, (ms, n) in prof.items():
         if n == 0:
             continue
         avg = ms / n
-        b = kernel_bytes(name, N, E_mean, C_mean, vacc, Einf_mean)
+        b = None if (name == "message" and frontier) else kernel_bytes(name, N, E_mean, C_mean, vacc, Einf_mean)
         kernels[name] = {"ms_per_launch": avg, "launches": n,
-                         "algorithmic_GB": b / 1e9,
+                         "algorithmic_GB": None if b is None else b / 1e9,
                          "GB_per_s": (b / 1e9) / (avg / 1e3) if b and avg > 0 else None}
+    if frontier:
+        kernels["message"]["path"] = "frontier (rows holding an infectious source)"
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
     dk = kernels[dom]
     achieved = dk["GB_per_s"] or 0.0
     # (not in counter runs, where the 1 GiB --copy-probe copy must be the only large one)
     copy_gbs = None if args.copy_probe else copy_bandwidth()
-    step_bytes = sum(kernel_bytes(nm, N, E_mean, C_mean, vacc, Einf_mean) for nm in kernels)
+    step_bytes = sum((v["algorithmic_GB"] or 0.0) * 1e9 for v in kernels.values())
     step_ms = sum(v["ms_per_launch"] for v in kernels.values())
     line = {
         "metric": METRIC,
@@ -406,6 +427,8 @@ def main():
         "config": {"workload": args.workload, "agents": N, "days_timed": args.steps,
                    "edges_per_day": E_mean, "contacts_per_agent_day": E_mean / N,
                    "infectious_source_edges_per_day": Einf_mean, "autotuned_tiling": tuning,
+                   "exposed_or_infectious_max": n_inf_max,
+                   "force_of_infection": "frontier" if frontier else "streaming",
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -419,6 +442,14 @@ def main():
                      if copy_gbs else None},
         "kernels": kernels,
     }
+    if not args.no_extras:
+        log("the same days with every edge streamed through the force of infection")
+        counts_s, wall_s, msg_ms = streaming_run(p, pop, args.warmup, args.steps)
+        assert np.array_equal(counts, counts_s)
+        b = kernel_bytes("message", N, E_mean, C_mean, vacc, Einf_mean)
+        line["streaming_message"] = {"ms_per_step": wall_s / args.steps * 1e3, "message_ms": msg_ms,
+                                     "message_GB_per_s": b / 1e9 / (msg_ms / 1e3),
+                                     "message_algorithmic_GB": b / 1e9, "counts_equal": True}
     if args.copy_probe:
         copy_probe()
     if not args.no_extras:

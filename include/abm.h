@@ -102,6 +102,10 @@ enum {
 #define ABM_FLAG_AUTOTUNE 8 /* at create, time the force-of-infection kernel's tilings
                                (LDS chunk x grid x shape) on day 0's graph, keep the fastest;
                                results are bitwise the same for every tiling            */
+#define ABM_FLAG_DENSE_MESSAGE 32 /* stream every edge through the force-of-infection
+                                      kernel every day; without it, a day with at most
+                                      N/256 infectious agents sums only the rows that hold
+                                      an infectious source (bitwise the same result)     */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
                                     assembly their smallest LDS room, so that leaves are
                                     sorted in several groups and tiles are written

@@ -98,7 +98,7 @@ struct Layout {
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, dtab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
       cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
-      traj, day, flags, seeds, ring_rp, ring_col, den_mask;
+      traj, day, flags, seeds, ring_rp, ring_col, den_mask, rmask, ninf, work, nwork;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
       pb_b1w, pb_buf2, pb_rsrc, pb_rstart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
@@ -118,6 +118,8 @@ struct Sizes {
 // every slot starts on a 256-byte boundary (the message kernel reads 16-byte groups)
 int64_t ring_rstride(const Sizes& z) { return (z.N + 1 + 63) & ~(int64_t)63; }
 int64_t ring_cstride(const Sizes& z) { return (z.ecap + 63) & ~(int64_t)63; }
+// room of one list of flagged rows: the agents of the tiles t with t mod FRONT_NB fixed
+int64_t front_cap(const Sizes& z) { return (z.ntiles + FRONT_NB - 1) / FRONT_NB * TILE; }
 
 }  // namespace
 
@@ -399,6 +401,10 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
   o.day = L.take<int32_t>(1);
+  o.rmask = L.take<uint32_t>((z.N + 31) / 32 + 1);
+  o.ninf = L.take<int32_t>(1);
+  o.work = L.take<int32_t>((int64_t)FRONT_NB * front_cap(z));
+  o.nwork = L.take<int32_t>(FRONT_NB);
   if (p.app_adoption > 0.f) {
     // the day's graph lives in slot day % den_window; slots start on 256-byte bounds
     o.ring_rp = L.take<int32_t>((int64_t)p.den_window * ring_rstride(z));
@@ -529,6 +535,8 @@ int autotune(abm_sim* s) {
   HIPCHK(s, hipEventCreate(&e1));
   float best = 1e30f;
   int32_t best_chunk = d.msg_chunk, best_grid = d.msg_grid, best_shape = d.msg_shape;
+  const int32_t sparse_div = d.sparse_div;
+  d.sparse_div = 0;                                        // the streaming kernels run
   for (int v = 0; v < message_variants(); ++v) {
     message_variant(d, v, &d.msg_chunk, &d.msg_grid, &d.msg_shape);
     launch_message(d, st);                                 // warm-up
@@ -550,6 +558,7 @@ int autotune(abm_sim* s) {
   d.msg_chunk = best_chunk;
   d.msg_grid = best_grid;
   d.msg_shape = best_shape;
+  d.sparse_div = sparse_div;
   HIPCHK(s, hipGetLastError());
   return ABM_OK;
 }
@@ -675,6 +684,12 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.prev_counts = (long long*)(ws + o.prev_counts);
   d.traj = (long long*)(ws + o.traj);
   d.day = (int32_t*)(ws + o.day);
+  d.rmask = (uint32_t*)(ws + o.rmask);
+  d.ninf = (int32_t*)(ws + o.ninf);
+  d.work = (int32_t*)(ws + o.work);
+  d.nwork = (int32_t*)(ws + o.nwork);
+  d.work_cap = (int32_t)front_cap(z);
+  d.sparse_div = (p->flags & ABM_FLAG_DENSE_MESSAGE) ? 0 : SPARSE_DIV;
   d.test_dmin = p->test_delay;
   d.test_dmax = p->test_delay_max;
   d.den_on = p->app_adoption > 0.f ? 1 : 0;
@@ -835,6 +850,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     HIPCHK(s, hipMemcpyAsync(ws + o.seeds, pop->initial_infected, z.nseeds * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));
   HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 4, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.ninf, 0, 4, st));
   if (d.den_on) {                          // no graphs before day 0: empty rows
     HIPCHK(s, hipMemsetAsync(ws + o.ring_rp, 0, (size_t)p->den_window * d.ring_rstride * 4, st));
     HIPCHK(s, hipMemsetAsync(ws + o.den_mask, 0, ((N + 31) / 32 + 1) * 4, st));

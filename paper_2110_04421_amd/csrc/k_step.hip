@@ -146,6 +146,10 @@ __device__ __forceinline__ bool stage_i(int st) {
 __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   __shared__ int hist[NBUCKET + 1];
   if (threadIdx.x <= NBUCKET) hist[threadIdx.x] = 0;
+  if (blockIdx.x == 0) {                                 // counted afresh today
+    if (threadIdx.x == 0) *d.ninf = 0;
+    for (int q = threadIdx.x; q < FRONT_NB; q += TILE) d.nwork[q] = 0;
+  }
   __syncthreads();
   const int4 tl = d.tiles[blockIdx.x];
   const int i = tl.y + threadIdx.x;
@@ -216,6 +220,7 @@ __global__ __launch_bounds__(TILE) void k_mask(Dev d) {
   const int w = blockIdx.x * TILE + threadIdx.x;       // coarse word: agents [256w, 256w+256)
   const int ncw = (d.N + 255) >> 8;
   uint32_t coarse = 0;
+  int ninf = 0;
   if (w < ncw) {
     for (int f = 0; f < 8; ++f) {
       const int i0 = (w << 8) + (f << 5);
@@ -233,16 +238,35 @@ __global__ __launch_bounds__(TILE) void k_mask(Dev d) {
         for (int k = 0; i0 + k < d.N && k < 32; ++k)
           if (d.code[i0 + k]) m |= 1u << k;
       }
-      if (i0 < d.N) d.imask[i0 >> 5] = m;
+      if (i0 < d.N) {
+        d.imask[i0 >> 5] = m;
+        d.rmask[i0 >> 5] = 0u;
+      }
+      ninf += __builtin_popcount(m);
 #pragma unroll
       for (int g = 0; g < 4; ++g)
         if ((m >> (8 * g)) & 0xFFu) coarse |= 1u << (4 * f + g);
     }
     d.cmask[w] = coarse;
   }
+  // one atomic per workgroup (a single counter: the fewer the better)
+  __shared__ int wsum[TILE / 64];
+  for (int o = 32; o > 0; o >>= 1) ninf += __shfl_xor(ninf, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = ninf;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (t) atomicAdd(d.ninf, t);
+  }
   // super-coarse: bit w = some agent of [256w, 256w+256) infectious (one word per wave)
   const unsigned long long b = __ballot(coarse != 0u);
   if ((threadIdx.x & 63) == 0 && (w >> 6) < d.nsc) d.scmask[w >> 6] = b;
+}
+
+// A frontier day: few enough agents infectious (k_mask's count) that the force of
+// infection sums only the rows that hold an infectious source.
+__device__ __forceinline__ bool sparse_day(const Dev& d) {
+  return d.sparse_div > 0 && (int64_t)*d.ninf * d.sparse_div <= (int64_t)d.N;
 }
 
 // ---- vaccination plan: one workgroup per replicate ------------------------------------
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(TILE * G) void k_message(Dev d) {
   const int grp = threadIdx.x / TILE, tid = threadIdx.x % TILE;
   float* term = term_[grp];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
-  if (*d.flags) return;
+  if (*d.flags || sparse_day(d)) return;
   const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // network factors, in registers
   if (LDSMASK)
     for (int q = threadIdx.x; q < d.nsc; q += TILE * G) scm[q] = d.scmask[q];
@@ -486,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
   float* term = term_[wv];
   uint32_t* nz = nzb_[wv];
   if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
-  if (*d.flags) return;
+  if (*d.flags || sparse_day(d)) return;
   const float wh = d.w_h, wo = d.w_o, wr = d.w_r;   // network factors, in registers
   // A wave's row bounds, row pointers and coefficient for the next workgroup iteration
   // (and the tile bounds for the one after) are loaded while the current one runs, and
@@ -613,6 +637,106 @@ __global__ __launch_bounds__(1024) void k_message_w(Dev d) {
     __syncthreads();
     if (threadIdx.x < 4 && tb + (int)threadIdx.x < d.ntiles)
       d.tile_counts[(size_t)(tb + threadIdx.x) * TILE_NC + ABM_C_INF_EDGES] = ninf_[threadIdx.x];
+  }
+}
+
+// ---- frontier force of infection ------------------------------------------------------
+// With few infectious agents, most rows hold no infectious source and sum to +0.  The
+// graph is symmetric (a household pair or a drawn contact gives an edge in each
+// direction), so the rows that hold infectious agent j are exactly the agents listed in
+// row j: k_mark flags them from the infectious agents' own rows, k_front_list lists the
+// flagged rows, and k_message_front sums each, term by term in edge order as the
+// streaming kernels do, so lambda and the infectious-edge counts are bitwise the same.
+__global__ __launch_bounds__(TILE) void k_mark(Dev d) {
+  if (*d.flags || !sparse_day(d)) return;
+  const int w = blockIdx.x * TILE + threadIdx.x;
+  if (w >= (d.N + 31) >> 5) return;
+  uint32_t m = d.imask[w];
+  while (m) {
+    const int j = (w << 5) + __builtin_ctz(m);
+    m &= m - 1u;
+    const int e1 = d.row_ptr[j + 1];
+    for (int e = d.row_ptr[j]; e < e1; ++e) {
+      const uint32_t i = (uint32_t)d.col[e] & COL_AGENT;
+      if (i < (uint32_t)d.N) atomicOr(&d.rmask[i >> 5], 1u << (i & 31u));
+    }
+  }
+}
+
+// Per tile: rows not flagged get lambda = +0 (as the streaming sum of no terms gives),
+// the tile's infectious-edge count starts at 0, and the flagged rows join list
+// (tile mod FRONT_NB), one atomic per wave for the wave's slots: a single list would
+// put every wave's atomic on one address.
+__global__ __launch_bounds__(TILE) void k_front_list(Dev d) {
+  if (*d.flags || !sparse_day(d)) return;
+  const int4 tl = d.tiles[blockIdx.x];
+  const int i = tl.y + threadIdx.x;
+  const bool live = i < tl.z;
+  const bool flagged = live && ((d.rmask[i >> 5] >> (i & 31)) & 1u);
+  if (live && !flagged) d.lambda[i] = 0.f;
+  if (threadIdx.x == 0) d.tile_counts[(size_t)blockIdx.x * TILE_NC + ABM_C_INF_EDGES] = 0u;
+  const unsigned long long b = __ballot(flagged);
+  if (b == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int list = blockIdx.x & (FRONT_NB - 1);
+  int base = 0;
+  if (lane == 0) base = atomicAdd(&d.nwork[list], __popcll(b));
+  base = __shfl(base, 0);
+  if (flagged) d.work[(size_t)list * d.work_cap + base + __popcll(b & ((1ull << lane) - 1ull))] = i;
+}
+
+// A workgroup per list, one lane per flagged row: its edges four at a time (sources, then their mask words,
+// then the codes of the infectious ones), the terms added in edge order.
+__global__ __launch_bounds__(TILE) void k_message_front(Dev d) {
+  __shared__ float atab[ATAB];
+  if (threadIdx.x < ATAB) atab[threadIdx.x] = d.atab[threadIdx.x];
+  if (*d.flags || !sparse_day(d)) return;
+  __syncthreads();
+  const float wh = d.w_h, wo = d.w_o, wr = d.w_r;
+  const int n = d.nwork[blockIdx.x];               // workgroup b takes list b
+  const int32_t* list = d.work + (size_t)blockIdx.x * d.work_cap;
+  for (int q = threadIdx.x; q < n; q += TILE) {
+    const int i = list[q];
+    const int rs = d.row_ptr[i], re = d.row_ptr[i + 1];
+    float sum = 0.f;
+    uint32_t hits = 0;
+    for (int e = rs; e < re; e += 4) {
+      uint32_t x[4], s[4], m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = e + u < re ? (uint32_t)d.col[e + u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s[u] = (x[u] & COL_AGENT) < (uint32_t)d.N ? (x[u] & COL_AGENT) : 0u;
+        m[u] = e + u < re ? d.imask[s[u] >> 5] : 0u;
+      }
+      uint32_t cd[4];
+      bool hit[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        hit[u] = (m[u] >> (s[u] & 31u)) & 1u;
+        cd[u] = hit[u] ? (uint32_t)d.code[s[u]] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (hit[u]) {
+          // the streaming kernels round each term to FP32 before adding it: no fused
+          // multiply-add here either
+#pragma clang fp contract(off)
+          const float term = col_weight(x[u], wh, wo, wr) * atab[cd[u]];
+          sum += term;
+          ++hits;
+        }
+    }
+    // the row's replicate: the last one starting at or before i
+    int lo = 0, hi = d.R - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (d.rep[mid].start <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const RepInfo& ri = d.rep[lo];
+    d.lambda[i] = ri.coef[d.age[i]] * sum;
+    if (hits) atomicAdd(&d.tile_counts[(size_t)(ri.tile0 + (i - ri.start) / TILE) * TILE_NC + ABM_C_INF_EDGES], hits);
   }
 }
 
@@ -906,6 +1030,11 @@ static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
 }
 
 void launch_message(const Dev& d, hipStream_t s) {
+  if (d.sparse_div > 0) {            // both paths are launched; each runs only on its days
+    hipLaunchKernelGGL(k_mark, dim3(((d.N + 31) / 32 + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+    hipLaunchKernelGGL(k_front_list, dim3(d.ntiles), dim3(TILE), 0, s, d);
+    hipLaunchKernelGGL(k_message_front, dim3(FRONT_NB), dim3(TILE), 0, s, d);
+  }
   const dim3 g(d.msg_grid > 0 ? d.msg_grid : d.ntiles);
   if (d.msg_shape == 3) {
     if (d.msg_chunk == 256)
