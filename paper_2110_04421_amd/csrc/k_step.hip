@@ -146,10 +146,6 @@ __device__ __forceinline__ bool stage_i(int st) {
 __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   __shared__ int hist[NBUCKET + 1];
   if (threadIdx.x <= NBUCKET) hist[threadIdx.x] = 0;
-  if (blockIdx.x == 0) {                                 // counted afresh today
-    if (threadIdx.x == 0) *d.ninf = 0;
-    for (int q = threadIdx.x; q < FRONT_NB; q += TILE) d.nwork[q] = 0;
-  }
   __syncthreads();
   const int4 tl = d.tiles[blockIdx.x];
   const int i = tl.y + threadIdx.x;
@@ -208,6 +204,12 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
   if (d.vacc_on) {
     __syncthreads();
     if (threadIdx.x < NBUCKET) d.vhist[(size_t)blockIdx.x * NBUCKET + threadIdx.x] = hist[threadIdx.x];
+  }
+  // the frontier counters start afresh today (stored last: a store before the tile's
+  // loads would keep the compiler from loading the tile record through the scalar cache)
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *d.ninf = 0;
+    for (int q = threadIdx.x; q < FRONT_NB; q += TILE) d.nwork[q] = 0;
   }
 }
 
@@ -663,26 +665,41 @@ __global__ __launch_bounds__(TILE) void k_mark(Dev d) {
   }
 }
 
-// Per tile: rows not flagged get lambda = +0 (as the streaming sum of no terms gives),
-// the tile's infectious-edge count starts at 0, and the flagged rows join list
-// (tile mod FRONT_NB), one atomic per wave for the wave's slots: a single list would
+// Every lambda is set to +0 (as the streaming sum of no terms gives; the flagged rows
+// are overwritten next), every tile's infectious-edge count starts at 0, and the flagged
+// rows are listed.  A wave takes 256 agents, four a lane; its flagged rows join list
+// (group of 256 mod FRONT_NB) with one atomic for the wave's slots: a single list would
 // put every wave's atomic on one address.
 __global__ __launch_bounds__(TILE) void k_front_list(Dev d) {
   if (*d.flags || !sparse_day(d)) return;
-  const int4 tl = d.tiles[blockIdx.x];
-  const int i = tl.y + threadIdx.x;
-  const bool live = i < tl.z;
-  const bool flagged = live && ((d.rmask[i >> 5] >> (i & 31)) & 1u);
-  if (live && !flagged) d.lambda[i] = 0.f;
-  if (threadIdx.x == 0) d.tile_counts[(size_t)blockIdx.x * TILE_NC + ABM_C_INF_EDGES] = 0u;
-  const unsigned long long b = __ballot(flagged);
-  if (b == 0ull) return;
+  const int gid = blockIdx.x * TILE + threadIdx.x, nthr = gridDim.x * TILE;
+  for (int q = gid; q < d.ntiles; q += nthr) d.tile_counts[(size_t)q * TILE_NC + ABM_C_INF_EDGES] = 0u;
   const int lane = threadIdx.x & 63;
-  const int list = blockIdx.x & (FRONT_NB - 1);
-  int base = 0;
-  if (lane == 0) base = atomicAdd(&d.nwork[list], __popcll(b));
-  base = __shfl(base, 0);
-  if (flagged) d.work[(size_t)list * d.work_cap + base + __popcll(b & ((1ull << lane) - 1ull))] = i;
+  const int ngrp = (d.N + 255) >> 8;
+  for (int g = gid >> 6; g < ngrp; g += nthr >> 6) {         // uniform per wave
+    const int i0 = (g << 8) + 4 * lane;
+    if (i0 + 3 < d.N) {
+      *reinterpret_cast<float4*>(d.lambda + i0) = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      for (int k = i0; k < d.N; ++k) d.lambda[k] = 0.f;
+    }
+    const uint32_t f = i0 < d.N ? (d.rmask[i0 >> 5] >> (i0 & 31)) & 0xFu : 0u;
+    const int c = __builtin_popcount(f);
+    int inc = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    const int total = __shfl(inc, 63);
+    if (total == 0) continue;
+    const int list = g & (FRONT_NB - 1);
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&d.nwork[list], total);
+    base = __shfl(base, 0);
+    int32_t* out = d.work + (size_t)list * d.work_cap + base + inc - c;
+    for (int k = 0, m = 0; k < 4; ++k)
+      if ((f >> k) & 1u) out[m++] = i0 + k;
+  }
 }
 
 // A workgroup per list, one lane per flagged row: its edges four at a time (sources, then their mask words,
@@ -1032,7 +1049,7 @@ static void launch_msg(const Dev& d, const dim3& g, hipStream_t s) {
 void launch_message(const Dev& d, hipStream_t s) {
   if (d.sparse_div > 0) {            // both paths are launched; each runs only on its days
     hipLaunchKernelGGL(k_mark, dim3(((d.N + 31) / 32 + TILE - 1) / TILE), dim3(TILE), 0, s, d);
-    hipLaunchKernelGGL(k_front_list, dim3(d.ntiles), dim3(TILE), 0, s, d);
+    hipLaunchKernelGGL(k_front_list, dim3(2048), dim3(TILE), 0, s, d);
     hipLaunchKernelGGL(k_message_front, dim3(FRONT_NB), dim3(TILE), 0, s, d);
   }
   const dim3 g(d.msg_grid > 0 ? d.msg_grid : d.ntiles);
