@@ -103,9 +103,14 @@ enum {
                                (LDS chunk x grid x shape) on day 0's graph, keep the fastest;
                                results are bitwise the same for every tiling            */
 #define ABM_FLAG_DENSE_MESSAGE 32 /* stream every edge through the force-of-infection
-                                      kernel every day; without it, a day with at most
-                                      N/256 infectious agents sums only the rows that hold
-                                      an infectious source (bitwise the same result)     */
+                                      kernel every day; without it, with 2^20 agents or
+                                      more, a day with at most N/256 infectious agents
+                                      sums only the rows that hold an infectious source
+                                      (bitwise the same result)                          */
+#define ABM_FLAG_FRONTIER_ANY_SIZE 64 /* test aid: allow that frontier path below 2^20
+                                      agents too, where the day is bound by launches and
+                                      the path's three extra kernels cost more than they
+                                      save                                               */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
                                     assembly their smallest LDS room, so that leaves are
                                     sorted in several groups and tiles are written

@@ -689,7 +689,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.work = (int32_t*)(ws + o.work);
   d.nwork = (int32_t*)(ws + o.nwork);
   d.work_cap = (int32_t)front_cap(z);
-  d.sparse_div = (p->flags & ABM_FLAG_DENSE_MESSAGE) ? 0 : SPARSE_DIV;
+  d.sparse_div = (p->flags & ABM_FLAG_DENSE_MESSAGE) ? 0
+                 : (z.N >= FRONT_MIN_N || (p->flags & ABM_FLAG_FRONTIER_ANY_SIZE)) ? SPARSE_DIV : 0;
   d.test_dmin = p->test_delay;
   d.test_dmax = p->test_delay_max;
   d.den_on = p->app_adoption > 0.f ? 1 : 0;

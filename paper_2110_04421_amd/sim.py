@@ -30,20 +30,22 @@ class Simulator:
     ``min_lds_room`` (a test aid) gives the graph builder's leaf sort and row assembly
     their smallest LDS room, which exercises their multi-group and direct-write paths;
     ``dense_message`` streams every edge through the force-of-infection kernel every day
-    (by default a day with at most N/256 infectious agents sums only the rows that hold
-    an infectious source; the result is bitwise the same).
+    (by default, with 2^20 agents or more, a day with at most N/256 infectious agents sums
+    only the rows that hold an infectious source; the result is bitwise the same);
+    ``frontier_any_size`` (a test aid) allows that path at any population size.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
                  claim_builder: bool = False, autotune: bool = False, min_lds_room: bool = False,
-                 dense_message: bool = False, stream=None):
+                 dense_message: bool = False, frontier_any_size: bool = False, stream=None):
         torch = _torch()
         self._lib = L.lib()
         flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
                  | (L.FLAG_CLAIM_BUILDER if claim_builder else 0)
                  | (L.FLAG_AUTOTUNE if autotune else 0)
                  | (L.FLAG_MIN_LDS_ROOM if min_lds_room else 0)
-                 | (L.FLAG_DENSE_MESSAGE if dense_message else 0))
+                 | (L.FLAG_DENSE_MESSAGE if dense_message else 0)
+                 | (L.FLAG_FRONTIER_ANY_SIZE if frontier_any_size else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)

@@ -2,7 +2,8 @@
 
 On a day with at most N/256 infectious agents the library sums only the rows that hold
 an infectious source, found from the infectious agents' own rows (the daily graph is
-symmetric); otherwise, or with ``dense_message``, every edge is streamed.  An epidemic
+symmetric); otherwise, or with ``dense_message``, every edge is streamed.  Populations
+here are below 2^20 agents, so ``frontier_any_size`` turns the frontier path on.  An epidemic
 that starts from a few seeds and grows past N/256 infectious agents crosses from one
 form to the other; daily lambda, counts (infectious-edge counts included) and the final
 state must be identical to the streaming-only run."""
@@ -20,7 +21,7 @@ pytestmark = pytest.mark.gpu
 def _days(p, pop, days, dense):
     from paper_2110_04421_amd.sim import Simulator
     out = []
-    with Simulator(p, pop, dense_message=dense) as s:
+    with Simulator(p, pop, dense_message=dense, frontier_any_size=not dense) as s:
         for _ in range(days):
             c = s.run(1)
             out.append((c.copy(), s.lam().view(np.uint32).copy()))
