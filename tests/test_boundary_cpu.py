@@ -102,3 +102,22 @@ def test_relaxed_incidence_rejects_a_wrong_parameter_shape():
     p, pop = workload(4, n=1000, n_steps=5)
     with pytest.raises(ValueError):
         relaxed_incidence(torch.zeros(1, 9, dtype=torch.float64), p, pop, 5)
+
+
+def test_header_constants_match_the_binding(tmp_path):
+    """The flags, count slots, abm_get items and the ABI version the binding uses are
+    the header's."""
+    names = {"ABM_ABI_VERSION": L.ABI_VERSION, "ABM_NC": L.NC, "ABM_C_INF_EDGES": L.C_INF_EDGES,
+             "ABM_C_HOSP": L.C_HOSP, "ABM_C_ICU": L.C_ICU, "ABM_C_NOTIFIED": L.C_NOTIFIED,
+             "ABM_GET_COL": L.GET_COL, "ABM_GET_W": L.GET_W, "ABM_GET_DAY": L.GET_DAY,
+             "ABM_FLAG_PROFILE": L.FLAG_PROFILE, "ABM_FLAG_NO_GRAPH": L.FLAG_NO_GRAPH,
+             "ABM_FLAG_CLAIM_BUILDER": L.FLAG_CLAIM_BUILDER, "ABM_FLAG_AUTOTUNE": L.FLAG_AUTOTUNE,
+             "ABM_FLAG_MIN_LDS_ROOM": L.FLAG_MIN_LDS_ROOM, "ABM_FLAG_DENSE_MESSAGE": L.FLAG_DENSE_MESSAGE,
+             "ABM_FLAG_FRONTIER_ANY_SIZE": L.FLAG_FRONTIER_ANY_SIZE, "ABM_DISEASE_COURSE": L.COURSE}
+    src = tmp_path / "k.c"
+    body = "".join(f'printf("%ld\\n", (long)({n}));' for n in names)
+    src.write_text('#include "abm.h"\n#include <stdio.h>\nint main(void){' + body + 'return 0;}\n')
+    exe = tmp_path / "k"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert dict(zip(names, vals)) == names
