@@ -118,7 +118,9 @@ struct Sizes {
 // every slot starts on a 256-byte boundary (the message kernel reads 16-byte groups)
 int64_t ring_rstride(const Sizes& z) { return (z.N + 1 + 63) & ~(int64_t)63; }
 int64_t ring_cstride(const Sizes& z) { return (z.ecap + 63) & ~(int64_t)63; }
-// room of one list of flagged rows: the agents of the tiles t with t mod FRONT_NB fixed
+// room of one list of flagged rows.  List b takes the 256-agent groups g with
+// g mod FRONT_NB = b: at most ceil(ceil(N/256)/FRONT_NB) groups of 256, and there are
+// at least ceil(N/256) tiles, so this bound holds
 int64_t front_cap(const Sizes& z) { return (z.ntiles + FRONT_NB - 1) / FRONT_NB * TILE; }
 
 }  // namespace

@@ -23,7 +23,7 @@ constexpr int PB_S1_CAP = 12288;  // entries of a batch staged in LDS by the lev
 constexpr int PB_HS_MAX = 4608;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
 constexpr int SPARSE_DIV = 256;
 constexpr int64_t FRONT_MIN_N = 1 << 20;   // smallest population that takes the frontier path
-constexpr int FRONT_NB = 1024;     // lists of flagged rows (tile index mod FRONT_NB): spread counters    // frontier force of infection with <= N/256 infectious agents
+constexpr int FRONT_NB = 1024;     // lists of flagged rows (256-agent group mod FRONT_NB): spread counters    // frontier force of infection with <= N/256 infectious agents
 constexpr int WIN = 16;            // soft-mode exposure history ring (>= e_days + i_days + 1)
 
 enum Purpose : uint32_t { P_AGENT = 0, P_AGENT2 = 1, P_VACC = 2, P_OCC = 3, P_RAND = 4, P_COURSE = 5, P_APP = 6 };
@@ -129,7 +129,7 @@ struct Dev {
   // infectious agents, only rows with an infectious source are summed (0: never)
   uint32_t* rmask;              // bit i: row i holds an infectious source today
   int32_t* ninf;                // infectious agents today (counted by k_mask)
-  int32_t* work;                // [FRONT_NB][work_cap] the flagged rows, by tile mod FRONT_NB
+  int32_t* work;                // [FRONT_NB][work_cap] the flagged rows, by 256-agent group mod FRONT_NB
   int32_t* nwork;               // [FRONT_NB] their numbers
   int32_t work_cap;             // agents of a list's tiles at most
   int32_t sparse_div;
