@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the agent count (testing)")
     ap.add_argument("--no-extras", action="store_true", help="skip the 100k, batched and CPU legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-message", action="store_true",
+                    help="time the streaming force of infection every day (no frontier days)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (PMC counter scale)")
     args = ap.parse_args()
@@ -376,12 +378,13 @@ def main():
     # the throughput is timed on the production path (each day one HIP graph launch);
     # the same days are then run again with HIP events around every kernel for the
     # per-kernel durations (eager launches, so slightly slower as a whole)
-    with Simulator(p, pop, autotune=True) as sim:
+    dense = args.dense_message
+    with Simulator(p, pop, autotune=True, dense_message=dense) as sim:
         tuning = sim.tuning()
         log(f"warm-up {args.warmup} days, timing {args.steps} days (tiling {tuning})")
         counts, wall = time_days(sim, args.warmup, args.steps)
     log(f"timed {args.steps} days in {wall:.3f} s; again with per-kernel events")
-    with Simulator(p, pop, profile=True, autotune=True) as sim:
+    with Simulator(p, pop, profile=True, autotune=True, dense_message=dense) as sim:
         counts_p, wall_p = time_days(sim, args.warmup, args.steps)
         prof = sim.profile()
     assert np.array_equal(counts, counts_p)
@@ -396,7 +399,7 @@ def main():
     # code is nonzero): at most N/256 on a day, and its force of infection takes the
     # frontier path, whose bytes depend on which rows hold infectious sources
     n_inf_max = int((counts[:, :, 1] + counts[:, :, 2]).sum(axis=1).max())
-    frontier = n_inf_max * 256 <= N
+    frontier = n_inf_max * 256 <= N and N >= 1 << 20 and not dense
     kernels = {}
     for name, (ms, n) in prof.items():
         if n == 0:
@@ -442,7 +445,7 @@ def main():
                      if copy_gbs else None},
         "kernels": kernels,
     }
-    if not args.no_extras:
+    if not args.no_extras and not dense:
         log("the same days with every edge streamed through the force of infection")
         counts_s, wall_s, msg_ms = streaming_run(p, pop, args.warmup, args.steps)
         assert np.array_equal(counts, counts_s)
