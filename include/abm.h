@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ABM_ABI_VERSION 3
+#define ABM_ABI_VERSION 4
 
 enum {
   ABM_OK = 0,
@@ -67,6 +67,10 @@ enum { ABM_STAGE_S = 0, ABM_STAGE_E = 1, ABM_STAGE_I = 2, ABM_STAGE_R = 3, ABM_S
        ABM_STAGE_ASYM = 5, ABM_STAGE_PRE_MILD = 6, ABM_STAGE_PRE_SEVERE = 7, ABM_STAGE_MILD = 8,
        ABM_STAGE_SEVERE = 9, ABM_STAGE_HOSP = 10, ABM_STAGE_ICU = 11 };
 #define ABM_DISEASE_SEIRM 0   /* fixed E and I durations, death drawn at removal      */
+/* Vaccine immunity (section 5 considers both): a protected agent is not infected, or
+ * (course model only) is infected as anyone else is and takes the asymptomatic course */
+#define ABM_IMMUNITY_STERILISING 0
+#define ABM_IMMUNITY_ASYMPTOMATIC 1
 #define ABM_DISEASE_COURSE 1  /* eleven stages, age-dependent paths, random durations */
 /* stage durations of the course (shift + Poisson(extra) days), in this order */
 enum { ABM_DUR_PRE = 0, ABM_DUR_ASYM, ABM_DUR_MILD, ABM_DUR_SEV_HOSP, ABM_DUR_SEV_R,
@@ -167,6 +171,7 @@ typedef struct {
                                       > 0 keeps den_window days of graphs (hard mode only) */
   float den_compliance;            /* notified app users who test the next day             */
   int32_t den_window;              /* days of contacts a positive result notifies (1..30) */
+  int32_t vacc_immunity;           /* ABM_IMMUNITY_*                                      */
 } abm_params;
 
 /* Population, concatenated over replicates (host arrays, copied at create). */

@@ -116,6 +116,11 @@ class Model:
         self.dmax = int(p.get("test_delay_max", self.dmin))
         self.den = f32(p.get("app_adoption", 0.0)) > 0.0
         self.window = int(p.get("den_window", 7))
+        # section 5's second immunity: protected agents are infected at the usual rate and
+        # their infections are asymptomatic (course model only)
+        self.immune_asym = int(p.get("vacc_immunity", 0)) == 1
+        if self.immune_asym and not self.eleven:
+            raise ValueError("asymptomatic vaccine immunity needs the eleven-stage course")
         self.history = {}
         if self.den:
             w = philox.draw_words(int(p["seed"]), self.loc, 0, self.word, philox.PURPOSE_APP, 0)
@@ -190,11 +195,13 @@ class Model:
                 out[sel] = self.dshift[k] + poisson_count(w[0][sel], self.dthr[k])
         return out
 
-    def infect(self, st, ids, t):
+    def infect(self, st, ids, t, protected=None):
         """The course of agents infected on day t: asymptomatic with p_asym[a], else
         severe with p_severe[a] (mild otherwise); a severe course is hospitalised with
         p_hosp[a], and a hospitalised one reaches intensive care with p_icu[a].  Lanes
-        0..3 of the course's block 0 on day t; the first stage's duration from block 1."""
+        0..3 of the course's block 0 on day t; the first stage's duration from block 1.
+        ``protected`` (per id): vaccine-protected agents under asymptomatic immunity,
+        whose course is asymptomatic whatever the draw (section 5)."""
         if ids.size == 0:
             return
         a = self.age[ids]
@@ -202,6 +209,8 @@ class Model:
                               philox.PURPOSE_COURSE, 0)
         u = [philox.uniform(x) for x in w]
         asym = u[0] < self.ptab["p_asym"][a]
+        if protected is not None:
+            asym = asym | protected
         severe = ~asym & (u[1] < self.ptab["p_severe"][a])
         hosp = severe & (u[2] < self.ptab["p_hosp"][a])
         icu = hosp & (u[3] < self.ptab["p_icu"][a])
@@ -403,7 +412,7 @@ class Model:
         u0, u1, u2, u3 = self.uniforms(t, philox.PURPOSE_AGENT)
         prob = -np.expm1(-lam * f32(p["dt"]))
         stage, tau = st["stage"], t - st["t_exp"]
-        sus = (stage == STAGE_S) & ~immune
+        sus = (stage == STAGE_S) & (~immune | self.immune_asym)
         inf = sus & (u0 < prob)
         counts[:, C_NEAR] = np.bincount(self.rep[sus & (np.abs(u0 - prob) <= NEAR_EPS)],
                                         minlength=self.nrep)
@@ -411,7 +420,8 @@ class Model:
         counts[:, C_NEW] = np.bincount(self.rep[inf], minlength=self.nrep)
         if self.eleven:
             self.progress(st, new, t)
-            self.infect(new, np.flatnonzero(inf), t)
+            ids = np.flatnonzero(inf)
+            self.infect(new, ids, t, immune[ids] & self.immune_asym)
         else:
             new["stage"][inf] = STAGE_E
             ed, idays = int(p["e_days"]), int(p["i_days"])

@@ -9,7 +9,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabm.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 HARD, SOFT = 0, 1
 SEIRM, COURSE = 0, 1
 NC = 16
@@ -58,6 +58,7 @@ class AbmParams(C.Structure):
         ("dur_extra", C.c_double * N_DUR),
         ("test_delay_max", C.c_int32), ("app_adoption", C.c_float), ("den_compliance", C.c_float),
         ("den_window", C.c_int32),
+        ("vacc_immunity", C.c_int32),
     ]
 
 
@@ -182,6 +183,7 @@ def make_params(cfg: dict, flags: int = 0) -> AbmParams:
     p.app_adoption = float(cfg.get("app_adoption", 0.0))
     p.den_compliance = float(cfg.get("den_compliance", 0.0))
     p.den_window = int(cfg.get("den_window", 7))
+    p.vacc_immunity = int(cfg.get("vacc_immunity", 0))
     return p
 
 

@@ -218,6 +218,10 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   }
   if (p->disease_model != ABM_DISEASE_SEIRM && p->disease_model != ABM_DISEASE_COURSE)
     return bad("disease_model");
+  if (p->vacc_immunity != ABM_IMMUNITY_STERILISING && p->vacc_immunity != ABM_IMMUNITY_ASYMPTOMATIC)
+    return bad("vacc_immunity");
+  if (p->vacc_immunity == ABM_IMMUNITY_ASYMPTOMATIC && p->disease_model != ABM_DISEASE_COURSE)
+    return bad("asymptomatic vaccine immunity needs the eleven-stage course");
   if (p->disease_model == ABM_DISEASE_COURSE) {
     if (p->mode != ABM_HARD) return bad("the eleven-stage course runs in hard mode only");
     const float* tabs[5] = {p->p_asym, p->p_severe, p->p_hosp, p->p_icu, p->p_die};
@@ -695,6 +699,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
                  : (z.N >= FRONT_MIN_N || (p->flags & ABM_FLAG_FRONTIER_ANY_SIZE)) ? SPARSE_DIV : 0;
   d.test_dmin = p->test_delay;
   d.test_dmax = p->test_delay_max;
+  d.immune_asym = p->vacc_immunity == ABM_IMMUNITY_ASYMPTOMATIC ? 1 : 0;
   d.den_on = p->app_adoption > 0.f ? 1 : 0;
   d.den_window = p->den_window;
   d.den_adoption = p->app_adoption;

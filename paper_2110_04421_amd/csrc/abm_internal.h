@@ -74,6 +74,7 @@ struct Dev {
   float p_death[ABM_N_AGE];
   int8_t vrank[2][ABM_N_AGE];   // priority class of (dose 1|2, age group)
   int32_t course_on;            // eleven-stage course instead of SEIRM
+  int32_t immune_asym;          // vaccine protection: asymptomatic infection, not none
   float cprob[5][ABM_N_AGE];    // course: p_asym, p_severe, p_hosp, p_icu, p_die
   int32_t dur_shift[ABM_N_DUR];
   const uint32_t* dtab;         // [ABM_N_DUR][64] Poisson thresholds of the durations' extra days

@@ -84,11 +84,13 @@ __device__ __forceinline__ int course_days(const Dev& d, int k, uint32_t x) {
   return d.dur_shift[k] + poisson_k(d.dtab + k * 64, x);
 }
 
+// (`protected_`: a vaccine-protected agent under asymptomatic immunity takes the
+// asymptomatic course whatever its draw)
 __device__ __forceinline__ void course_infect(const Dev& d, AgentState& a, uint32_t loc, int t,
-                                              uint32_t stream, int age) {
+                                              uint32_t stream, int age, bool protected_ = false) {
   const uint4 b0 = philox(loc, (uint32_t)t, stream, P_COURSE << 24, d.key0, d.key1);
   const uint4 b1 = philox(loc, (uint32_t)t, stream, (P_COURSE << 24) | 1u, d.key0, d.key1);
-  const bool asym = u01(b0.x) < d.cprob[0][age];
+  const bool asym = protected_ || u01(b0.x) < d.cprob[0][age];
   const bool severe = !asym && u01(b0.y) < d.cprob[1][age];
   const bool hosp = severe && u01(b0.z) < d.cprob[2][age];
   const bool icu = hosp && u01(b0.w) < d.cprob[3][age];
@@ -818,14 +820,14 @@ __global__ __launch_bounds__(TILE) void k_fused(Dev d) {
     const int st0 = a.stage;
     const int tau = t - (int)a.t_exp;
     if (st0 == ABM_STAGE_S) {
-      if (!immune) {
+      if (!immune || d.immune_asym) {
         const double p = -expm1(-(double)d.lambda[i] * (double)d.dt);
         const double u = (double)u01(b.x);
         if (u < p) {
           a.t_exp = (int16_t)t;
           is_new = true;
           if (d.course_on)
-            course_infect(d, a, loc, t, ri.stream, age);
+            course_infect(d, a, loc, t, ri.stream, age, immune);
           else
             a.stage = ABM_STAGE_E;
         }

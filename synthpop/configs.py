@@ -33,6 +33,7 @@ BASE = dict(
     app_adoption=0.0,                    # digital exposure notification: app users' share (0 = off)
     den_compliance=0.8,                  # notified app users who test the next day
     den_window=7,                        # days of contacts a positive result notifies
+    vacc_immunity=0,                     # 0 sterilising, 1 asymptomatic infections (course)
     vacc_rate=0.0, vacc_trigger=0.01, eff1=0.52, eff2=0.95, dose_lag=12,
     strategy=STRAT_STANDARD,
     mode=MODE_HARD, gumbel_tau=0.5, checkpoint_every=10,

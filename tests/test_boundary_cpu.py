@@ -69,6 +69,12 @@ def test_workspace_size_and_errors():
     assert rc == -1
     rc, *_ = _ws(dict(p, edge_capacity=2**31), pop)
     assert rc == -4
+    rc, *_ = _ws(dict(p, vacc_immunity=1), pop)                     # needs the course model
+    assert rc == -1
+    rc, *_ = _ws(dict(p, vacc_immunity=1, disease_model=1), pop)
+    assert rc == 0
+    rc, *_ = _ws(dict(p, vacc_immunity=2, disease_model=1), pop)
+    assert rc == -1
 
 
 def test_abi_mismatch_and_small_workspace_fail_before_device_work():
@@ -113,7 +119,8 @@ def test_header_constants_match_the_binding(tmp_path):
              "ABM_FLAG_PROFILE": L.FLAG_PROFILE, "ABM_FLAG_NO_GRAPH": L.FLAG_NO_GRAPH,
              "ABM_FLAG_CLAIM_BUILDER": L.FLAG_CLAIM_BUILDER, "ABM_FLAG_AUTOTUNE": L.FLAG_AUTOTUNE,
              "ABM_FLAG_MIN_LDS_ROOM": L.FLAG_MIN_LDS_ROOM, "ABM_FLAG_DENSE_MESSAGE": L.FLAG_DENSE_MESSAGE,
-             "ABM_FLAG_FRONTIER_ANY_SIZE": L.FLAG_FRONTIER_ANY_SIZE, "ABM_DISEASE_COURSE": L.COURSE}
+             "ABM_FLAG_FRONTIER_ANY_SIZE": L.FLAG_FRONTIER_ANY_SIZE, "ABM_DISEASE_COURSE": L.COURSE,
+             "ABM_IMMUNITY_ASYMPTOMATIC": 1}
     src = tmp_path / "k.c"
     body = "".join(f'printf("%ld\\n", (long)({n}));' for n in names)
     src.write_text('#include "abm.h"\n#include <stdio.h>\nint main(void){' + body + 'return 0;}\n')

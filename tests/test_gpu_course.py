@@ -22,6 +22,15 @@ def test_course_lockstep_with_interventions():
     assert worst < 1e-5
 
 
+def test_asymptomatic_vaccine_immunity_lockstep():
+    """Protected agents infected at the usual rate, on the asymptomatic course."""
+    require_gpu()
+    p, pop = workload(1, n=20000, n_steps=60, vacc_trigger=0.002, vacc_rate=0.03, eff1=0.9,
+                      vacc_immunity=1, **SEVERE)
+    near, worst = _lockstep(p, pop, 60)
+    assert worst < 1e-5
+
+
 def test_course_batched_replicates_lockstep():
     require_gpu()
     p, pop = workload(3, n=30000, n_rep=5, n_steps=30, vacc_trigger=0.002, **SEVERE)

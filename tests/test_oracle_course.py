@@ -79,3 +79,27 @@ def test_course_run_conserves_agents_and_deaths_come_from_intensive_care():
     assert np.all(st["course"][dead] & 28 == 28)      # hospitalised, ICU, dies
     S = np.concatenate([[N - 10], c[:, ostep.C_S]])
     assert np.array_equal(-np.diff(S), c[:, ostep.C_NEW])
+
+
+def test_asymptomatic_vaccine_immunity():
+    """Section 5's second immunity: a protected agent is infected at the usual rate and
+    its course is asymptomatic.  With no asymptomatic share in the tables and certain
+    protection from dose_lag days after the first dose, an infection is asymptomatic
+    exactly when it falls on a protected day; under sterilising immunity no infection
+    falls on such a day."""
+    base = dict(n=8000, n_steps=70, vacc_trigger=0.002, vacc_rate=0.03, eff1=1.0, eff2=1.0, dose_lag=3,
+                disease_model=1, p_asym=[0.0] * 9)
+    out = {}
+    for imm in (0, 1):
+        p, pop = workload(1, vacc_immunity=imm, **base)
+        out[imm] = ostep.run(pop, p)
+    for imm, (traj, st, _) in out.items():
+        inf = st["t_exp"] >= 0
+        prot = inf & (st["d1"] != ostep.NEVER) & (st["t_exp"] >= st["d1"].astype(np.int64) + 3)
+        asym = inf & ((st["course"] & 3) == ostep.K_ASYM)
+        if imm == 0:
+            assert not prot.any() and not asym.any()
+        else:
+            assert prot.sum() > 5
+            assert np.array_equal(asym, prot)
+    assert out[1][0][:, :, ostep.C_NEW].sum() > out[0][0][:, :, ostep.C_NEW].sum()
