@@ -115,6 +115,9 @@ enum {
                                       agents too, where the day is bound by launches and
                                       the path's three extra kernels cost more than they
                                       save                                               */
+#define ABM_FLAG_STRAIGHT_THROUGH 128 /* relaxed mode: the forward pass takes the hard
+                                      infection draw (the relaxed sample's sign) and the
+                                      adjoint the relaxed sample's derivative            */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
                                     assembly their smallest LDS room, so that leaves are
                                     sorted in several groups and tiles are written

@@ -18,6 +18,10 @@ Interventions are off in this mode.
 
 Tangents are propagated alongside every quantity (dual numbers with 10 components,
 one per parameter of the agent's own replicate).
+
+Straight-through variant (``straight_through``): the forward pass takes the hard
+sample [u < p] (the relaxed sample's sign, z > 0), so the state follows the hard step,
+and the tangent of the sample is still the relaxed one's, y(1 - y)/tau_g dz.
 """
 from __future__ import annotations
 
@@ -37,8 +41,9 @@ def sigmoid(z):
 
 
 class SoftModel:
-    def __init__(self, pop, params, R=None, S=None):
+    def __init__(self, pop, params, R=None, S=None, straight_through=False):
         self.pop = pop
+        self.st = bool(straight_through)
         self.p = dict(params)
         self.maps = static_maps(pop)
         self.N = int(pop.agent_offset[-1])
@@ -107,7 +112,11 @@ class SoftModel:
             ell = np.log(np.expm1(x[pos]))
             lu = self.logit_u(t)
             y[pos] = sigmoid((ell - lu[pos]) / self.tau)
-            e = s * y
+            yf = y                             # the sample the state takes
+            if self.st:
+                yf = np.zeros(N)
+                yf[pos] = (ell - lu[pos] > 0).astype(np.float64)
+            e = s * yf
             if tangents:
                 sigma_d = A @ inf_d
                 lam_d = coef_d * sigma[:, None] + coef[:, None] * sigma_d
@@ -115,7 +124,7 @@ class SoftModel:
                 p = -np.expm1(-x[pos])
                 dy[pos] = y[pos] * (1 - y[pos]) / self.tau / p * self.dt
                 y_d = dy[:, None] * lam_d
-                e_d = s_d * y[:, None] + s[:, None] * y_d
+                e_d = s_d * yf[:, None] + s[:, None] * y_d
             else:
                 e_d = np.zeros((N, NTHETA))
             if record:

@@ -212,6 +212,8 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   if (p->dose_lag < 0 || p->dose_lag > 10000) return bad("dose_lag");
   if (p->strategy < 0 || p->strategy > 2) return bad("strategy");
   if (!(p->vacc_rate >= 0 && p->vacc_rate <= 1)) return bad("vacc_rate");
+  if ((p->flags & ABM_FLAG_STRAIGHT_THROUGH) && p->mode != ABM_SOFT)
+    return bad("the straight-through estimator is a relaxed-mode option");
   if (p->mode == ABM_SOFT) {
     if (!(p->gumbel_tau > 0.f)) return bad("gumbel_tau <= 0");
     if (p->checkpoint_every < 1) return bad("checkpoint_every < 1");
@@ -700,6 +702,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.test_dmin = p->test_delay;
   d.test_dmax = p->test_delay_max;
   d.immune_asym = p->vacc_immunity == ABM_IMMUNITY_ASYMPTOMATIC ? 1 : 0;
+  d.straight = (p->flags & ABM_FLAG_STRAIGHT_THROUGH) ? 1 : 0;
   d.den_on = p->app_adoption > 0.f ? 1 : 0;
   d.den_window = p->den_window;
   d.den_adoption = p->app_adoption;

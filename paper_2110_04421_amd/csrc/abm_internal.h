@@ -75,6 +75,7 @@ struct Dev {
   int8_t vrank[2][ABM_N_AGE];   // priority class of (dose 1|2, age group)
   int32_t course_on;            // eleven-stage course instead of SEIRM
   int32_t immune_asym;          // vaccine protection: asymptomatic infection, not none
+  int32_t straight;             // relaxed mode: hard sample forward, relaxed derivative back
   float cprob[5][ABM_N_AGE];    // course: p_asym, p_severe, p_hosp, p_icu, p_die
   int32_t dur_shift[ABM_N_DUR];
   const uint32_t* dtab;         // [ABM_N_DUR][64] Poisson thresholds of the durations' extra days

@@ -115,8 +115,8 @@ __global__ __launch_bounds__(TILE) void k_soft_update(Dev d, int32_t seg_slot) {
     const float x = lam * d.dt;
     float y = 0.f;
     if (x > 0.f) {
-      const float ell = logf(expm1f(x));
-      y = sigmoidf((ell - logit_u(d, ri, i, t)) / d.gtau);
+      const float z = (logf(expm1f(x)) - logit_u(d, ri, i, t)) / d.gtau;
+      y = d.straight ? (z > 0.f ? 1.f : 0.f) : sigmoidf(z);   // the sample the state takes
     }
     const float s = d.s[i];
     e = s * y;
@@ -191,7 +191,10 @@ __global__ __launch_bounds__(TILE) void k_adj_day(Dev d, int32_t t, int32_t seg_
     float lbar = 0.f;
     if (x > 0.f) {
       const float p = -expm1f(-x);
-      lbar = ybar * y * (1.f - y) / d.gtau * d.dt / p;
+      // straight-through: the saved sample is the hard one; the derivative is the
+      // relaxed sample's, recomputed from the same uniform
+      const float ys = d.straight ? sigmoidf((logf(expm1f(x)) - logit_u(d, ri, i, t)) / d.gtau) : y;
+      lbar = ybar * ys * (1.f - ys) / d.gtau * d.dt / p;
     }
     d.vtmp[i] = ri.coef[a] * lbar;
     gR = lbar * (d.kappa * ri.S[a]) * sigma;

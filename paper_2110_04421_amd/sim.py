@@ -32,12 +32,15 @@ class Simulator:
     ``dense_message`` streams every edge through the force-of-infection kernel every day
     (by default, with 2^20 agents or more, a day with at most N/256 infectious agents sums
     only the rows that hold an infectious source; the result is bitwise the same);
-    ``frontier_any_size`` (a test aid) allows that path at any population size.
+    ``frontier_any_size`` (a test aid) allows that path at any population size;
+    ``straight_through`` (relaxed mode) takes the hard infection draw forward and the
+    relaxed sample's derivative in the adjoint.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
                  claim_builder: bool = False, autotune: bool = False, min_lds_room: bool = False,
-                 dense_message: bool = False, frontier_any_size: bool = False, stream=None):
+                 dense_message: bool = False, frontier_any_size: bool = False,
+                 straight_through: bool = False, stream=None):
         torch = _torch()
         self._lib = L.lib()
         flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
@@ -45,7 +48,8 @@ class Simulator:
                  | (L.FLAG_AUTOTUNE if autotune else 0)
                  | (L.FLAG_MIN_LDS_ROOM if min_lds_room else 0)
                  | (L.FLAG_DENSE_MESSAGE if dense_message else 0)
-                 | (L.FLAG_FRONTIER_ANY_SIZE if frontier_any_size else 0))
+                 | (L.FLAG_FRONTIER_ANY_SIZE if frontier_any_size else 0)
+                 | (L.FLAG_STRAIGHT_THROUGH if straight_through else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)

@@ -183,3 +183,29 @@ def test_gradient_descent_fit_moves_toward_the_true_parameters():
     assert best < 0.3 * hist[0] and hist[-1] < 0.5 * hist[0]
     assert np.all(np.abs(eff(th) - eff(th_true)) < 0.5 * np.abs(eff(th0) - eff(th_true)))
     assert np.all(hard(th) < 0.2 * hard(th0))
+
+
+def test_straight_through_forward_and_adjoint_match_oracle():
+    """Hard draws forward, the relaxed sample's derivative in the adjoint."""
+    T = 40
+    p, pop = workload(4, n=20000, n_steps=T)
+    c_o, cd_o, _ = SoftModel(pop, p, straight_through=True).run(T)
+    dL = np.random.default_rng(11).normal(size=(1, T))
+    g_o = gradient(cd_o, dL)
+    with _sim(p, pop, straight_through=True) as s:
+        c_g = s.run(T)
+        g_g = s.grad(dL.astype(np.float32))
+    # each hard draw is a comparison the GPU makes in FP32 and the oracle in FP64: a
+    # draw within rounding of its threshold may fall the other way (rare at this size)
+    flips = float(np.abs(c_g.astype(np.float64) - c_o).sum())
+    assert flips <= 2, f"straight-through incidence differs by {flips}"
+    ok, err = _close(g_g.astype(np.float64), g_o, 1e-3 if flips == 0 else 5e-2)
+    assert ok, f"adjoint rel err {err}: {g_g} vs {g_o}"
+
+
+def test_straight_through_is_a_relaxed_mode_option():
+    require_gpu()
+    from paper_2110_04421_amd.sim import Simulator
+    p, pop = workload(1, n=2000, n_steps=5)
+    with pytest.raises(Exception):
+        Simulator(p, pop, straight_through=True)

@@ -43,3 +43,19 @@ def test_sigmoid_is_the_logistic_function():
     ref = np.array([0.0, 9.357622968840175e-14, 0.2689414213699951, 0.5, 0.8807970779778823,
                     1.0, 1.0])
     assert np.allclose(sigmoid(z), ref, rtol=1e-12, atol=1e-300)
+
+
+def test_straight_through_forward_is_the_hard_step_at_any_temperature():
+    """The straight-through forward pass takes the relaxed sample's sign, which is the
+    hard draw u < p, so its incidence is the hard oracle's at a finite temperature; its
+    tangents are the relaxed sample's, so they differ from the relaxed run's only
+    through the different trajectory (equal on day 0, where the state is the same)."""
+    p, pop = workload(4, n=4000, gumbel_tau=0.5)
+    T = 35
+    c, cd, _ = SoftModel(pop, p, straight_through=True).run(T)
+    traj, _, _ = ostep.run(pop, dict(p, mode=0), n_steps=T)
+    assert np.array_equal(c[0], traj[:, 0, ostep.C_NEW].astype(np.float64))
+    assert c[0].sum() > 50
+    _, cd_soft, _ = SoftModel(pop, p).run(1)
+    assert np.allclose(cd[:, 0], cd_soft[:, 0], rtol=1e-12, atol=0)
+    assert np.abs(cd[:, 1:]).max() > 0
