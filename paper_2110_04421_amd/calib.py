@@ -181,9 +181,10 @@ def curve_loss(c, target):
 
 
 def gd_fit(params, base_pop, targets, theta0, seed, stream0=0, iters=30, lr=0.05, days=180,
-           batch=256, tau=0.1, log=None):
+           batch=256, tau=0.1, log=None, straight_through=False):
     """Fit (R, S_0..S_8) to each hard incidence curve by gradient descent through the
-    relaxed simulator's adjoint (abm_grad).
+    relaxed simulator's adjoint (abm_grad); with ``straight_through`` the forward runs
+    are hard and the adjoint uses the relaxed sample's derivative.
 
     Target r is fitted on its own Philox stream (seed, stream0 + r), so the relaxed run
     shares the noise of the run that made the curve.  Adam on the unit scale, projected
@@ -216,7 +217,7 @@ def gd_fit(params, base_pop, targets, theta0, seed, stream0=0, iters=30, lr=0.05
         m = np.zeros_like(u)
         v = np.zeros_like(u)
         best = np.full(b1 - b0, np.inf)
-        with Simulator(p, pop) as sim:
+        with Simulator(p, pop, straight_through=straight_through) as sim:
             for it in range(iters):
                 th = from_unit(u)
                 sim.set_theta(th)
