@@ -209,6 +209,9 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
     if (p->test_delay < 1) return bad("test_delay must be >= 1");
   }
   if (p->quarantine_days < 0 || p->quarantine_days > 10000) return bad("quarantine_days");
+  // day fields of the agent record are int16: the last quarantine must end in range
+  // (stage ends of the course come at most 60 + 63 days after their start)
+  if (p->n_steps + p->quarantine_days > 32767) return bad("n_steps + quarantine_days > 32767");
   if (p->dose_lag < 0 || p->dose_lag > 10000) return bad("dose_lag");
   if (p->strategy < 0 || p->strategy > 2) return bad("strategy");
   if (!(p->vacc_rate >= 0 && p->vacc_rate <= 1)) return bad("vacc_rate");
@@ -344,6 +347,13 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   // occupancy, not correctness.
   const double leaf_mean = rbar * (double)((int64_t)1 << lb);
   z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
+  // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048);
+  // the generation pass stages a batch in LDS, so more than 24576 draws (high contact
+  // means) take the claim builder
+  double mo = 0, mr = 0;
+  for (int k = 0; k < ABM_N_OCC; ++k) mo = std::max(mo, p->mu_occupation[k] / 2.0);
+  for (int k = 0; k < ABM_N_AGE; ++k) mr = std::max(mr, p->mu_random[k] / 2.0);
+  z.bcap = ((int64_t)(1.3 * 1024.0 * (mo + mr)) + 2048 + 255) / 256 * 256;
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
             leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
             N < ((int64_t)1 << 27);   // initiators fit the 27 low bits of a partition word
@@ -361,11 +371,6 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   // a level-1 workgroup keeps its batches' run offsets in LDS
   z.bpw = std::max<int64_t>(1, std::min<int64_t>(z.bpw, PB_HS_MAX / std::max<int64_t>(z.nb1, 1) - 1));
   z.ngrid = (z.nbatch + z.bpw - 1) / z.bpw;
-  // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048)
-  double mo = 0, mr = 0;
-  for (int k = 0; k < ABM_N_OCC; ++k) mo = std::max(mo, p->mu_occupation[k] / 2.0);
-  for (int k = 0; k < ABM_N_AGE; ++k) mr = std::max(mr, p->mu_random[k] / 2.0);
-  z.bcap = ((int64_t)(1.3 * 1024.0 * (mo + mr)) + 2048 + 255) / 256 * 256;
   z.s1_nparts = (z.nb1 * z.nbatch + SCAN_BLOCK - 1) / SCAN_BLOCK;
   z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
   z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;

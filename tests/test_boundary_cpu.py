@@ -43,9 +43,9 @@ def test_struct_layout_matches_c(tmp_path):
                     L.AbmParams.edge_capacity.offset, C.sizeof(L.AbmPopulation)]
 
 
-def _ws(p, pop):
+def _ws(p, pop, flags=0):
     lib = L.lib()
-    P = L.make_params(p)
+    P = L.make_params(p, flags)
     Q, keep = L.make_population(pop)
     n = C.c_size_t(0)
     rc = lib.abm_workspace_size(C.byref(P), C.byref(Q), C.byref(n))
@@ -75,6 +75,25 @@ def test_workspace_size_and_errors():
     assert rc == 0
     rc, *_ = _ws(dict(p, vacc_immunity=2, disease_model=1), pop)
     assert rc == -1
+
+
+def test_high_contact_means_take_the_claim_builder():
+    """At the validator's largest contact means a batch's draws exceed the generation
+    pass's LDS room, so the layout is the claim builder's (no partition buffers)."""
+    p, pop = workload(1, n=5000)
+    hi = dict(p, mu_random=[40.0] * 9, mu_occupation=[40.0] * 23)
+    rc, n_hi, *_ = _ws(hi, pop)
+    rc2, n_claim, *_ = _ws(hi, pop, L.FLAG_CLAIM_BUILDER)
+    assert rc == 0 and rc2 == 0 and n_hi == n_claim
+    rc, n_lo, *_ = _ws(p, pop)
+    rc2, n_lo_claim, *_ = _ws(p, pop, L.FLAG_CLAIM_BUILDER)
+    assert n_lo > n_lo_claim                  # the default means partition
+
+
+def test_int16_day_fields_stay_in_range():
+    p, pop = workload(0)
+    assert _ws(dict(p, n_steps=30000, quarantine_days=2767), pop)[0] == 0
+    assert _ws(dict(p, n_steps=30000, quarantine_days=2768), pop)[0] == -1
 
 
 def test_abi_mismatch_and_small_workspace_fail_before_device_work():

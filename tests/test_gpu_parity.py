@@ -66,6 +66,22 @@ def test_csr_bit_exact(k, n, nrep):
             assert np.array_equal(w, w_o.astype(np.float32))
 
 
+@pytest.mark.parametrize("mu", [15.0, 40.0])
+def test_csr_bit_exact_at_high_contact_means(mu):
+    """At mean 15 a batch's draws pass the level-1 scatter's and the assembly's LDS
+    room (their direct paths run); at the validator's largest mean, 40 per network, the
+    claim builder takes over.  Either way the graph is the oracle's."""
+    p, pop = workload(1, n=3000, n_steps=4, mu_random=[mu] * 9, mu_occupation=[mu] * 23)
+    with _sim(p, pop) as s:
+        for t in range(2):
+            s.run(1)
+            rp, col, w = s.csr()
+            rp_o, col_o, w_o, _ = og.build_graph(pop, p, t)
+            assert np.array_equal(rp.astype(np.int64), rp_o)
+            assert np.array_equal(col.astype(np.int64), col_o)
+            assert np.array_equal(w, w_o.astype(np.float32))
+
+
 def _lockstep(p, pop, T, graph=True, allow_near=True, check_csr_every=0):
     """Step GPU and oracle together; resync the GPU from the oracle after a counted
     near-threshold disagreement.  Returns (near draws seen, worst lambda rel err)."""
