@@ -113,10 +113,16 @@ __global__ __launch_bounds__(TILE) void k_soft_update(Dev d, int32_t seg_slot) {
     const float sigma = d.sigma[i];
     const float lam = ri.coef[d.age[i]] * sigma;
     const float x = lam * d.dt;
-    float y = 0.f;
+    float y = 0.f;                       // the sample the state takes
     if (x > 0.f) {
-      const float z = (logf(expm1f(x)) - logit_u(d, ri, i, t)) / d.gtau;
-      y = d.straight ? (z > 0.f ? 1.f : 0.f) : sigmoidf(z);   // the sample the state takes
+      if (d.straight) {
+        // the hard step's draw: u < 1 - exp(-lambda dt) in FP64 on the same uniform
+        const uint4 b = philox((uint32_t)(i - ri.start), (uint32_t)t, ri.stream, P_AGENT << 24, d.key0, d.key1);
+        const double p = -expm1(-(double)lam * (double)d.dt);
+        y = (double)u01(b.x) < p ? 1.f : 0.f;
+      } else {
+        y = sigmoidf((logf(expm1f(x)) - logit_u(d, ri, i, t)) / d.gtau);
+      }
     }
     const float s = d.s[i];
     e = s * y;
