@@ -215,26 +215,52 @@ typedef struct {
   int16_t t_next;     /* day the current stage of the course ends (ABM_NEVER if none) */
 } abm_agent_state;
 
-/* Bytes of device workspace the simulation needs (edge room included). */
+/* Bytes of device workspace the simulation needs: the agent records of section 3
+ * ("Agent State Definition"), one day's household + occupation + random contact graph
+ * (section 3, "Interaction Networks") with an edge room of the mean plus 8 standard
+ * deviations of the Poisson contact counts, and the graph builder's partitions.
+ * Validates p and pop first (ABM_E_ARG / ABM_E_ABI / ABM_E_CAPACITY on a bad input;
+ * *bytes untouched then). */
 int abm_workspace_size(const abm_params* p, const abm_population* pop, size_t* bytes);
 
-/* Validate, copy the population to the device, build the tables, set day 0 (initial
- * infections exposed on day -1), and capture the day's kernel chain in a HIP graph.
- * Synchronises the stream before returning. */
+/* Validate, copy the population to the device, build the tables, set day 0, and
+ * capture the day's kernel chain in a HIP graph.  The tables are those the paper's
+ * model statement fixes: the Gamma integral over each day since exposure times the
+ * stage factor A_s (section 3, eq. 1), the Poisson contact-count thresholds of the
+ * daily networks (section 3, "Interaction Networks"), and the vaccination priority
+ * classes of the three strategies (section 5, Table 1).  The initial infections are
+ * exposed on day -1 (section 5's protocol of ten initial infections).  Synchronises
+ * the stream before returning.  On failure *out is still set (free it with
+ * abm_destroy; abm_last_error has the reason): ABM_E_ARG, ABM_E_ABI,
+ * ABM_E_WORKSPACE (d_workspace NULL or smaller than abm_workspace_size), ABM_E_HIP. */
 int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace,
                size_t ws_bytes, void* hip_stream, abm_sim** out);
 
-/* Enqueue n_days days (asynchronous). */
+/* Enqueue n_days days (asynchronous, hard mode).  One day: results due today start
+ * quarantines (section 4, "Self-quarantine", "Testing"); doses are allocated by the
+ * Table 1 priority (section 5); the day's contact graph is drawn (section 3,
+ * "Interaction Networks"); each agent's force of infection is eq. 1 summed over its
+ * contacts, and it is infected with probability eq. 2, 1 - exp(-lambda dt); stages
+ * advance (section 3, "Disease Progression"); tests are drawn.  ABM_E_STATE past
+ * n_steps or in soft mode; device-side overflow surfaces at abm_sync/run/get. */
 int abm_step(abm_sim* s, int32_t n_days);
 
-/* Enqueue n_days days, wait, and copy their outputs: h_counts [n_days][R][ABM_NC]
- * (hard mode; may be NULL), h_soft_incidence [R][n_days] (soft mode: relaxed daily
- * incidence; may be NULL). */
+/* Enqueue n_days days (the day of abm_step), wait, and copy their outputs:
+ * h_counts [n_days][R][ABM_NC] (hard mode; may be NULL): the compartment counts,
+ * infections, tests, doses and deaths the paper reports per run (section 4's sample
+ * results, section 5's protocol); h_soft_incidence [R][n_days] (soft mode; may be
+ * NULL): the relaxed daily incidence, where eq. 2's draw is replaced by a
+ * Gumbel-softmax sample on the same uniform (the differentiable simulation the
+ * abstract and section 1 motivate).  Returns ABM_E_CAPACITY if a day's graph
+ * overflowed its room. */
 int abm_run(abm_sim* s, int32_t n_days, int64_t* h_counts, float* h_soft_incidence);
 
-/* Soft mode, after abm_run from day 0: gradient of L with respect to (R, S_0..S_8) of
- * every replicate, given dL/d(soft incidence) h_dL [R][days run].  Reverse sweep over
- * checkpoints kept every checkpoint_every days; writes h_dtheta [R][ABM_N_THETA]. */
+/* Soft mode, after abm_run from day 0: gradient of L with respect to eq. 1's R and
+ * S_0..S_8 of every replicate, given dL/d(soft incidence) h_dL [R][days run] (the
+ * gradient-based calibration the abstract, section 1 and section 6 name as the use of
+ * a differentiable simulator).  Reverse sweep over checkpoints kept every
+ * checkpoint_every days; writes h_dtheta [R][ABM_N_THETA].  ABM_E_STATE in hard mode
+ * or before a soft run. */
 int abm_grad(abm_sim* s, const float* h_dL, float* h_dtheta);
 
 /* Soft mode: replace every replicate's parameters theta = (R, S_0..S_8) with
@@ -265,16 +291,22 @@ enum {
                           that LDS mask, 3 four tiles with each wave streaming the
                           edges of 64 rows through its own LDS chunk               */
 };
-/* Copy a device quantity to host (synchronous; h_bytes must be at least its size). */
+/* Copy a device quantity to host (synchronous; h_bytes must be at least its size,
+ * else ABM_E_ARG): the agent records of section 3 ("Agent State Definition"), eq. 1's
+ * force of infection and infectiousness codes, the day's contact graph (section 3,
+ * "Interaction Networks"), the tables. */
 int abm_get(abm_sim* s, int32_t what, void* h_dst, size_t h_bytes);
 
 /* Overwrite the hard-mode state: day, per-replicate vaccination latch (uint8[R]) and
- * agent states (abm_agent_state[N]).  Used to resume and to resynchronise with an
- * external reference. */
+ * agent states (abm_agent_state[N], section 3's agent state).  Used to resume and to
+ * resynchronise with an external reference.  Every draw is keyed on (seed, stream,
+ * day, agent), so a resumed run equals the uninterrupted one.  ABM_E_ARG on a wrong
+ * agent count or day; ABM_E_STATE in soft mode. */
 int abm_set_state(abm_sim* s, int32_t day, const uint8_t* h_latch,
                   const abm_agent_state* h_state, size_t n_agents);
 
-/* Wait for the stream and surface device-side errors. */
+/* Wait for the stream and surface device-side errors (ABM_E_CAPACITY).  A runtime
+ * call with no counterpart in the paper. */
 int abm_sync(abm_sim* s);
 
 void abm_destroy(abm_sim* s);
@@ -294,6 +326,10 @@ int abm_profile_reset(abm_sim* s);
 int abm_philox(uint64_t seed, const uint32_t* d_ctr, int64_t n, uint32_t* d_out, void* hip_stream);
 
 /* ---- Calibration network (maps a daily incidence curve to the parameters) ----------
+ * Learned calibration of eq. 1's R and S_a from a run's incidence: section 1 names
+ * the restrictive randomised search used to calibrate such simulators, and section 6
+ * the move beyond grid search as future work; the network is trained on the
+ * simulator's own runs and judged by re-simulating its prediction.
  * Fully connected 192 -> 256 -> 256 -> 16, ReLU after the two hidden layers.  BF16
  * weights and activations, FP32 accumulation on the matrix cores, FP32 master weights
  * with Adam.  Parameter blob layout (both the BF16 and the FP32 copies):
