@@ -175,6 +175,82 @@ def sim_profiled(sim) -> bool:
     return bool(sim._p.flags & 1)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---- the oracle's force-of-infection pass split over destination ranges ------------
+# (worker processes are spawned: they import numpy and the oracle only, never the GPU)
+_LAM = {}
+
+
+def _lam_init(folder):
+    for k in ("coef", "atab", "code", "row_ptr", "col", "w"):
+        _LAM[k] = np.load(os.path.join(folder, k + ".npy"), mmap_mode="r")
+
+
+def _lam_part(rng):
+    from oracle import step as ostep
+    lo, hi = rng
+    return ostep.lambda_rows(_LAM["coef"], np.asarray(_LAM["atab"]), _LAM["code"], _LAM["row_ptr"],
+                             _LAM["col"], _LAM["w"], lo, hi)[0]
+
+
+def lambda_pass_split(n: int = 1_000_000, max_procs: int = 16):
+    """The oracle's lambda pass (eq. 1 over one day's graph) on a population of ``n``
+    agents with the 50M-agent workload's contact structure (20 contacts per agent per
+    day), infectious codes on a seeded 2 % of agents: one process, then the rows split
+    into equal-edge destination ranges over min(cpu_count, max_procs) spawned worker
+    processes.  The two results must be bitwise equal (each row is summed in the same
+    order)."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    from synthpop import workload
+    from oracle import graph as og
+    from oracle import step as ostep
+    p, pop = workload(2, n=n)
+    N = pop.n_agents
+    rp, col, w, _ = og.build_graph(pop, p, 0)
+    m = ostep.Model(pop, p)
+    rng = np.random.default_rng(5)
+    code = np.where(rng.random(N) < 0.02, rng.integers(1, 16, N), 0).astype(np.int64)
+    E = int(rp[-1])
+    t0 = time.perf_counter()
+    lam1, _ = ostep.lambda_rows(m.coef, m.Atab, code, rp, col, w, 0, N)
+    t_one = time.perf_counter() - t0
+    P = max(1, min(os.cpu_count() or 1, max_procs))
+    cuts = np.searchsorted(rp, np.linspace(0, E, P + 1)).clip(0, N)
+    cuts[0], cuts[-1] = 0, N
+    ranges = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    shm = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    folder = tempfile.mkdtemp(prefix="abm_lam_", dir=shm)
+    try:
+        for k, v in (("coef", m.coef), ("atab", m.Atab), ("code", code), ("row_ptr", rp), ("col", col), ("w", w)):
+            np.save(os.path.join(folder, k + ".npy"), np.ascontiguousarray(v))
+        with mp.get_context("spawn").Pool(P, initializer=_lam_init, initargs=(folder,)) as pool:
+            pool.map(_lam_part, ranges)                  # warm-up: imports, page-in
+            t0 = time.perf_counter()
+            parts = pool.map(_lam_part, ranges)
+            t_multi = time.perf_counter() - t0
+    finally:
+        shutil.rmtree(folder, ignore_errors=True)
+    lamP = np.concatenate(parts)
+    return {"agents": N, "edges": E, "single_process_s": t_one, "processes": P,
+            "multi_process_s": t_multi, "single_process_edges_per_s": E / t_one,
+            "multi_process_edges_per_s": E / t_multi,
+            "bitwise_equal": bool(np.array_equal(lamP.view(np.uint64), lam1.view(np.uint64))),
+            "sample": f"one day's graph of a {N}-agent population with the plain-50M contact "
+                      f"structure; FP64 numpy oracle lambda pass"}
+
+
 def cpu_baseline(budget_s: float = 15.0):
     """The FP64 oracle, as it stands, on the first days of the 100k-agent workload."""
     from synthpop import workload
@@ -194,7 +270,9 @@ def cpu_baseline(budget_s: float = 15.0):
     wall = time.perf_counter() - t0
     return {"value": edges / wall, "unit": "edge-interactions/s", "cores": 1, "kind": "oracle",
             "sample": f"plain-100k (100,000 agents), days 0..{days - 1} of 180, FP64 numpy oracle, "
-                      f"one process; {edges} edge-interactions in {wall:.1f} s"}
+                      f"one process (one core); {edges} edge-interactions in {wall:.1f} s",
+            "host_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+            "lambda_pass": lambda_pass_split()}
 
 
 def course_run(days: int = 40, warmup: int = 5):

@@ -74,6 +74,18 @@ def vaccination_priority(strategy: int, dose: int, age_group):
     raise ValueError("unknown strategy")
 
 
+def lambda_rows(coef, atab, code, row_ptr, col, w, lo, hi):
+    """(lambda_j, sigma_j) for the destinations lo <= j < hi: sigma_j sums B_{n(e)} *
+    Atab[code of e's source] over row j of the day's graph and lambda_j = coef_j *
+    sigma_j (eq. 1 summed over the day's contacts of j).  Rows are independent, so a
+    range of them can be computed apart from the rest."""
+    e0, e1 = int(row_ptr[lo]), int(row_ptr[hi])
+    rows = np.repeat(np.arange(hi - lo), np.diff(np.asarray(row_ptr[lo:hi + 1])))
+    terms = np.asarray(w[e0:e1]) * atab[np.asarray(code)[np.asarray(col[e0:e1])]]
+    sigma = np.bincount(rows, weights=terms, minlength=hi - lo)
+    return np.asarray(coef[lo:hi]) * sigma, sigma
+
+
 class Model:
     """Static data of a run: population, maps, tables, per-replicate parameters."""
 
@@ -357,10 +369,7 @@ class Model:
         """lambda_j = R kappa S[a_j] * sum_{e in row j} B_{n(e)} * A Phi(tau_src(e))
         (eq. 1 summed over the day's contacts; non-infectious sources contribute 0)."""
         row_ptr, col, w, _ = graph
-        rows = np.repeat(np.arange(self.N), np.diff(row_ptr))
-        terms = w * self.Atab[code[col]]
-        sigma = np.bincount(rows, weights=terms, minlength=self.N)
-        return self.coef * sigma, sigma
+        return lambda_rows(self.coef, self.Atab, code, row_ptr, col, w, 0, self.N)
 
     def step(self, st, t, prev_counts, graph=None):
         """Advance state(t) -> state(t+1).  Returns (new_state, out) with out holding

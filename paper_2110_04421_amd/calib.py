@@ -121,13 +121,13 @@ class Calibrator:
         hist, best = [], (np.inf, None)
         for ep in range(epochs):
             perm = torch.from_numpy(rng.permutation(n)).cuda()
-            tot = 0.0
+            tot = torch.zeros(1, dtype=torch.float32, device="cuda")
             for b0 in range(0, n - batch + 1, batch):
                 idx = perm[b0:b0 + batch]
-                loss = self.net.train_step(x[idx].contiguous(), y[idx].contiguous(), NTHETA, lr=lr)
-                tot += float(loss.cpu())
+                # the loss stays on the device (stream order): one read-back an epoch
+                tot += self.net.train_step(x[idx].contiguous(), y[idx].contiguous(), NTHETA, lr=lr)
             val = self._mse(xv, yv)
-            hist.append((tot / max(1, n // batch), val))
+            hist.append((float(tot.cpu()) / max(1, n // batch), val))
             if val < best[0]:
                 best = (val, (self.net.master.clone(), self.net.params.clone()))
             if log:

@@ -6,6 +6,9 @@
 // rounded to BF16 (nearest, ties to even) when staged in LDS, plus an epilogue (bias,
 // ReLU, mask by a ReLU output, FP32 and/or BF16 stores).  A 64x64 output tile per
 // workgroup, 4 waves of 32x32 (2x2 MFMA blocks of 16x16), K in steps of 32.
+#include <mutex>
+#include <unordered_map>
+
 #include "abm_internal.h"
 
 namespace abm {
@@ -218,6 +221,22 @@ unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 using namespace abm;
 
+// The batch of the last forward enqueued on each workspace, kept on the host so that
+// the backward checks it without waiting for the stream.
+namespace {
+std::mutex batch_mu;
+std::unordered_map<const void*, int32_t> batch_of;
+void remember_batch(const void* ws, int32_t B) {
+  std::lock_guard<std::mutex> g(batch_mu);
+  batch_of[ws] = B;
+}
+int32_t last_batch(const void* ws) {
+  std::lock_guard<std::mutex> g(batch_mu);
+  const auto it = batch_of.find(ws);
+  return it == batch_of.end() ? -1 : it->second;
+}
+}  // namespace
+
 extern "C" {
 
 int abm_mlp_workspace_size(int32_t max_batch, size_t* bytes) {
@@ -248,7 +267,9 @@ int abm_mlp_forward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float*
   hipLaunchKernelGGL(k_copy_f32, dim3(blocks((int64_t)B * 16)), dim3(256), 0, s, (const float*)w.y, d_y,
                      (int64_t)B * 16);
   hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.hdr, B);
-  return hipGetLastError() == hipSuccess ? ABM_OK : ABM_E_HIP;
+  if (hipGetLastError() != hipSuccess) return ABM_E_HIP;
+  remember_batch(d_ws, B);
+  return ABM_OK;
 }
 
 int abm_mlp_backward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float* d_target, int32_t B,
@@ -257,10 +278,7 @@ int abm_mlp_backward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float
   MlpWs w = mlp_layout(d_ws, B);
   if (w.total > ws_bytes) return ABM_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  int32_t hb = 0;
-  if (hipMemcpyAsync(&hb, w.hdr, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return ABM_E_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return ABM_E_HIP;
-  if (hb != B) return ABM_E_STATE;     // the last forward used another batch
+  if (last_batch(d_ws) != B) return ABM_E_STATE;     // the last forward used another batch
   hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, s, (const float*)w.y, d_target, B, n_out, w.dy, d_loss);
   // dW3 = dY^T H2 ; db3 = colsum dY
   Gemm g = plain(16, 256, B);
