@@ -345,6 +345,18 @@ int abm_mlp_workspace_size(int32_t max_batch, size_t* bytes);
 /* y [B][16] fp32 = MLP(x [B][192] fp32); params bf16 (ABM_MLP_NPARAM). */
 int abm_mlp_forward(void* d_ws, size_t ws_bytes, const uint16_t* d_params_bf16, const float* d_x,
                     int32_t B, float* d_y, void* hip_stream);
+/* The forward pass above with no workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation).  Same kernels and result as abm_mlp_forward; the activations go to a
+ * scratch array of the library, one per GPU, sized for ABM_MLP_NOALLOC_MAX_BATCH rows
+ * (about 1.5 MB, held until the process ends).  Allocates nothing.  B larger than
+ * ABM_MLP_NOALLOC_MAX_BATCH: ABM_E_WORKSPACE; B < 1 or a null pointer: ABM_E_ARG.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one GPU (two
+ * streams, two threads) race, so serialise them.  The backward pass cannot follow this
+ * forward (it needs the activations in a workspace of the caller's). */
+#define ABM_MLP_NOALLOC_MAX_BATCH 1024
+int abm_mlp_forward_noalloc(const uint16_t* d_params_bf16, const float* d_x, int32_t B, float* d_y,
+                            void* hip_stream);
 /* MSE loss mean over B*n_out of (y - target) on the first n_out outputs; writes
  * d_grads_f32 (ABM_MLP_NPARAM) and the loss to d_loss (device float).  Uses the
  * activations of the last forward with the same params. */

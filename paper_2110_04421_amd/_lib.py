@@ -23,6 +23,7 @@ FLAG_DENSE_MESSAGE, FLAG_FRONTIER_ANY_SIZE, FLAG_STRAIGHT_THROUGH = 32, 64, 128
  GET_LATCH, GET_SOFT_S, GET_COEF, GET_TUNING) = range(13)
 MLP_IN, MLP_H, MLP_OUT = 192, 256, 16
 MLP_NPARAM = 256 * 192 + 256 + 256 * 256 + 256 + 16 * 256 + 16
+MLP_NOALLOC_MAX_BATCH = 1024
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "ABI mismatch", -3: "workspace too small",
           -4: "edge capacity exceeded", -5: "HIP runtime error", -6: "call out of order"}
@@ -105,6 +106,7 @@ def lib():
         "abm_philox": (C.c_int, [u64, vp, i64, vp, vp]),
         "abm_mlp_workspace_size": (C.c_int, [i32, C.POINTER(sz)]),
         "abm_mlp_forward": (C.c_int, [vp, sz, vp, vp, i32, vp, vp]),
+        "abm_mlp_forward_noalloc": (C.c_int, [vp, vp, i32, vp, vp]),
         "abm_mlp_backward": (C.c_int, [vp, sz, vp, vp, i32, i32, vp, vp, vp]),
         "abm_mlp_adam": (C.c_int, [vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]),
     }
@@ -121,8 +123,8 @@ def exported_symbols():
     return ["abm_workspace_size", "abm_create", "abm_step", "abm_run", "abm_grad", "abm_set_theta", "abm_get",
             "abm_set_state", "abm_sync", "abm_destroy", "abm_error_string", "abm_last_error",
             "abm_profile_kernels", "abm_profile_name", "abm_profile_get", "abm_profile_reset",
-            "abm_philox", "abm_mlp_workspace_size", "abm_mlp_forward", "abm_mlp_backward",
-            "abm_mlp_adam"]
+            "abm_philox", "abm_mlp_workspace_size", "abm_mlp_forward", "abm_mlp_forward_noalloc",
+            "abm_mlp_backward", "abm_mlp_adam"]
 
 
 class AbmError(RuntimeError):

@@ -183,7 +183,29 @@ struct MlpWs {
   size_t total;
 };
 
-size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of the layout below for a batch of B (the sum mlp_layout takes).
+constexpr size_t mlp_ws_bytes(int64_t B) {
+  size_t o = 256;
+  o = al(o + (size_t)B * 192 * 2);
+  o = al(o + (size_t)B * 256 * 2);
+  o = al(o + (size_t)B * 256 * 2);
+  o = al(o + (size_t)B * 16 * 4);
+  o = al(o + (size_t)B * 16 * 4);
+  o = al(o + (size_t)B * 256 * 4);
+  o = al(o + (size_t)B * 256 * 4);
+  return o;
+}
+// The forward pass touches only the layout's first five parts (header, Xb, H1, H2, Y).
+constexpr size_t mlp_fwd_bytes(int64_t B) {
+  size_t o = 256;
+  o = al(o + (size_t)B * 192 * 2);
+  o = al(o + (size_t)B * 256 * 2);
+  o = al(o + (size_t)B * 256 * 2);
+  o = al(o + (size_t)B * 16 * 4);
+  return o;
+}
 
 MlpWs mlp_layout(void* base, int64_t B) {
   MlpWs w{};
@@ -235,22 +257,10 @@ int32_t last_batch(const void* ws) {
   const auto it = batch_of.find(ws);
   return it == batch_of.end() ? -1 : it->second;
 }
-}  // namespace
-
-extern "C" {
-
-int abm_mlp_workspace_size(int32_t max_batch, size_t* bytes) {
-  if (!bytes || max_batch < 1) return ABM_E_ARG;
-  *bytes = mlp_layout(nullptr, max_batch).total;
-  return ABM_OK;
-}
-
-int abm_mlp_forward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float* d_x, int32_t B,
-                    float* d_y, void* stream) {
-  if (!d_ws || !P || !d_x || !d_y || B < 1) return ABM_E_ARG;
-  MlpWs w = mlp_layout(d_ws, B);
-  if (w.total > ws_bytes) return ABM_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
+// The forward pass on workspace w: inputs rounded to BF16, two hidden layers with bias
+// and ReLU, the output layer in FP32, copied to y.
+hipError_t enqueue_forward(const MlpWs& w, const uint16_t* P, const float* d_x, int32_t B, float* d_y,
+                           hipStream_t s) {
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks((int64_t)B * 192)), dim3(256), 0, s, d_x, w.xb, (int64_t)B * 192);
   Gemm g = plain(B, 256, 192);
   g.sam = 192; g.sak = 1; g.sbn = 192; g.sbk = 1;
@@ -267,8 +277,63 @@ int abm_mlp_forward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float*
   hipLaunchKernelGGL(k_copy_f32, dim3(blocks((int64_t)B * 16)), dim3(256), 0, s, (const float*)w.y, d_y,
                      (int64_t)B * 16);
   hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.hdr, B);
-  if (hipGetLastError() != hipSuccess) return ABM_E_HIP;
+  return hipGetLastError();
+}
+
+// Scratch of the allocation-free forward: the activations of one batch of at most
+// ABM_MLP_NOALLOC_MAX_BATCH rows, in the layout of mlp_layout (about 1.5 MB).  Each
+// GPU holds its own copy for the life of the process.  Its device address is taken
+// once per device (with that device current) and kept; the array's name is a host-side
+// stand-in and is never handed to a kernel.
+constexpr size_t NOALLOC_BYTES = mlp_fwd_bytes(ABM_MLP_NOALLOC_MAX_BATCH);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES] = {};
+
+hipError_t scratch_base(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int abm_mlp_workspace_size(int32_t max_batch, size_t* bytes) {
+  if (!bytes || max_batch < 1) return ABM_E_ARG;
+  *bytes = mlp_ws_bytes(max_batch);
+  return ABM_OK;
+}
+
+int abm_mlp_forward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float* d_x, int32_t B,
+                    float* d_y, void* stream) {
+  if (!d_ws || !P || !d_x || !d_y || B < 1) return ABM_E_ARG;
+  MlpWs w = mlp_layout(d_ws, B);
+  if (w.total > ws_bytes) return ABM_E_WORKSPACE;
+  if (enqueue_forward(w, P, d_x, B, d_y, (hipStream_t)stream) != hipSuccess) return ABM_E_HIP;
   remember_batch(d_ws, B);
+  return ABM_OK;
+}
+
+int abm_mlp_forward_noalloc(const uint16_t* P, const float* d_x, int32_t B, float* d_y, void* stream) {
+  if (!P || !d_x || !d_y || B < 1) return ABM_E_ARG;
+  if (B > ABM_MLP_NOALLOC_MAX_BATCH) return ABM_E_WORKSPACE;
+  void* base = nullptr;
+  if (scratch_base(&base) != hipSuccess) return ABM_E_HIP;
+  MlpWs w = mlp_layout(base, B);
+  if (enqueue_forward(w, P, d_x, B, d_y, (hipStream_t)stream) != hipSuccess) return ABM_E_HIP;
   return ABM_OK;
 }
 
