@@ -153,7 +153,9 @@ typedef struct {
   int32_t strategy;                /* ABM_STRATEGY_* (priority order of Table 1)          */
   float gumbel_tau;                /* temperature of the relaxed infection (soft mode)    */
   int32_t checkpoint_every;        /* soft mode: days between adjoint checkpoints         */
-  int64_t edge_capacity;           /* directed-edge room per day; 0 = mean + 8 sigma      */
+  int64_t edge_capacity;           /* directed-edge room per day; 0 = mean + 8 sigma of
+                                      the contact counts of independent replicates (give
+                                      more room when replicates share a stream word)     */
   int32_t flags;                   /* ABM_FLAG_*                                          */
   int32_t disease_model;           /* ABM_DISEASE_SEIRM or ABM_DISEASE_COURSE (hard mode)  */
   /* the course, per age group: asymptomatic share of infections, severe share of the

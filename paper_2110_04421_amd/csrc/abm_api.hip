@@ -332,7 +332,9 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.ecap = (int64_t)ecap;
   // partitioned builder geometry: leaves of 2^lb destinations holding a few thousand
   // received entries, at most 1024 level-1 buckets of 256 leaves
-  z.ccap = (int64_t)std::ceil(cmean + 8.0 * std::sqrt(cmean) + 4096.0);
+  // room for the day's contacts: at least what the edge room leaves after the household
+  // edges (each contact is two edges), so that a larger edge_capacity enlarges both
+  z.ccap = (int64_t)std::ceil(std::max(cmean + 8.0 * std::sqrt(cmean), (ecap - hh_edges) / 2.0) + 4096.0);
   const double rbar = cmean / (double)N;
   int lb = (int)std::floor(std::log2(6000.0 / std::max(rbar, 0.5)));
   lb = std::min(11, std::max(6, lb));

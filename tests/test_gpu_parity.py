@@ -8,7 +8,7 @@ counted (zero on the 1,000-agent workload).
 import numpy as np
 import pytest
 
-from helpers import require_gpu, to_records, from_records, state_mismatch, lam_close
+from helpers import require_gpu, lockstep, from_records, state_mismatch
 from oracle import graph as og
 from oracle import philox as oph
 from oracle import step as ostep
@@ -83,39 +83,10 @@ def test_csr_bit_exact_at_high_contact_means(mu):
 
 
 def _lockstep(p, pop, T, graph=True, allow_near=True, check_csr_every=0):
-    """Step GPU and oracle together; resync the GPU from the oracle after a counted
-    near-threshold disagreement.  Returns (near draws seen, worst lambda rel err)."""
-    m = ostep.Model(pop, p)
-    st = m.init_state()
-    prev = np.zeros((m.nrep, ostep.NC), np.int64)
-    m.put_counts(prev, st)
-    near_total, worst = 0, 0.0
-    with _sim(p, pop, graph=graph) as s:
-        for t in range(T):
-            cg = s.run(1)[0]
-            new, out = m.step(st, t, prev)
-            assert np.array_equal(s.code().astype(np.int64), out["code"]), f"codes differ on day {t}"
-            ok, err = lam_close(s.lam(), out["lam"])
-            worst = max(worst, err)
-            assert ok, f"lambda rel err {err} on day {t}"
-            if check_csr_every and t % check_csr_every == 0:
-                rp, col, w = s.csr()
-                assert np.array_equal(col.astype(np.int64), out["graph"][1])
-            gst = from_records(s.state(), s.latch())
-            bad = state_mismatch(gst, new)
-            near = (st["stage"] == 0) & ~out["immune"] & (np.abs(out["u0"] - out["prob"]) <= 1e-6)
-            near_total += int(near.sum())
-            assert set(bad.tolist()) <= set(np.flatnonzero(near).tolist()), \
-                f"day {t}: {bad.size} agents differ outside the near-threshold window"
-            assert np.array_equal(gst["latch"], new["latch"])
-            if bad.size:
-                assert allow_near
-                s.set_state(t + 1, new["latch"].astype(np.uint8), to_records(new, s.state().dtype))
-            else:
-                keep = [c for c in range(ostep.NC) if c != ostep.C_NEAR]
-                assert np.array_equal(cg[:, keep], out["counts"][:, keep]), f"counts differ on day {t}"
-            st, prev = new, out["counts"]
-    return near_total, worst
+    """Step GPU and oracle together (helpers.lockstep); (near draws, worst lambda err)."""
+    near, worst, _ = lockstep(_sim, p, pop, T, graph=graph, allow_near=allow_near,
+                              check_csr_every=check_csr_every)
+    return near, worst
 
 
 def test_trajectory_plain_1k_bit_exact():
