@@ -413,6 +413,58 @@ def adjoint_cost(days: int = 180):
             "dL_dR_of_total_incidence": float(g[0, 0])}
 
 
+def mlp_throughput(reps: int = 50):
+    """Achieved TFLOP/s of the calibration network's BF16 matrix-core kernels: the
+    forward pass at a batch of 1024 and a training step (forward, backward, Adam) at
+    a batch of 256, timed with HIP events on the stream the kernels run on."""
+    import torch
+    from paper_2110_04421_amd.mlp import MLP
+    from paper_2110_04421_amd import _lib as L
+    net = MLP(1024, seed=1)
+    fwd_flop = 2.0 * (L.MLP_IN * L.MLP_H + L.MLP_H * L.MLP_H + L.MLP_H * L.MLP_OUT)
+    x = torch.randn(1024, L.MLP_IN, device="cuda")
+    xt, yt = x[:256].contiguous(), torch.zeros(256, L.MLP_OUT, device="cuda")
+    out = {"workload": "calibration network 192-256-256-16, BF16 operands, FP32 accumulation",
+           "peak_TFLOP_per_s": 2500.0}
+    for name, fn, flop in (("forward_batch_1024", lambda: net.forward(x), 1024 * fwd_flop),
+                           # backward: two products per layer (weights and inputs; the
+                           # first layer's input gradient is not formed)
+                           ("train_step_batch_256", lambda: net.train_step(xt, yt, 10, lr=0.0),
+                            256 * fwd_flop * (3.0 - (L.MLP_IN * L.MLP_H) / (fwd_flop / 2.0)))):
+        for _ in range(5):
+            fn()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        out[name] = {"us_per_call": sec * 1e6, "TFLOP_per_s": flop / sec / 1e12,
+                     "frac_of_peak": flop / sec / 1e12 / 2500.0}
+    return out
+
+
+def calibration_leg(n_train: int = 4096, n_heldout: int = 256, agents: int = 10_000, days: int = 120):
+    """Learned calibration against grid search, re-simulation error and wall time of
+    each (the network, the 41-point R grid, the 231-point R x shared-susceptibility
+    grid, and that grid at the network's simulation budget)."""
+    from paper_2110_04421_amd import calib
+    s = calib.run(n_train=n_train, n_heldout=n_heldout, n_agents=agents, epochs=20, days=days,
+                  n_gd=64, gd_iters=20)
+    keys = ("resim_rel_l2_same_stream", "resim_rel_l2_same_stream_median",
+            "resim_rel_l2_independent_stream", "transmissibility_rmse_log", "simulations_per_method",
+            "seconds")
+    out = {"workload": f"calib-{agents // 1000}k: {agents} agents, {days} days, {n_train} training runs, "
+                       f"{n_heldout} held-out curves; gradient refinement on the first 64"}
+    out.update({k: s[k] for k in keys})
+    gd = s["gradient_descent"]
+    out["gradient_refinement"] = {k: gd[k] for k in ("resim_rel_l2_same_stream",
+                                                     "resim_rel_l2_same_stream_median", "seconds")}
+    return out
+
+
 def _initial(sim, pop):
     rec = np.zeros(sim.N, sim.state().dtype)
     rec["t_exp"] = rec["q_until"] = rec["test_day"] = rec["d1"] = rec["d2"] = -32768
@@ -540,6 +592,10 @@ def main():
         line["batched"] = batched_vs_plain()
         log("adjoint cost")
         line["adjoint"] = adjoint_cost()
+        log("calibration network throughput")
+        line["mlp"] = mlp_throughput()
+        log("learned calibration against grid search")
+        line["calibration"] = calibration_leg()
         log("eleven-stage course at 50M agents")
         line["course"] = course_run()
         log("exposure notification at 50M agents")

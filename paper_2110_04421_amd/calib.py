@@ -11,6 +11,13 @@ groups, is the fallback and the baseline.  Gradient descent through the relaxed
 simulator's adjoint (``gd_fit``), from the training mean and from the network's
 prediction, is the third method.
 
+R and the S_a enter eq. 1 only as the products rho_a = R S_a (the coefficient of
+age group a is R kappa S_a), so a curve can at best identify the nine products, and
+mostly their mean.  The network is therefore trained on the standardised logarithms
+of the products; a prediction is split back into (R, S) with R = mean_a(rho_a) /
+mean(S range) clipped to the R range and S_a = rho_a / R, which re-simulates the
+predicted products exactly.
+
     python -m paper_2110_04421_amd.calib --train 50000 --heldout 1000 --agents 100000
 """
 from __future__ import annotations
@@ -42,6 +49,23 @@ def from_unit(u):
     out[:, 0] = R_LO + u[:, 0] * (R_HI - R_LO)
     out[:, 1:] = S_LO + u[:, 1:] * (S_HI - S_LO)
     return out
+
+
+S_MID = 0.5 * (S_LO + S_HI)
+N_RHO = 9
+
+
+def products(theta):
+    """rho_a = R S_a [n, 9]: what eq. 1 sees of (R, S_0..S_8)."""
+    t = np.asarray(theta, np.float64)
+    return t[:, :1] * t[:, 1:]
+
+
+def split_products(rho):
+    """(R, S) with R S_a = rho_a: R = mean(rho) / mean of the S range, within [3, 7]."""
+    rho = np.asarray(rho, np.float64)
+    R = np.clip(rho.mean(1) / S_MID, R_LO, R_HI)
+    return np.concatenate([R[:, None], rho / R[:, None]], 1)
 
 
 def sample_theta(n, seed):
@@ -91,17 +115,28 @@ class Features:
 
 
 class Calibrator:
+    """The network maps features of a curve to the standardised log products
+    log(R S_a) (nine outputs of sixteen)."""
+
     def __init__(self, seed=0, max_batch=1024):
         from .mlp import MLP
         self.net = MLP(max_batch, seed=seed)
         self.feat = None
 
-    def _mse(self, x, y):
+    def _targets(self, theta):
+        y = np.zeros((theta.shape[0], L.MLP_OUT), np.float32)
+        y[:, :N_RHO] = (np.log(products(theta)) - self.zmu) / self.zsd
+        return y
+
+    def _forward_all(self, x):
         out = []
         for b0 in range(0, x.shape[0], self.net.max_batch):
             out.append(self.net.forward(x[b0:b0 + self.net.max_batch].contiguous()))
-        pred = self.net.torch.cat(out)[:, :NTHETA]
-        return float(((pred - y[:, :NTHETA]) ** 2).mean().cpu())
+        return self.net.torch.cat(out)
+
+    def _mse(self, x, y):
+        pred = self._forward_all(x)[:, :N_RHO]
+        return float(((pred - y[:, :N_RHO]) ** 2).mean().cpu())
 
     def train(self, curves, theta, epochs=30, batch=256, lr=1e-3, seed=0, val_frac=0.1, log=None):
         """Adam on the network's own kernels; the epoch with the lowest validation MSE
@@ -110,10 +145,10 @@ class Calibrator:
         n_all = theta.shape[0]
         n_val = max(1, int(val_frac * n_all))
         self.feat = Features().fit(curves[n_val:])
+        z = np.log(products(theta[n_val:]))
+        self.zmu, self.zsd = z.mean(0), z.std(0) + 1e-6
         x_all = torch.from_numpy(self.feat(curves)).cuda()
-        y_all = np.zeros((n_all, L.MLP_OUT), np.float32)
-        y_all[:, :NTHETA] = to_unit(theta)
-        y_all = torch.from_numpy(y_all).cuda()
+        y_all = torch.from_numpy(self._targets(theta)).cuda()
         xv, yv = x_all[:n_val], y_all[:n_val]
         x, y = x_all[n_val:], y_all[n_val:]
         rng = np.random.default_rng(seed)
@@ -125,7 +160,7 @@ class Calibrator:
             for b0 in range(0, n - batch + 1, batch):
                 idx = perm[b0:b0 + batch]
                 # the loss stays on the device (stream order): one read-back an epoch
-                tot += self.net.train_step(x[idx].contiguous(), y[idx].contiguous(), NTHETA, lr=lr)
+                tot += self.net.train_step(x[idx].contiguous(), y[idx].contiguous(), N_RHO, lr=lr)
             val = self._mse(xv, yv)
             hist.append((float(tot.cpu()) / max(1, n // batch), val))
             if val < best[0]:
@@ -138,12 +173,11 @@ class Calibrator:
         return hist
 
     def predict(self, curves):
+        """(R, S_0..S_8) [n, 10] whose products are the network's prediction."""
         import torch
         x = torch.from_numpy(self.feat(curves)).cuda()
-        out = []
-        for b0 in range(0, x.shape[0], self.net.max_batch):
-            out.append(self.net.forward(x[b0:b0 + self.net.max_batch].contiguous()).cpu().numpy())
-        return from_unit(np.concatenate(out)[:, :NTHETA])
+        zt = self._forward_all(x)[:, :N_RHO].cpu().numpy().astype(np.float64)
+        return split_products(np.exp(zt * self.zsd + self.zmu))
 
 
 def rel_l2(a, b):
@@ -239,14 +273,24 @@ def gd_fit(params, base_pop, targets, theta0, seed, stream0=0, iters=30, lr=0.05
     return best_th, hist / n, float(best_all.mean())
 
 
+def matched_grid2_thetas(n_runs):
+    """A two-dimensional grid (R x one shared susceptibility) of about ``n_runs``
+    points, twice as many R values as susceptibility values: grid search given the
+    simulations the network's training set took."""
+    n_s = max(2, int(round(np.sqrt(n_runs / 2.0))))
+    return grid2_thetas(n_r=max(2, n_runs // n_s), n_s=n_s)
+
+
 def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, batch=256,
-        log=None, tol=None, n_gd=256, gd_iters=30):
+        log=None, tol=None, n_gd=256, gd_iters=30, matched_grid=True):
     """The whole calibration study; returns a summary dict.
 
     Held-out targets: seed 2, stream words 0..n-1.  Each prediction is re-simulated
     twice: on the target's own stream (common random numbers: isolates the parameter
     error; the true parameters give 0) and on an independent stream (seed 3; the true
-    parameters give the noise floor)."""
+    parameters give the noise floor).  Grid search runs on seed 4: the 41-point R grid,
+    the 231-point R x shared-susceptibility grid and (``matched_grid``) a grid of that
+    form with as many points as the network's training runs."""
     from synthpop import workload
     p, pop = workload(4, n=n_agents, mode=L.HARD, n_steps=days)
     t0 = time.perf_counter()
@@ -262,50 +306,53 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
     t0 = time.perf_counter()
     th_mlp = cal.predict(c_ho)
     t_pred = time.perf_counter() - t0
-    gt = grid_thetas()
-    t0 = time.perf_counter()
-    c_grid = simulate_curves(p, pop, gt, seed=4, days=days, batch=batch)
-    th_grid = grid_fit(c_grid, gt, c_ho)
-    t_grid = time.perf_counter() - t0
+    fits = {"mlp": th_mlp}
+    seconds = dict(training_data=t_data, training=t_train, mlp_predict=t_pred)
+    runs = dict(mlp=n_train)
+    grids = [("grid", grid_thetas()), ("grid2d", grid2_thetas())]
+    if matched_grid:
+        grids.append(("grid2d_matched", matched_grid2_thetas(n_train)))
+    for name, gt in grids:
+        t0 = time.perf_counter()
+        fits[name] = grid_fit(simulate_curves(p, pop, gt, seed=4, days=days, batch=batch), gt, c_ho)
+        seconds[name + "_search"] = time.perf_counter() - t0
+        runs[name] = int(gt.shape[0])
     th_mean = np.tile(th_tr.mean(0), (n_heldout, 1))
-    g2 = grid2_thetas()
-    t0 = time.perf_counter()
-    th_grid2 = grid_fit(simulate_curves(p, pop, g2, seed=4, days=days, batch=batch), g2, c_ho)
-    t_grid2 = time.perf_counter() - t0
+    fits["training_mean_params"] = th_mean
     sim = lambda th, seed: simulate_curves(p, pop, th, seed=seed, days=days, batch=batch)
-    e_ind = {k: rel_l2(sim(th, 3), c_ho) for k, th in
-             (("mlp", th_mlp), ("grid", th_grid), ("grid2d", th_grid2), ("true_params", th_ho),
-              ("training_mean_params", th_mean))}
-    e_crn = {k: rel_l2(sim(th, 2), c_ho) for k, th in
-             (("mlp", th_mlp), ("grid", th_grid), ("grid2d", th_grid2), ("training_mean_params", th_mean))}
+    e_ind = {k: rel_l2(sim(th, 3), c_ho) for k, th in list(fits.items()) + [("true_params", th_ho)]}
+    e_crn = {k: rel_l2(sim(th, 2), c_ho) for k, th in fits.items()}
     unit = lambda th: float(np.sqrt(((to_unit(th) - to_unit(th_ho)) ** 2).mean()))
     rmse_R = lambda th: float(np.sqrt(((th[:, 0] - th_ho[:, 0]) ** 2).mean()))
+    lrho = lambda th: np.log(products(th))
+    rho_rmse = lambda th: float(np.sqrt(((lrho(th) - lrho(th_ho)) ** 2).mean()))
+    rbar = lambda th: np.log(products(th).mean(1))
+    rbar_rmse = lambda th: float(np.sqrt(((rbar(th) - rbar(th_ho)) ** 2).mean()))
     summary = dict(
         agents=n_agents, days=days, train_runs=n_train, heldout=n_heldout, epochs=epochs,
+        simulations_per_method=runs,
         train_mse_first=hist[0][0], train_mse_last=hist[-1][0], best_val_mse=cal.best_val,
         resim_rel_l2_independent_stream={k: float(v.mean()) for k, v in e_ind.items()},
         resim_rel_l2_same_stream={k: float(v.mean()) for k, v in e_crn.items()},
         resim_rel_l2_same_stream_median={k: float(np.median(v)) for k, v in e_crn.items()},
-        param_rmse_unit=dict(mlp=unit(th_mlp), grid=unit(th_grid), grid2d=unit(th_grid2),
-                             training_mean=unit(th_mean)),
-        R_rmse=dict(mlp=rmse_R(th_mlp), grid=rmse_R(th_grid), grid2d=rmse_R(th_grid2),
-                    training_mean=rmse_R(th_mean)),
-        seconds=dict(training_data=t_data, training=t_train, mlp_predict=t_pred,
-                     grid_search=t_grid, grid2d_search=t_grid2))
+        transmissibility_rmse_log={k: rbar_rmse(th) for k, th in fits.items()},
+        products_rmse_log={k: rho_rmse(th) for k, th in fits.items()},
+        param_rmse_unit={k: unit(th) for k, th in fits.items()},
+        R_rmse={k: rmse_R(th) for k, th in fits.items()},
+        seconds=seconds)
     if n_gd > 0:
         # gradient descent through the adjoint on the first n_gd held-out curves, from
         # the training mean and from the network's prediction
         k = min(n_gd, n_heldout)
         gd = {}
         for name, th0 in (("gd_from_mean", th_mean[:k]), ("gd_from_mlp", th_mlp[:k]),
-                          ("gd_from_grid2d", th_grid2[:k])):
+                          ("gd_from_grid2d", fits["grid2d"][:k])):
             t0 = time.perf_counter()
             th, h, lbest = gd_fit(p, pop, c_ho[:k], th0, seed=2, iters=gd_iters, days=days, batch=batch,
                                   log=log)
             gd[name] = dict(seconds=time.perf_counter() - t0, loss_first=float(h[0]), loss_best=lbest,
                             theta=th)
-        sub = {"mlp": th_mlp[:k], "grid": th_grid[:k], "grid2d": th_grid2[:k],
-               "training_mean_params": th_mean[:k]}
+        sub = {n_: th[:k] for n_, th in fits.items()}
         sub.update({n_: v["theta"] for n_, v in gd.items()})
         e_sub = {n_: rel_l2(simulate_curves(p, pop, th, seed=2, days=days, batch=batch), c_ho[:k])
                  for n_, th in sub.items()}
@@ -321,7 +368,7 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
         # fallback: where the network's re-simulation misses the target by more than tol,
         # grid search runs as well and the better of the two fits is kept
         fb = e_crn["mlp"] > tol
-        e_comb = np.where(fb, np.minimum(e_crn["grid"], e_crn["mlp"]), e_crn["mlp"])
+        e_comb = np.where(fb, np.minimum(e_crn["grid2d"], e_crn["mlp"]), e_crn["mlp"])
         summary["with_fallback"] = dict(tol=tol, fallback_share=float(fb.mean()),
                                         resim_rel_l2_same_stream=float(e_comb.mean()))
     return summary
