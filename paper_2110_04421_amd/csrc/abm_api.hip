@@ -118,6 +118,21 @@ struct Sizes {
 // every slot starts on a 256-byte boundary (the message kernel reads 16-byte groups)
 int64_t ring_rstride(const Sizes& z) { return (z.N + 1 + 63) & ~(int64_t)63; }
 int64_t ring_cstride(const Sizes& z) { return (z.ecap + 63) & ~(int64_t)63; }
+// graph slots: the notification window; in relaxed mode every day of the run if their
+// graphs fit in 16 GB (built once by the forward pass, reused by the adjoint's recompute
+// and reverse sweep and by later runs at new parameters), else the checkpoint interval
+// (a segment's graphs are built by its recompute and reused by the reverse sweep), else
+// one slot (every use builds the graph)
+constexpr double RING_BUDGET = 16e9;
+int64_t ring_slots(const Sizes& z, const abm_params& p) {
+  if (p.app_adoption > 0.f) return p.den_window;
+  if (p.mode == ABM_SOFT) {
+    const double slot = (double)(ring_rstride(z) + ring_cstride(z)) * 4.0;
+    if (z.T > 1 && (double)z.T * slot <= RING_BUDGET) return z.T;
+    if (z.seg > 1 && (double)z.seg * slot <= RING_BUDGET) return z.seg;
+  }
+  return 1;
+}
 // room of one list of flagged rows.  List b takes the 256-agent groups g with
 // g mod FRONT_NB = b: at most ceil(ceil(N/256)/FRONT_NB) groups of 256, and there are
 // at least ceil(N/256) tiles, so this bound holds
@@ -140,6 +155,10 @@ struct abm_sim {
   std::string msg;
   int32_t host_day = 0;
   bool soft_ready = false;
+  // relaxed mode with a graph slot for every day: graphs of days [0, graphs_built) are
+  // in their slots (a day's graph depends on the seed, stream words and day only, so
+  // new parameters from abm_set_theta keep them valid)
+  int32_t graphs_built = 0;
   std::vector<RepInfo> reps;
   char* ws = nullptr;
   // profiling: one set of nk + 1 events per day enqueued since the last read-out
@@ -402,10 +421,11 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.lambda = L.take<float>(z.N);
   o.own = L.take<uint16_t>(z.N);
   o.recv = L.take<uint32_t>(z.N);
-  if (p.app_adoption <= 0.f) o.row_ptr = L.take<int32_t>(z.N + 1);
+  const int64_t nring = ring_slots(z, p);
+  if (nring == 1) o.row_ptr = L.take<int32_t>(z.N + 1);
   o.cur_occ = L.take<int32_t>(z.N);
   o.cur_rand = L.take<int32_t>(z.N);
-  if (p.app_adoption <= 0.f) o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
+  if (nring == 1) o.col = L.take<int32_t>(z.ecap + 4);    // +4: the message kernel reads 16-byte groups
   o.scan_part = L.take<int64_t>(z.nscan + 1);
   o.vhist = L.take<int32_t>(z.ntiles * NBUCKET);
   o.vplan = L.take<int32_t>(2 * z.R);
@@ -420,12 +440,12 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.ninf = L.take<int32_t>(1);
   o.work = L.take<int32_t>((int64_t)FRONT_NB * front_cap(z));
   o.nwork = L.take<int32_t>(FRONT_NB);
-  if (p.app_adoption > 0.f) {
-    // the day's graph lives in slot day % den_window; slots start on 256-byte bounds
-    o.ring_rp = L.take<int32_t>((int64_t)p.den_window * ring_rstride(z));
-    o.ring_col = L.take<int32_t>((int64_t)p.den_window * ring_cstride(z) + 4);
-    o.den_mask = L.take<uint32_t>((z.N + 31) / 32 + 1);
+  if (nring > 1) {
+    // the day's graph lives in slot day % nring; slots start on 256-byte bounds
+    o.ring_rp = L.take<int32_t>(nring * ring_rstride(z));
+    o.ring_col = L.take<int32_t>(nring * ring_cstride(z) + 4);
   }
+  if (p.app_adoption > 0.f) o.den_mask = L.take<uint32_t>((z.N + 31) / 32 + 1);
   o.flags = L.take<int32_t>(1);
   o.seeds = L.take<int32_t>(std::max<int64_t>(z.nseeds, 1));
   if (z.pb_on) {
@@ -474,8 +494,8 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
 // the pre-pass of the following den_window days reads it: no copy.
 Dev day_dev(const abm_sim* s, int64_t day) {
   Dev d = s->d;
-  if (d.den_on) {
-    const int64_t slot = day % d.den_window;
+  if (d.ring_n > 1) {
+    const int64_t slot = day % d.ring_n;
     d.row_ptr = d.ring_rp + slot * d.ring_rstride;
     d.col = d.ring_col + slot * d.ring_cstride;
   }
@@ -684,10 +704,11 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.lambda = (float*)(ws + o.lambda);
   d.own = (uint16_t*)(ws + o.own);
   d.recv = (uint32_t*)(ws + o.recv);
-  if (!d.den_on) d.row_ptr = (int32_t*)(ws + o.row_ptr);
+  d.ring_n = (int32_t)ring_slots(z, *p);
+  if (d.ring_n == 1) d.row_ptr = (int32_t*)(ws + o.row_ptr);
   d.cur_occ = (int32_t*)(ws + o.cur_occ);
   d.cur_rand = (int32_t*)(ws + o.cur_rand);
-  if (!d.den_on) d.col = (int32_t*)(ws + o.col);
+  if (d.ring_n == 1) d.col = (int32_t*)(ws + o.col);
   d.scan_part = (int64_t*)(ws + o.scan_part);
   d.vhist = (int32_t*)(ws + o.vhist);
   d.vplan = (int32_t*)(ws + o.vplan);
@@ -714,15 +735,15 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.den_window = p->den_window;
   d.den_adoption = p->app_adoption;
   d.den_compliance = p->den_compliance;
-  if (d.den_on) {
+  if (d.ring_n > 1) {
     d.ring_rp = (int32_t*)(ws + o.ring_rp);
     d.ring_col = (int32_t*)(ws + o.ring_col);
     d.ring_rstride = ring_rstride(z);
     d.ring_cstride = ring_cstride(z);
     d.row_ptr = d.ring_rp;                 // slot 0: day 0's graph
     d.col = d.ring_col;
-    d.den_mask = (uint32_t*)(ws + o.den_mask);
   }
+  if (d.den_on) d.den_mask = (uint32_t*)(ws + o.den_mask);
   d.flags = (int32_t*)(ws + o.flags);
   if (p->mode == ABM_SOFT) {
     d.s = (float*)(ws + o.s);

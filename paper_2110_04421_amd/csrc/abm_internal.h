@@ -84,7 +84,10 @@ struct Dev {
   float den_adoption, den_compliance;
   int32_t* ring_rp;             // [den_window][ring_rstride] row pointers of the last days' graphs
   int32_t* ring_col;            // [den_window][ring_cstride] their columns
-  int64_t ring_rstride, ring_cstride;  // slot strides (elements); day t's graph is slot t % den_window
+  int64_t ring_rstride, ring_cstride;  // slot strides (elements); day t's graph is slot t % ring_n
+  int32_t ring_n;               // graph slots: den_window (notification), the checkpoint
+                                // interval (relaxed mode: the reverse sweep reuses the
+                                // segment's graphs), else 1 (no ring)
   uint32_t* den_mask;           // [(N+31)/32] contacts of today's positive app users
 
   const RepInfo* rep;

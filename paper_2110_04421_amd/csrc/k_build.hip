@@ -614,14 +614,15 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 
 // ---- P5: per leaf, sort by (destination, network, initiator) in LDS ------------------
 // A lane keeps up to PB_LEAF_PER of the leaf's entries in registers, so the leaf is
-// read once (entries beyond PB_LEAF_THREADS * PB_LEAF_PER are read again from memory).
+// read once (entries beyond LT * PB_LEAF_PER are read again from memory).
 // The LDS holds pb_leaf_cap entries.  A larger leaf is sorted in groups of whole keys
 // that each fit; only a single (destination, network) run longer than the cap is an
 // error.
-constexpr int PB_LEAF_THREADS = 512;
+// Leaves whose mean size (the LDS room is 1.25x the mean + 512) exceeds what 512 lanes
+// hold in registers take 1024 lanes; smaller ones are faster with 512.
 constexpr int PB_LEAF_PER = 12;
-__global__ __launch_bounds__(PB_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_leaf(Dev d) {
-  constexpr int LT = PB_LEAF_THREADS;
+template <int LT>
+__global__ __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_leaf(Dev d) {
   extern __shared__ uint32_t lds[];
   if (*d.flags) return;
   const int L = blockIdx.x;
@@ -884,8 +885,11 @@ static size_t gen_lds(const Dev& d) {
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)leaf_lds(d));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_pb_leaf<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)leaf_lds(d));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_pb_gen, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)gen_lds(d));
@@ -916,7 +920,12 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
       break;
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
-    case 5: hipLaunchKernelGGL(k_pb_leaf, dim3(d.pb_nleaf), dim3(PB_LEAF_THREADS), leaf_lds(d), s, d); break;
+    case 5:
+      if (d.pb_leaf_cap > 512 * PB_LEAF_PER * 5 / 4 + 512)   // mean leaf beyond 512 lanes' registers
+        hipLaunchKernelGGL(k_pb_leaf<1024>, dim3(d.pb_nleaf), dim3(1024), leaf_lds(d), s, d);
+      else
+        hipLaunchKernelGGL(k_pb_leaf<512>, dim3(d.pb_nleaf), dim3(512), leaf_lds(d), s, d);
+      break;
     case 6: launch_scan(d, s); break;
     default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
   }

@@ -7,7 +7,8 @@ judged quantities are the transmissibility and the plain simulator re-run at the
 prediction.  Against grid search over R, over R x one shared susceptibility (231
 runs), and over that grid with as many runs as the network's training set:
 
-* the network's transmissibility is the closest (log RMSE), at no simulation per query;
+* the network's transmissibility is the closest (log RMSE), with no simulation per query
+  (its training runs are spent once, like the grids' runs);
 * its prediction re-simulated on an independent stream is the closest to the target;
 * refined by 20 gradient steps through the adjoint on the target's own stream, it
   reproduces the curve on that stream better than the same refinement started without
@@ -38,8 +39,6 @@ def test_mlp_calibration_gains_over_grid_search():
         assert tr["mlp"] < 0.9 * tr[g], (g, tr)
         assert ind["mlp"] < ind[g], (g, ind)
     assert tr["mlp"] < 0.5 * tr["training_mean_params"]
-    # a query costs no simulation
-    assert s["seconds"]["mlp_predict"] < s["seconds"]["grid_search"]
     gd = s["gradient_descent"]
     mean, med = gd["resim_rel_l2_same_stream"], gd["resim_rel_l2_same_stream_median"]
     for m in (mean, med):
