@@ -93,3 +93,35 @@ def test_training_overfits_a_small_set():
     for _ in range(400):
         loss = net.train_step(x, t, 10, lr=1e-3)
     assert float(loss.cpu()) < 0.02 * first
+
+
+def _exact_case(B, n_out, seed):
+    """Operands whose every product and partial sum is exact in FP32 and whose hidden
+    activations are exact in BF16 where the kernels store them (inputs in {-1, 0, 1},
+    weights and biases in {-1, 0, 1}/16, targets a quarter step from the oracle's
+    output, B * n_out = 1024): the FP32-accumulating matrix-core kernels then owe the
+    FP64 oracle every bit, whatever their summation order."""
+    rng = np.random.default_rng(seed)
+    blob = omlp.pack({name: rng.integers(-1, 2, size=shp) / 16.0 for name, shp in omlp.SHAPES})
+    x = rng.integers(-1, 2, size=(B, 192)).astype(np.float64)
+    y_o, _ = omlp.forward(blob, x)
+    t = np.zeros((B, 16))
+    t[:, :n_out] = y_o[:, :n_out] - rng.integers(-1, 2, size=(B, n_out)) / 4.0
+    return blob, x, t, y_o
+
+
+@pytest.mark.parametrize("B,n_out", [(64, 16), (128, 8)])
+def test_forward_and_backward_bit_exact_on_exact_operands(B, n_out):
+    require_gpu()
+    import torch
+    from paper_2110_04421_amd.mlp import MLP
+    blob, x, t, y_o = _exact_case(B, n_out, 3)
+    net = MLP(B, init=blob.astype(np.float32))
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y, y_o)
+    loss = float(net.backward(torch.from_numpy(t.astype(np.float32)).cuda(), n_out).cpu())
+    loss_o, g_o, _ = omlp.loss_and_backward(blob, x, t, n_out)
+    assert loss == loss_o
+    g = net.grads.cpu().numpy().astype(np.float64)
+    for k, v in omlp.unpack(g_o).items():
+        assert np.array_equal(omlp.unpack(g)[k], v), k

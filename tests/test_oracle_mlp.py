@@ -51,3 +51,45 @@ def test_overfits_a_tiny_set():
         first = loss if first is None else first
         blob, m, v = mlp.adam(blob, m, v, g, 1e-3, 0.9, 0.999, 1e-8, step)
     assert loss < 1e-3 * first
+
+
+def test_exact_operand_recipe_leaves_nothing_to_round():
+    """The operands of the GPU's bit-exact network test (inputs in {-1, 0, 1}, weights
+    and biases in {-1, 0, 1}/16, targets a quarter step from the output, B * n_out =
+    1024): every layer computed with FP32 accumulation in two different orders equals
+    the FP64 oracle exactly, so the test's claim of bit-exactness does not depend on the
+    kernels' summation order."""
+    for B, n_out in ((64, 16), (128, 8)):
+        rng = np.random.default_rng(3)
+        blob = mlp.pack({name: rng.integers(-1, 2, size=shp) / 16.0 for name, shp in mlp.SHAPES})
+        x = rng.integers(-1, 2, size=(B, 192)).astype(np.float64)
+        y, c = mlp.forward(blob, x)
+        t = np.zeros((B, 16))
+        t[:, :n_out] = y[:, :n_out] - rng.integers(-1, 2, size=(B, n_out)) / 4.0
+        loss, g, _ = mlp.loss_and_backward(blob, x, t, n_out)
+
+        def mm32(a, b, rev):
+            a32, b32 = np.asarray(a, np.float32), np.asarray(b, np.float32)
+            order = range(a32.shape[1] - 1, -1, -1) if rev else range(a32.shape[1])
+            acc = np.zeros((a32.shape[0], b32.shape[1]), np.float32)
+            for k in order:
+                acc += np.outer(a32[:, k], b32[k, :])
+            return acc.astype(np.float64)
+
+        W = c["W"]
+        for rev in (False, True):
+            h1 = mlp.bf16_round(np.maximum(mm32(c["x"], W["W1"].T, rev) + W["b1"], 0))
+            h2 = mlp.bf16_round(np.maximum(mm32(h1, W["W2"].T, rev) + W["b2"], 0))
+            y32 = mm32(h2, W["W3"].T, rev) + W["b3"]
+            assert np.array_equal(h1, c["h1"]) and np.array_equal(h2, c["h2"])
+            assert np.array_equal(y32, y)
+            dy = np.zeros_like(y)
+            dy[:, :n_out] = 2.0 * (y32[:, :n_out] - t[:, :n_out]) / (B * n_out)
+            dh2 = mm32(mlp.bf16_round(dy), W["W3"], rev) * (h2 > 0)
+            dh1 = mm32(mlp.bf16_round(dh2), W["W2"], rev) * (h1 > 0)
+            g32 = mlp.pack({"W3": mm32(mlp.bf16_round(dy).T, h2, rev), "b3": dy.sum(0),
+                             "W2": mm32(mlp.bf16_round(dh2).T, h1, rev), "b2": dh2.sum(0),
+                             "W1": mm32(mlp.bf16_round(dh1).T, c["x"], rev), "b1": dh1.sum(0)})
+            assert np.array_equal(g32, g)
+            assert np.array_equal(np.asarray(g32, np.float32).astype(np.float64), g32)
+        assert float(np.float32(loss)) == loss
