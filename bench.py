@@ -71,8 +71,8 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         "pb_hist2": 2.0 * C,                       # the 16-bit destination parts
         "pb_scatter2": 14.0 * C,                   # 6-byte entries in, 8-byte leaf entries out
         "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
-        "rowptr": 18.0 * N,
-        "pb_assemble": 4.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col out
+        "pb_tiles": 36.0 * nbt * 4,                # per tile: record, degree, two list starts, start out
+        "pb_assemble": 4.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col + row_ptr out
         # claim-based builder
         "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 4.0 * E + 8.0 * C + 24.0 * N,
         "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
@@ -85,7 +85,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
 
 
 KERNEL_SOURCES = {"message": "k_step.hip", "fused": "k_step.hip", "pre": "k_step.hip",
-                  "mask": "k_step.hip", "rowptr": "k_graph.hip", "pb_assemble": "k_build.hip",
+                  "mask": "k_step.hip", "pb_assemble": "k_build.hip", "pb_tiles": "k_build.hip",
                   "pb_gen": "k_build.hip", "pb_scatter1": "k_build.hip",
                   "pb_hist2": "k_build.hip", "pb_scatter2": "k_build.hip",
                   "pb_leaf": "k_build.hip", "pb_scan1": "k_build.hip"}

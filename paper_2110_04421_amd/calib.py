@@ -314,12 +314,16 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
         grids.append(("grid2d_matched", matched_grid2_thetas(n_train)))
     for name, gt in grids:
         t0 = time.perf_counter()
-        fits[name] = grid_fit(simulate_curves(p, pop, gt, seed=4, days=days, batch=batch), gt, c_ho)
+        if log:
+            log(f"grid search {name}: {gt.shape[0]} runs")
+        fits[name] = grid_fit(simulate_curves(p, pop, gt, seed=4, days=days, batch=batch, log=log), gt, c_ho)
         seconds[name + "_search"] = time.perf_counter() - t0
         runs[name] = int(gt.shape[0])
     th_mean = np.tile(th_tr.mean(0), (n_heldout, 1))
     fits["training_mean_params"] = th_mean
-    sim = lambda th, seed: simulate_curves(p, pop, th, seed=seed, days=days, batch=batch)
+    sim = lambda th, seed: simulate_curves(p, pop, th, seed=seed, days=days, batch=batch, log=log)
+    if log:
+        log("re-simulating every fit on the independent and the targets' own streams")
     e_ind = {k: rel_l2(sim(th, 3), c_ho) for k, th in list(fits.items()) + [("true_params", th_ho)]}
     e_crn = {k: rel_l2(sim(th, 2), c_ho) for k, th in fits.items()}
     unit = lambda th: float(np.sqrt(((to_unit(th) - to_unit(th_ho)) ** 2).mean()))
@@ -354,7 +358,7 @@ def run(n_train=50000, n_heldout=1000, n_agents=100_000, epochs=30, days=180, ba
                             theta=th)
         sub = {n_: th[:k] for n_, th in fits.items()}
         sub.update({n_: v["theta"] for n_, v in gd.items()})
-        e_sub = {n_: rel_l2(simulate_curves(p, pop, th, seed=2, days=days, batch=batch), c_ho[:k])
+        e_sub = {n_: rel_l2(simulate_curves(p, pop, th, seed=2, days=days, batch=batch, log=log), c_ho[:k])
                  for n_, th in sub.items()}
         summary["gradient_descent"] = dict(
             targets=k, iterations=gd_iters,

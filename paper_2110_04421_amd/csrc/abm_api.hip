@@ -100,7 +100,7 @@ struct Offsets {
       cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds, ring_rp, ring_col, den_mask, rmask, ninf, work, nwork;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
-      pb_b1w, pb_buf2, pb_rsrc, pb_rstart;
+      pb_b1w, pb_buf2, pb_rsrc, pb_rstart, pb_tdeg, pb_tstart, pb_tpart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
       gtheta, gpart, dL;
 };
@@ -464,6 +464,9 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_buf2 = L.take<uint2>(z.ccap);
     o.pb_rsrc = L.take<uint32_t>(z.ccap);
     o.pb_rstart = L.take<int32_t>(z.N + 1);
+    o.pb_tdeg = L.take<int32_t>(z.ntiles);
+    o.pb_tstart = L.take<int32_t>(z.ntiles);
+    o.pb_tpart = L.take<int64_t>((z.ntiles + TILE - 1) / TILE + 1);
   }
   if (p.mode == ABM_SOFT) {
     o.s = L.take<float>(z.N);
@@ -798,6 +801,10 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_sh = (int32_t)std::max<int64_t>(0, z.lb - 8);
     d.pb_rsrc = (uint32_t*)(ws + o.pb_rsrc);
     d.pb_rstart = (int32_t*)(ws + o.pb_rstart);
+    d.pb_tdeg = (int32_t*)(ws + o.pb_tdeg);
+    d.pb_tstart = (int32_t*)(ws + o.pb_tstart);
+    d.pb_tpart = (int64_t*)(ws + o.pb_tpart);
+    d.pb_ntgrp = (int32_t)((z.ntiles + TILE - 1) / TILE);
   }
   name_kernels(s);
 

@@ -164,6 +164,10 @@ struct Dev {
   int32_t pb_sh;
   uint32_t* pb_rsrc;        // [ccap] received initiators, sorted by (dest, network, initiator)
   int32_t* pb_rstart;       // [N + 1] first received entry of each destination; [N] = total
+  int32_t* pb_tdeg;         // [ntiles] household and own edges of a tile's rows
+  int32_t* pb_tstart;       // [ntiles] a tile's first edge within its group of 256 tiles
+  int64_t* pb_tpart;        // [ntiles / 256 + 1] first edge of each group; [last] = total
+  int32_t pb_ntgrp;         // groups of 256 tiles
 
   // soft mode
   float* s;            // susceptible mass [N]

@@ -17,10 +17,12 @@
 //   P5  leaf sort   per leaf, in LDS: counting sort by (destination, network), then each
 //                   (destination, network) run sorted by initiator; received counts and
 //                   the received-list start of every destination.
-//   row pointers    the prefix scan of k_graph.hip (scan1-3).
-//   P6  assemble    each row: household, own occupation draws, received occupation,
-//                   own random draws, received random; the own and received parts of
-//                   a tile are contiguous ranges, copied by all lanes together.
+//   S3  tiles       each tile's first edge: a scan of the tiles' edge totals (household
+//                   and own edges from P1, received entries from P5).
+//   P6  assemble    row pointers (the tile's degree scan after its first edge), then
+//                   each row: household, own occupation draws, received occupation, own
+//                   random draws, received random; the own and received parts of a tile
+//                   are contiguous ranges, copied by all lanes together.
 // Every run written in P2/P4 leaves as consecutive lanes on consecutive addresses, and
 // every random access of a per-edge scatter becomes an LDS access.
 #include "abm_internal.h"
@@ -129,7 +131,7 @@ __device__ __forceinline__ void put_b1(const Dev& d, int pos, uint32_t p, uint32
 __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_gen(Dev d) {
   extern __shared__ uint32_t stage[];        // [pb_bcap] draws, then [pb_bpw][nh2] histograms
   __shared__ uint32_t T[NPT * 64];
-  __shared__ int wsum[PB_THREADS / 64];
+  __shared__ int wsum[PB_THREADS / 64], wdeg[PB_THREADS / 64];
   __shared__ int ntot;
   // two 16-bit counters a word (a batch has at most pb_bcap <= 24576 draws)
   const int nh2 = (d.pb_nb1 + 1) >> 1;
@@ -175,16 +177,24 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       const int y = __shfl_up(inc, o);
       if (lane >= o) inc += y;
     }
+    // the row's household and own edges, summed over the tile for its first edge
+    int hd = live ? (int)sr.hh_n - 1 + c : 0;
+    for (int o = 32; o > 0; o >>= 1) hd += __shfl_xor(hd, o);
     if (lane == 63) wsum[wv] = inc;
+    if (lane == 0) wdeg[wv] = hd;
     __syncthreads();
     int wb = 0;
     for (int q = 0; q < wv; ++q) wb += wsum[q];
     const int off = wb + inc - c;
     if (tid == PB_THREADS - 1) ntot = wb + inc;
     if ((tid & (TILE - 1)) == 0 && tix < d.ntiles) {    // the tile's own-list range
-      int cnt = 0;
-      for (int q = wv; q < wv + TILE / 64; ++q) cnt += wsum[q];
+      int cnt = 0, dg = 0;
+      for (int q = wv; q < wv + TILE / 64; ++q) {
+        cnt += wsum[q];
+        dg += wdeg[q];
+      }
       d.pb_tbase[tix] = make_int2(off, cnt);
+      d.pb_tdeg[tix] = dg;
     }
     __syncthreads();
     const int n = ntot;
@@ -750,6 +760,33 @@ __global__ __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // holds the source id with the network in the top two bits; the tile's edge range is
 // written with consecutive lanes on consecutive addresses.  A tile with more edges
 // than the LDS room writes directly.
+// The tile's first edge: a tile's edges are its rows' household and own edges (summed
+// by the generation pass) and its received entries (the span of its rows' received
+// lists); k_pb_tsum scans them within groups of 256 tiles and k_pb_parts scans the
+// groups, so the row pointers come from about N/256 values, not from N degrees.
+__global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
+  __shared__ int wsum[TILE / 64];
+  if (*d.flags) return;
+  const int t = blockIdx.x * TILE + (int)threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int v = 0;
+  if (t < d.ntiles) {
+    const int4 tl = d.tiles[t];
+    v = d.pb_tdeg[t] + d.pb_rstart[tl.z] - d.pb_rstart[tl.y];
+  }
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int q = 0; q < wv; ++q) wb += wsum[q];
+  if (t < d.ntiles) d.pb_tstart[t] = wb + inc - v;
+  if (threadIdx.x == TILE - 1) d.pb_tpart[blockIdx.x] = (int64_t)(wb + inc);
+}
+
 __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   extern __shared__ int32_t scol[];                  // [pb_asm_cap] staged row, then [pb_asm_cap] u16 positions
   __shared__ int wsum[TILE / 64];
@@ -764,6 +801,7 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   const int g0 = d.pb_rstart[tl.y], g1 = d.pb_rstart[tl.z];
   const int oend = tb.y;
   const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + tb.x;
+  const int64_t b64 = d.pb_tpart[tix >> 8] + d.pb_tstart[tix];
   int ov[PB_UNROLL], rv[PB_UNROLL];
 #pragma unroll
   for (int u = 0; u < PB_UNROLL; ++u) {
@@ -771,17 +809,43 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     ov[u] = k < oend ? (int)ob[k] : 0;
     rv[u] = g0 + k < g1 ? (int)d.pb_rsrc[g0 + k] : 0;
   }
-  const int base = d.row_ptr[tl.y], end = d.row_ptr[tl.z];
-  const bool staged = end - base <= cap;
   const int i = tl.y + threadIdx.x;
   const bool live = i < tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int ko = 0, kr = 0;
+  int ko = 0, kr = 0, deg = 0;
+  StaticRec sr{};
+  uint32_t rcv = 0u;
   if (live) {
     const uint32_t o = d.own[i];
     ko = (int)(o & 0xFFu);
     kr = (int)(o >> 8);
+    sr = d.srec[i];
+    rcv = d.recv[i];
+    deg = (int)sr.hh_n - 1 + ko + kr + (int)(rcv >> 16) + (int)(rcv & 0xFFFFu);
   }
+  // the rows' degrees, scanned in the tile, after the tile's first edge
+  int dinc = deg;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(dinc, o);
+    if (lane >= o) dinc += y;
+  }
+  if (lane == 63) wsum[wv] = dinc;
+  __syncthreads();
+  int dwb = 0, dtot = 0;
+  for (int q = 0; q < TILE / 64; ++q) {
+    if (q < wv) dwb += wsum[q];
+    dtot += wsum[q];
+  }
+  if (b64 + dtot > d.ecap) {                         // the same for every lane
+    if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
+    return;
+  }
+  if (tix == d.ntiles - 1 && threadIdx.x == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
+  __syncthreads();                                   // wsum is free again
+  const int base = (int)b64, end = base + dtot;
+  const int rp0 = base + dwb + dinc - deg;           // this row's first edge
+  if (live) d.row_ptr[i] = rp0;
+  const bool staged = end - base <= cap;
   const int c = ko + kr;
   int inc = c;
   for (int o = 1; o < 64; o <<= 1) {
@@ -795,11 +859,10 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   // each row's lane writes its household part and, for every entry of its own and
   // received lists, that entry's position in the tile (network in the top bits)
   if (live) {
-    const StaticRec sr = d.srec[i];
-    const uint32_t r = d.recv[i];
+    const uint32_t r = rcv;
     const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
     const int rs = d.pb_rstart[i] - g0;
-    int pos = d.row_ptr[i];
+    int pos = rp0;
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
       if (m != i) {
         if (staged) scol[pos - base] = m;
@@ -873,7 +936,7 @@ int build_steps(const Dev& d) { return d.pb_on ? 8 : 5; }
 
 const char* build_step_name(const Dev& d, int k) {
   static const char* pb[8] = {"pb_gen", "pb_scan1", "pb_scatter1", "pb_hist2",
-                              "pb_scatter2", "pb_leaf", "rowptr", "pb_assemble"};
+                              "pb_scatter2", "pb_leaf", "pb_tiles", "pb_assemble"};
   static const char* cl[5] = {"clear", "count", "scan", "fill", "canon"};
   return d.pb_on ? pb[k] : cl[k];
 }
@@ -926,7 +989,10 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       else
         hipLaunchKernelGGL(k_pb_leaf<512>, dim3(d.pb_nleaf), dim3(512), leaf_lds(d), s, d);
       break;
-    case 6: launch_scan(d, s); break;
+    case 6:
+      hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
+      break;
     default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
   }
 }
