@@ -41,15 +41,12 @@ def household_edges(pop) -> int:
     return int((s * (s - 1)).sum())
 
 
-def leaf_bits(N: int, C: float) -> int:
-    """Leaf size exponent of the partitioned builder (same rule as the library)."""
-    rbar = max(C / N, 0.5)
-    lb = min(11, max(6, int(np.floor(np.log2(6000.0 / rbar)))))
-    while lb < 11 and -(-N // (1 << (lb + 8))) > 1024:
-        lb += 1
-    while lb > 6 and (N >> lb) < 1024 and -(-N // (1 << (lb + 7))) <= 1024:
-        lb -= 1
-    return lb
+def level1_buckets(N: int) -> int:
+    """Level-1 buckets of the partitioned builder (same rule as the library, one
+    replicate): destinations are numbered by tile slot, leaves are tiles of 256."""
+    slots = -(-N // 256) * 256
+    nb1 = lambda l2: -(-slots // (1 << (l2 + 8)))
+    return nb1(9) if nb1(8) > 512 else nb1(8)
 
 
 def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float = None) -> float:
@@ -57,8 +54,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
     the day, Einf = those with an infectious source, C = contacts drawn (each gives two
     edges), N = agents."""
     Einf = E if Einf is None else Einf
-    lb = leaf_bits(N, C)
-    nbt, nb1 = -(-N // 1024), -(-N // (1 << (lb + 8)))
+    nbt, nb1 = -(-N // 1024), level1_buckets(N)
     table = {
         # force of infection: col (source and network) + 1 mask bit per edge, a code
         # byte per infectious edge; row_ptr, age, lambda per row
@@ -70,9 +66,9 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         "pb_scatter1": 2.0 * N + 10.0 * C,         # counts and own list in, 6-byte entries out
         "pb_hist2": 2.0 * C,                       # the 16-bit destination parts
         "pb_scatter2": 14.0 * C,                   # 6-byte entries in, 8-byte leaf entries out
-        "pb_leaf": 12.0 * C + 8.0 * N,             # entries in, sorted initiators + counts out
-        "pb_tiles": 36.0 * nbt * 4,                # per tile: record, degree, two list starts, start out
-        "pb_assemble": 4.0 * E + 8.0 * C + 30.0 * N,   # own + received lists in, col + row_ptr out
+        "pb_tiles": 16.0 * nbt * 4,                # per tile: degree and leaf bounds in, start out
+        # leaf entries, own list, counts and static records in; col and row_ptr out
+        "pb_rows": 4.0 * E + 12.0 * C + 22.0 * N,
         # claim-based builder
         "count": 18.0 * N + 8.0 * C, "scan": 26.0 * N, "fill": 4.0 * E + 8.0 * C + 24.0 * N,
         "canon": 11.0 * N + 8.0 * C, "clear": 4.0 * N,
@@ -85,10 +81,10 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
 
 
 KERNEL_SOURCES = {"message": "k_step.hip", "fused": "k_step.hip", "pre": "k_step.hip",
-                  "mask": "k_step.hip", "pb_assemble": "k_build.hip", "pb_tiles": "k_build.hip",
+                  "mask": "k_step.hip", "pb_rows": "k_build.hip", "pb_tiles": "k_build.hip",
                   "pb_gen": "k_build.hip", "pb_scatter1": "k_build.hip",
                   "pb_hist2": "k_build.hip", "pb_scatter2": "k_build.hip",
-                  "pb_leaf": "k_build.hip", "pb_scan1": "k_build.hip"}
+                  "pb_scan1": "k_build.hip"}
 
 
 def source_sha(kernel: str):

@@ -118,10 +118,11 @@ enum {
 #define ABM_FLAG_STRAIGHT_THROUGH 128 /* relaxed mode: the forward pass takes the hard
                                       infection draw (the relaxed sample's sign) and the
                                       adjoint the relaxed sample's derivative            */
-#define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's leaf sort and row
-                                    assembly their smallest LDS room, so that leaves are
-                                    sorted in several groups and tiles are written
-                                    directly; the graph is bitwise the same             */
+#define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's level-1 scatter
+                                    and row pass their smallest LDS and register room,
+                                    so that batches and tiles are written directly and
+                                    received entries are read twice; the graph is
+                                    bitwise the same                                    */
 
 /* Model parameters; copied at create.  Section 3 eq. 1: lambda = R * S_a * A_s * B_n /
  * Ibar * integral of the Gamma infectiousness density over the day. */

@@ -100,7 +100,7 @@ struct Offsets {
       cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds, ring_rp, ring_col, den_mask, rmask, ninf, work, nwork;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
-      pb_b1w, pb_buf2, pb_rsrc, pb_rstart, pb_tdeg, pb_tstart, pb_tpart;
+      pb_b1w, pb_buf2, pb_tdeg, pb_tstart, pb_tpart;
   size_t s, ehist, inf, sigma, soft_inc, seg_sigma, seg_y, seg_s, ckpt, s_bar, ibar, vtmp, lam_bar,
       gtheta, gpart, dL;
 };
@@ -109,8 +109,8 @@ struct Sizes {
   int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
-  int64_t pb_on = 0, lb = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
-  int64_t leaf_cap = 0, asm_cap = 0, s1_cap = PB_S1_CAP;
+  int64_t pb_on = 0, l2 = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
+  int64_t asm_cap = 0, s1_cap = PB_S1_CAP, rper = 12;
   int64_t fseg = 1;
 };
 
@@ -327,12 +327,20 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
     hh_edges += s * (s - 1);
   }
   std::vector<uint16_t> wpn(N, 0);
-  for (int w = 0; w < pop->n_workplaces; ++w)
+  // replicates are separate populations: a workplace's members share one (the graph
+  // builder numbers a partner within its initiator's replicate)
+  const int64_t* ao = pop->agent_offset;
+  auto rep_of = [&](int64_t a) { return (int64_t)(std::upper_bound(ao, ao + R + 1, a) - ao) - 1; };
+  for (int w = 0; w < pop->n_workplaces; ++w) {
+    int64_t rw = -1;
     for (int64_t q = pop->wp_start[w]; q < pop->wp_start[w + 1]; ++q) {
       const int64_t a = pop->wp_members[q];
       if (a < 0 || a >= N) return bad("workplace member out of range");
+      if (q == pop->wp_start[w]) rw = rep_of(a);
+      else if (a < ao[rw] || a >= ao[rw + 1]) return bad("workplace crosses a replicate boundary");
       wpn[a] = (uint16_t)(pop->wp_start[w + 1] - pop->wp_start[w]);
     }
+  }
   double cmean = 0;
   for (int r = 0; r < R; ++r) {
     const int64_t lo = pop->agent_offset[r], hi = pop->agent_offset[r + 1];
@@ -349,25 +357,17 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
     return ABM_E_CAPACITY;
   }
   z.ecap = (int64_t)ecap;
-  // partitioned builder geometry: leaves of 2^lb destinations holding a few thousand
-  // received entries, at most 1024 level-1 buckets of 256 leaves
   // room for the day's contacts: at least what the edge room leaves after the household
   // edges (each contact is two edges), so that a larger edge_capacity enlarges both
   z.ccap = (int64_t)std::ceil(std::max(cmean + 8.0 * std::sqrt(cmean), (ecap - hh_edges) / 2.0) + 4096.0);
-  const double rbar = cmean / (double)N;
-  int lb = (int)std::floor(std::log2(6000.0 / std::max(rbar, 0.5)));
-  lb = std::min(11, std::max(6, lb));
-  auto nb1_of = [&](int b) { return (N + ((int64_t)1 << (b + 8)) - 1) >> (b + 8); };
-  while (lb < 11 && nb1_of(lb) > 1024) ++lb;
-  // small populations: smaller leaves, so that there are enough of them to fill the GPU
-  while (lb > 6 && (N >> lb) < 1024 && nb1_of(lb - 1) <= 1024) --lb;
-  z.lb = lb;
-  z.nb1 = nb1_of(lb);
-  // a leaf holds about rbar * 2^lb entries; its LDS room is 1.25x that (+512).  A
-  // larger leaf is sorted in several groups of destinations, so the room only bounds
-  // occupancy, not correctness.
-  const double leaf_mean = rbar * (double)((int64_t)1 << lb);
-  z.leaf_cap = std::max<int64_t>(1024, std::min<int64_t>(24576, ((int64_t)(1.25 * leaf_mean) + 512 + 255) / 256 * 256));
+  // partitioned builder geometry: destinations numbered by tile slot, leaves of 256
+  // slots (one tile each), level-1 buckets of 2^(8 + l2) slots; l2 = 9 only where 256
+  // leaves a bucket would make more than 512 buckets
+  const int64_t slots = z.ntiles * TILE;
+  auto nb1_of = [&](int l2) { return (slots + ((int64_t)1 << (l2 + 8)) - 1) >> (l2 + 8); };
+  const int l2 = nb1_of(8) > 512 ? 9 : 8;
+  z.l2 = l2;
+  z.nb1 = nb1_of(l2);
   // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048);
   // the generation pass stages a batch in LDS, so more than 24576 draws (high contact
   // means) take the claim builder
@@ -376,15 +376,15 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   for (int k = 0; k < ABM_N_AGE; ++k) mr = std::max(mr, p->mu_random[k] / 2.0);
   z.bcap = ((int64_t)(1.3 * 1024.0 * (mo + mr)) + 2048 + 255) / 256 * 256;
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
-            leaf_mean <= 4.0 * 24576.0 && z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
+            z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
             N < ((int64_t)1 << 27);   // initiators fit the 27 low bits of a partition word
   // edges of a tile staged in LDS by the row assembly: 1.1x the mean (+512)
   const double tile_mean = emean * (double)TILE / (double)N;
   z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.1 * tile_mean) + 512 + 255) / 256 * 256));
   if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {
-    z.leaf_cap = 1024;
     z.asm_cap = 2048;
     z.s1_cap = 0;
+    z.rper = 1;
   }
   z.nbatch = (z.ntiles + 3) / 4;
   // batches per generation / level-1 workgroup: up to 16, keeping >= 1024 workgroups
@@ -394,7 +394,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.ngrid = (z.nbatch + z.bpw - 1) / z.bpw;
   z.s1_nparts = (z.nb1 * z.nbatch + SCAN_BLOCK - 1) / SCAN_BLOCK;
   z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
-  z.nleaf = (N + ((int64_t)1 << lb) - 1) >> lb;
+  z.nleaf = z.nb1 << z.l2;
   if (p->mode == ABM_SOFT) {
     z.seg = p->checkpoint_every;
     z.nckpt = (z.T + z.seg - 1) / z.seg + 1;
@@ -457,13 +457,11 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
     o.pb_nchunks = L.take<int32_t>(1);
     o.pb_chunks = L.take<int4>(z.maxch);
-    o.pb_hist2 = L.take<int32_t>(z.maxch * 256);
-    o.pb_leaf = L.take<int32_t>(z.nb1 * 256 + 1);
+    o.pb_hist2 = L.take<int32_t>(z.maxch << z.l2);
+    o.pb_leaf = L.take<int32_t>(z.nleaf + 1);
     o.pb_b1h = L.take<uint16_t>(z.ccap);
     o.pb_b1w = L.take<uint32_t>(z.ccap);
     o.pb_buf2 = L.take<uint2>(z.ccap);
-    o.pb_rsrc = L.take<uint32_t>(z.ccap);
-    o.pb_rstart = L.take<int32_t>(z.N + 1);
     o.pb_tdeg = L.take<int32_t>(z.ntiles);
     o.pb_tstart = L.take<int32_t>(z.ntiles);
     o.pb_tpart = L.take<int64_t>((z.ntiles + TILE - 1) / TILE + 1);
@@ -772,7 +770,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.msg_shape = 0;
   d.pb_on = (int32_t)z.pb_on;
   if (z.pb_on) {
-    d.pb_lb = (int32_t)z.lb;
+    d.pb_l2 = (int32_t)z.l2;
     d.pb_nb1 = (int32_t)z.nb1;
     d.pb_nbatch = (int32_t)z.nbatch;
     d.pb_bpw = (int32_t)z.bpw;
@@ -781,7 +779,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_s1_nparts = (int32_t)z.s1_nparts;
     d.pb_maxch = (int32_t)z.maxch;
     d.pb_nleaf = (int32_t)z.nleaf;
-    d.pb_leaf_cap = (int32_t)z.leaf_cap;
+    d.pb_rper = (int32_t)z.rper;
     d.pb_asm_cap = (int32_t)z.asm_cap;
     d.pb_s1_cap = (int32_t)z.s1_cap;
     d.pb_ccap = z.ccap;
@@ -798,9 +796,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_b1h = (uint16_t*)(ws + o.pb_b1h);
     d.pb_b1w = (uint32_t*)(ws + o.pb_b1w);
     d.pb_buf2 = (uint2*)(ws + o.pb_buf2);
-    d.pb_sh = (int32_t)std::max<int64_t>(0, z.lb - 8);
-    d.pb_rsrc = (uint32_t*)(ws + o.pb_rsrc);
-    d.pb_rstart = (int32_t*)(ws + o.pb_rstart);
+    d.pb_sh = (int32_t)(z.l2 - 8);
     d.pb_tdeg = (int32_t*)(ws + o.pb_tdeg);
     d.pb_tstart = (int32_t*)(ws + o.pb_tstart);
     d.pb_tpart = (int64_t*)(ws + o.pb_tpart);

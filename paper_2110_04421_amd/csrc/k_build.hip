@@ -1,28 +1,27 @@
 // Daily contact graph, partitioned builder.  Same CSR, same canonical order as the
 // claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
-// global atomics and without random 4-byte scatters:
+// global atomics and without random 4-byte scatters.  Destinations are numbered by tile
+// slot (tile * 256 + row in the tile), so that the last level of the partition, a leaf
+// of 256 slots, is one tile of rows:
 //
 //   P1  gen         per batch of 4 tiles: draw every agent's contacts once (Philox, and
-//                   the workplace-member loads), store them in agent order in the
-//                   batch's own list, keep the agent's counts, histogram the partners
-//                   by level-1 digit (dest >> (LB + 8)).
+//                   the workplace-member loads), store the partners' slots in agent
+//                   order in the batch's own list, keep the agent's counts and each
+//                   tile's household + own edge count, histogram the partners by
+//                   level-1 digit (slot >> (8 + l2)).
 //   S1  scan        digit-major exclusive scan of the histograms -> each (digit, batch)
 //                   run's offset; level-1 bucket bounds; chunk table.
 //   P2  scatter-1   read the batch's own list, counting-sort its entries
-//                   (dest, src | net) by digit in LDS, write each run contiguously
-//                   as 6-byte entries (16-bit destination part, 32-bit source word).
-//   P3  hist-2      per chunk of a level-1 bucket: histogram by level-2 digit.
-//   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
-//   P4  scatter-2   entries into leaves of 2^LB destinations.
-//   P5  leaf sort   per leaf, in LDS: counting sort by (destination, network), then each
-//                   (destination, network) run sorted by initiator; received counts and
-//                   the received-list start of every destination.
-//   S3  tiles       each tile's first edge: a scan of the tiles' edge totals (household
-//                   and own edges from P1, received entries from P5).
-//   P6  assemble    row pointers (the tile's degree scan after its first edge), then
-//                   each row: household, own occupation draws, received occupation, own
-//                   random draws, received random; the own and received parts of a tile
-//                   are contiguous ranges, copied by all lanes together.
+//                   (slot, src | net) by digit in LDS, write each run contiguously
+//                   as 6-byte entries (16-bit slot part, 32-bit source word).
+//   P3  hist-2      per chunk of a level-1 bucket: histogram by leaf digit (l2 bits).
+//   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf (= tile) bounds.
+//   P4  scatter-2   entries into leaves.
+//   S3  tiles       each tile's first edge: a scan of the tiles' edge totals.
+//   P5  rows        per tile: count the leaf per (row, network), row pointers, then each
+//                   row: household, own occupation draws, received occupation, own
+//                   random draws, received random, the received runs sorted by
+//                   initiator in LDS.
 // Every run written in P2/P4 leaves as consecutive lanes on consecutive addresses, and
 // every random access of a per-edge scatter becomes an LDS access.
 #include "abm_internal.h"
@@ -113,9 +112,9 @@ __device__ __forceinline__ StaticRec load_srec_nt(const StaticRec* p) {
   return r;
 }
 
-// Level-1 partition entry of (destination p, initiator | network << 31).
+// Level-1 partition entry of (destination slot p, initiator | network << 31).
 __device__ __forceinline__ void put_b1(const Dev& d, int pos, uint32_t p, uint32_t w) {
-  const uint32_t dib = p & ((1u << (d.pb_lb + 8)) - 1u);
+  const uint32_t dib = p & ((1u << (d.pb_l2 + 8)) - 1u);
   d.pb_b1h[pos] = (uint16_t)(dib >> d.pb_sh);
   d.pb_b1w[pos] = w | ((dib & ((1u << d.pb_sh) - 1u)) << 27);
 }
@@ -140,7 +139,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   for (int k = threadIdx.x; k < d.pb_bpw * nh2; k += PB_THREADS) hist[k] = 0u;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
-  const int s1 = d.pb_lb + 8;
+  const int s1 = d.pb_l2 + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = 0; j < d.pb_bpw; ++j) {
     const int bt = blockIdx.x * d.pb_bpw + j;
@@ -209,14 +208,18 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       go.blk = bo;
       Gen gr = gen_rand(d, ri, loc, t);
       gr.blk = br;
+      // partners are kept as tile slots (a partner is in its initiator's replicate)
+      const int dl = (ri.tile0 << 8) - ri.start;
       go.each(d, ko, [&](int q, int p) {
-        stage[off + q - 1] = (uint32_t)p;
-        const int dg = p >> s1;
+        const int sl = p + dl;
+        stage[off + q - 1] = (uint32_t)sl;
+        const int dg = sl >> s1;
         atomicAdd(&h[dg >> 1], 1u << (16 * (dg & 1)));
       });
       gr.each(d, kr, [&](int q, int p) {
-        stage[off + ko + q - 1] = (uint32_t)p;
-        const int dg = p >> s1;
+        const int sl = p + dl;
+        stage[off + ko + q - 1] = (uint32_t)sl;
+        const int dg = sl >> s1;
         atomicAdd(&h[dg >> 1], 1u << (16 * (dg & 1)));
       });
     }
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
 // for each of its entries.  Entries are counting-sorted by digit into
 // LDS and each run leaves as consecutive lanes on consecutive addresses; a batch with
 // more than PB_S1_CAP entries writes each entry directly to its run.  The order inside
-// a run is immaterial: the leaf sort orders fully.  The next batch's agent counts and
+// a run is immaterial: the row pass orders fully.  The next batch's agent counts and
 // the first rounds of its own list are loaded while the current batch is placed.
 constexpr int PB_S1_PF = 10;           // own-list entries a lane loads for the next batch
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
   __shared__ int nstage;
   if (*d.flags) return;
-  const int s1 = d.pb_lb + 8;
+  const int s1 = d.pb_l2 + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
   const int bt0 = blockIdx.x * d.pb_bpw;
@@ -497,12 +500,14 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
 }
 
 // ---- P3: level-2 histograms per chunk -----------------------------------------------
+constexpr int PB_L2_MAX = 512;         // leaves per level-1 bucket (2^l2)
 __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
-  __shared__ int hist[256];
+  __shared__ int hist[PB_L2_MAX];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
-  hist[threadIdx.x] = 0;
+  const int nd = 1 << d.pb_l2, d2s = 8 - d.pb_sh;    // leaf digit = b1h >> d2s
+  for (int k = threadIdx.x; k < nd; k += TILE) hist[k] = 0;
   __syncthreads();
   const int4 ch = d.pb_chunks[c];
   for (int eb = ch.y; eb < ch.z; eb += TILE * PB_UNROLL) {
@@ -514,10 +519,10 @@ __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u)
-      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> (d.pb_lb - d.pb_sh)) & 255u], 1);
+      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> d2s) & (nd - 1)], 1);
   }
   __syncthreads();
-  d.pb_hist2[(size_t)c * 256 + threadIdx.x] = hist[threadIdx.x];
+  for (int k = threadIdx.x; k < nd; k += TILE) d.pb_hist2[((size_t)c << d.pb_l2) + k] = hist[k];
 }
 
 // ---- S2: per bucket, digit-major exclusive scan of its chunks' histograms ------------
@@ -528,14 +533,15 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
   const int b = blockIdx.x;
   const int c0 = d.pb_bchunk[b], nc = d.pb_bchunk[b + 1] - c0;
   const int base = d.pb_bstart[b];
+  const int l2 = d.pb_l2, nd = 1 << l2;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  const int n = 256 * nc;
+  const int n = nd * nc;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int q0 = 0; q0 < n; q0 += TILE) {
     const int q = q0 + threadIdx.x;
     const int dg = nc ? q / nc : 0, cc = nc ? q % nc : 0;
-    const int v = q < n ? d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] : 0;
+    const int v = q < n ? d.pb_hist2[((size_t)(c0 + cc) << l2) + dg] : 0;
     int inc = v;
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(inc, o);
@@ -547,37 +553,37 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
     for (int k = 0; k < wv; ++k) wb += wsum[k];
     const int ex = carry + wb + inc - v;
     if (q < n) {
-      d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] = base + ex;
-      if (cc == 0) d.pb_leaf[(size_t)b * 256 + dg] = base + ex;
+      d.pb_hist2[((size_t)(c0 + cc) << l2) + dg] = base + ex;
+      if (cc == 0) d.pb_leaf[((size_t)b << l2) + dg] = base + ex;
     }
     __syncthreads();
     if (threadIdx.x == TILE - 1) carry += wb + inc;
     __syncthreads();
   }
   if (nc == 0)
-    for (int dg = threadIdx.x; dg < 256; dg += TILE) d.pb_leaf[(size_t)b * 256 + dg] = base;
-  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 * 256] = d.pb_bstart[d.pb_nb1];
+    for (int dg = threadIdx.x; dg < nd; dg += TILE) d.pb_leaf[((size_t)b << l2) + dg] = base;
+  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 << l2] = d.pb_bstart[d.pb_nb1];
 }
 
-// ---- P4: scatter into leaves ---------------------------------------------------------
+// ---- P4: scatter into leaves (tiles) -------------------------------------------------
 // The chunk is read once into registers (PB_S2_PER entries a lane), counting-sorted by
 // leaf digit in LDS, and each leaf's part of the chunk leaves as one contiguous run of
-// consecutive lanes.  The order inside a run is immaterial: the leaf sort orders fully.
+// consecutive lanes.  The order inside a run is immaterial: the row pass orders fully.
 constexpr int PB_S2_THREADS = 1024;
 constexpr int PB_S2_PER = PB_CHUNK / PB_S2_THREADS;
 __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
   __shared__ uint2 sorted[PB_CHUNK];
-  __shared__ int cnt[256], first[256];
-  __shared__ int wsum[4];
+  __shared__ int cnt[PB_L2_MAX], first[PB_L2_MAX];
+  __shared__ int wsum[PB_L2_MAX / 64];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
   const int4 ch = d.pb_chunks[c];
   const int n = ch.z - ch.y;
   const int tid = threadIdx.x;
-  if (tid < 256) cnt[tid] = 0;
+  const int nd = 1 << d.pb_l2, d2s = 8 - d.pb_sh;   // leaf digit = b1h >> d2s
+  if (tid < nd) cnt[tid] = 0;
   __syncthreads();
-  const int d2s = d.pb_lb - d.pb_sh;          // level-2 digit = (b1h >> d2s) & 255
   uint2 x[PB_S2_PER];                         // (b1h, b1w)
   int rank[PB_S2_PER];
 #pragma unroll
@@ -588,18 +594,18 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d2s) & 255u], 1) : 0;
+    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d2s) & (nd - 1)], 1) : 0;
   }
   __syncthreads();
-  const int v = tid < 256 ? cnt[tid] : 0;
+  const int v = tid < nd ? cnt[tid] : 0;
   int inc = v;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(inc, o);
     if ((tid & 63) >= o) inc += y;
   }
-  if (tid < 256 && (tid & 63) == 63) wsum[tid >> 6] = inc;
+  if (tid < nd && (tid & 63) == 63) wsum[tid >> 6] = inc;
   __syncthreads();
-  if (tid < 256) {
+  if (tid < nd) {
     int wb = 0;
     for (int q = 0; q < (tid >> 6); ++q) wb += wsum[q];
     first[tid] = wb + inc - v;
@@ -608,172 +614,30 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    if (k < n) sorted[first[(x[j].x >> d2s) & 255u] + rank[j]] = x[j];
+    if (k < n) sorted[first[(x[j].x >> d2s) & (nd - 1)] + rank[j]] = x[j];
   }
   __syncthreads();
-  const int* off = d.pb_hist2 + (size_t)c * 256;
-  const uint32_t lmask = (1u << d.pb_sh) - 1u, dmask = (1u << d.pb_lb) - 1u;
+  const int* off = d.pb_hist2 + ((size_t)c << d.pb_l2);
+  const uint32_t lmask = (1u << d.pb_sh) - 1u;
   for (int k = tid; k < n; k += PB_S2_THREADS) {
     const uint2 y = sorted[k];
-    const int dg = (y.x >> d2s) & 255u;
+    const int dg = (y.x >> d2s) & (nd - 1);
     const int pos = off[dg] + (k - first[dg]);
     const uint32_t dib = (y.x << d.pb_sh) | ((y.y >> 27) & lmask);
-    d.pb_buf2[pos] = make_uint2((dib & dmask) | ((y.y >> 31) << 15), y.y & 0x07FFFFFFu);
+    d.pb_buf2[pos] = make_uint2((dib & 255u) | ((y.y >> 31) << 15), y.y & 0x07FFFFFFu);
   }
 }
 
-// ---- P5: per leaf, sort by (destination, network, initiator) in LDS ------------------
-// A lane keeps up to PB_LEAF_PER of the leaf's entries in registers, so the leaf is
-// read once (entries beyond LT * PB_LEAF_PER are read again from memory).
-// The LDS holds pb_leaf_cap entries.  A larger leaf is sorted in groups of whole keys
-// that each fit; only a single (destination, network) run longer than the cap is an
-// error.
-// Leaves whose mean size (the LDS room is 1.25x the mean + 512) exceeds what 512 lanes
-// hold in registers take 1024 lanes; smaller ones are faster with 512.
-constexpr int PB_LEAF_PER = 12;
-template <int LT>
-__global__ __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_leaf(Dev d) {
-  extern __shared__ uint32_t lds[];
-  if (*d.flags) return;
-  const int L = blockIdx.x;
-  const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
-  const int n = hi - lo;
-  const int cap = d.pb_leaf_cap;
-  const int nkeys = 2 << d.pb_lb;             // (destination offset, network)
-  uint32_t* sorted = lds;                     // [cap]
-  int* cnt = (int*)(lds + cap);               // [nkeys + 1]
-  __shared__ int wsum[LT / 64];
-  __shared__ int carry, grp_end;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int k = tid; k <= nkeys; k += LT) cnt[k] = 0;
-  __syncthreads();
-  const uint32_t dmask = (1u << d.pb_lb) - 1u;
-  // x = (destination within the leaf | network << 15, initiator)
-  auto key = [&](const uint2& v) { return (int)(((v.x & dmask) << 1) | (v.x >> 15)); };
-  uint2 x[PB_LEAF_PER];
-#pragma unroll
-  for (int j = 0; j < PB_LEAF_PER; ++j) {
-    const int e = lo + j * LT + tid;
-    x[j] = e < hi ? d.pb_buf2[e] : make_uint2(0u, 0u);
-  }
-#pragma unroll
-  for (int j = 0; j < PB_LEAF_PER; ++j)
-    if (lo + j * LT + tid < hi) atomicAdd(&cnt[key(x[j])], 1);
-  for (int e = lo + PB_LEAF_PER * LT + tid; e < hi; e += LT) atomicAdd(&cnt[key(d.pb_buf2[e])], 1);
-  __syncthreads();
-  // per-destination received counts (before the counts become offsets)
-  const int dest0 = L << d.pb_lb;
-  for (int k = tid; k <= (int)dmask; k += LT) {
-    const int dest = dest0 + k;
-    if (dest < d.N) {
-      const int co = cnt[2 * k], cr = cnt[2 * k + 1];
-      if (co > 0xFFFE || cr > 0xFFFE) atomicOr(d.flags, FLAG_RECV_OVERFLOW);
-      d.recv[dest] = ((uint32_t)co << 16) | (uint32_t)cr;
-    }
-  }
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int k0 = 0; k0 < nkeys; k0 += LT) {
-    const int k = k0 + tid;
-    const int v = k < nkeys ? cnt[k] : 0;
-    int inc = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    int wb = 0;
-    for (int q = 0; q < wv; ++q) wb += wsum[q];
-    if (k < nkeys) {
-      cnt[k] = carry + wb + inc - v;
-      if ((k & 1) == 0 && dest0 + (k >> 1) < d.N) d.pb_rstart[dest0 + (k >> 1)] = lo + carry + wb + inc - v;
-    }
-    __syncthreads();
-    if (tid == LT - 1) carry += wb + inc;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    cnt[nkeys] = n;
-    if (L == d.pb_nleaf - 1) d.pb_rstart[d.N] = hi;   // end of the last destination's list
-  }
-  __syncthreads();
-  // cnt[k] is the start of run k; placing run k's entries advances cnt[k] to its end,
-  // which is the start of run k + 1, so after a group run k is [cnt[k-1], cnt[k]).
-  for (int ka = 0; ka < nkeys;) {
-    const int o_lo = cnt[ka];
-    if (tid == 0) {
-      int a = ka, b = nkeys;                  // largest kb with cnt[kb] - o_lo <= cap
-      while (a < b) {
-        const int m = (a + b + 1) >> 1;
-        if (cnt[m] - o_lo <= cap) a = m; else b = m - 1;
-      }
-      grp_end = a;
-    }
-    __syncthreads();
-    const int kb = grp_end;
-    if (kb == ka) {                           // one run longer than the LDS
-      if (tid == 0) atomicOr(d.flags, FLAG_CAPACITY);
-      return;
-    }
-    const int o_hi = cnt[kb];
-    __syncthreads();                          // everyone has read cnt[ka] before placement
-#pragma unroll
-    for (int j = 0; j < PB_LEAF_PER; ++j) {
-      const int k = key(x[j]);
-      if (lo + j * LT + tid < hi && k >= ka && k < kb)
-        sorted[atomicAdd(&cnt[k], 1) - o_lo] = x[j].y;
-    }
-    for (int e = lo + PB_LEAF_PER * LT + tid; e < hi; e += LT) {
-      const uint2 v = d.pb_buf2[e];
-      const int k = key(v);
-      if (k >= ka && k < kb) sorted[atomicAdd(&cnt[k], 1) - o_lo] = v.y;
-    }
-    __syncthreads();
-    for (int k = ka + tid; k < kb; k += LT) {
-      const int a = (k > ka ? cnt[k - 1] : o_lo) - o_lo, b = cnt[k] - o_lo;
-      for (int y0 = a + 1; y0 < b; ++y0) {
-        const uint32_t v = sorted[y0];
-        int y = y0 - 1;
-        while (y >= a && sorted[y] > v) {
-          sorted[y + 1] = sorted[y];
-          --y;
-        }
-        sorted[y + 1] = v;
-      }
-    }
-    __syncthreads();
-    for (int k = tid; k < o_hi - o_lo; k += LT) d.pb_rsrc[lo + o_lo + k] = sorted[k];
-    __syncthreads();
-    ka = kb;
-  }
-}
-
-// ---- P6: assemble each row --------------------------------------------------------
-// Rows of a tile are contiguous in the CSR.  Each lane lays out its row (household,
-// own workplace draws, received workplace, own random draws, received random), writes
-// its household part to the LDS copy of the tile's edge range, and writes into a 16-bit
-// LDS table the position of every entry of its own and received lists.  The tile's own
-// draws (one contiguous range of its batch's own list) and its received lists (one
-// contiguous range of the sorted received lists) are then read with consecutive lanes
-// on consecutive entries, and each entry goes to its tabled position.  The staged row
-// holds the source id with the network in the top two bits; the tile's edge range is
-// written with consecutive lanes on consecutive addresses.  A tile with more edges
-// than the LDS room writes directly.
-// The tile's first edge: a tile's edges are its rows' household and own edges (summed
-// by the generation pass) and its received entries (the span of its rows' received
-// lists); k_pb_tsum scans them within groups of 256 tiles and k_pb_parts scans the
-// groups, so the row pointers come from about N/256 values, not from N degrees.
+// ---- S3: each tile's first edge --------------------------------------------------
+// A tile's edges are its rows' household and own edges (summed by P1) and its received
+// entries (its leaf); k_pb_tsum scans them within groups of 256 tiles and k_pb_parts
+// scans the groups, so the row pointers come from about N/256 values, not N degrees.
 __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   __shared__ int wsum[TILE / 64];
   if (*d.flags) return;
   const int t = blockIdx.x * TILE + (int)threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int v = 0;
-  if (t < d.ntiles) {
-    const int4 tl = d.tiles[t];
-    v = d.pb_tdeg[t] + d.pb_rstart[tl.z] - d.pb_rstart[tl.y];
-  }
+  const int v = t < d.ntiles ? d.pb_tdeg[t] + d.pb_leaf[t + 1] - d.pb_leaf[t] : 0;
   int inc = v;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(inc, o);
@@ -787,43 +651,76 @@ __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   if (threadIdx.x == TILE - 1) d.pb_tpart[blockIdx.x] = (int64_t)(wb + inc);
 }
 
-__global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
-  extern __shared__ int32_t scol[];                  // [pb_asm_cap] staged row, then [pb_asm_cap] u16 positions
+// ---- P5: the rows of a tile ------------------------------------------------------
+// One workgroup per tile, one lane per row.  The tile's leaf (its received entries, in
+// no particular order) is read once into registers (pb_rper entries a lane, the rest
+// read again from memory) and counted per (row, network) in LDS; with the household
+// size and own counts these give the rows' degrees, whose scan after the tile's first
+// edge gives the row pointers.  Each lane lays out its row (household, own workplace
+// draws, received workplace, own random draws, received random), writes its
+// household part into the LDS copy of the tile's edge range, a 16-bit LDS table entry
+// with the position of each of its own draws, and the first position of each of its
+// two received runs.  The tile's own draws (one contiguous range of its batch's own
+// list) are read with consecutive lanes on consecutive entries and dropped at their
+// tabled positions; each received entry takes the next position of its (row,
+// network) run.  Each lane then sorts its two runs by initiator (they are short), and
+// the tile's edge range leaves with consecutive lanes on consecutive addresses.  A
+// column word is the source id with the network in its top two bits.  A tile with more
+// edges than the LDS room is laid out in the column array itself.
+constexpr int PB_ROWS_PER = 12;        // received entries a lane keeps in registers
+__device__ __forceinline__ int rkey(uint32_t x) { return (int)(((x & 255u) << 1) | (x >> 15)); }
+
+__global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
+  extern __shared__ int32_t scol[];                  // [cap] staged edges, then [cap] u16 positions
+  __shared__ int cur[2 * TILE];                      // (row, network): received count, then next position
   __shared__ int wsum[TILE / 64];
   if (*d.flags) return;
   const int cap = d.pb_asm_cap;
   uint16_t* pos_of = reinterpret_cast<uint16_t*>(scol + cap);
-  const int tix = blockIdx.x;
+  const int tix = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  cur[tid] = 0;
+  cur[tid + TILE] = 0;
   const int4 tl = d.tiles[tix];
-  // the tile's two source ranges are known before any row is laid out, so the first
-  // round of each copy is loaded together with the rows' own data
+  const RepInfo& ri = d.rep[tl.x];
+  const int dl = (ri.tile0 << 8) - ri.start;        // slot - agent id in this replicate
   const int2 tb = d.pb_tbase[tix];
-  const int g0 = d.pb_rstart[tl.y], g1 = d.pb_rstart[tl.z];
   const int oend = tb.y;
   const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + tb.x;
+  const int lo = d.pb_leaf[tix], hi = d.pb_leaf[tix + 1];
+  const int nreg = min(hi - lo, d.pb_rper * TILE);
   const int64_t b64 = d.pb_tpart[tix >> 8] + d.pb_tstart[tix];
-  int ov[PB_UNROLL], rv[PB_UNROLL];
+  // the first round of own draws and the leaf, loaded with the rows' own data
+  int ov[PB_UNROLL];
 #pragma unroll
   for (int u = 0; u < PB_UNROLL; ++u) {
-    const int k = u * TILE + (int)threadIdx.x;
+    const int k = u * TILE + tid;
     ov[u] = k < oend ? (int)ob[k] : 0;
-    rv[u] = g0 + k < g1 ? (int)d.pb_rsrc[g0 + k] : 0;
   }
-  const int i = tl.y + threadIdx.x;
+  uint2 x[PB_ROWS_PER];
+#pragma unroll
+  for (int j = 0; j < PB_ROWS_PER; ++j) {
+    const int k = j * TILE + tid;
+    x[j] = k < nreg ? d.pb_buf2[lo + k] : make_uint2(0u, 0u);
+  }
+  const int i = tl.y + tid;
   const bool live = i < tl.z;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int ko = 0, kr = 0, deg = 0;
+  int ko = 0, kr = 0;
   StaticRec sr{};
-  uint32_t rcv = 0u;
   if (live) {
     const uint32_t o = d.own[i];
     ko = (int)(o & 0xFFu);
     kr = (int)(o >> 8);
     sr = d.srec[i];
-    rcv = d.recv[i];
-    deg = (int)sr.hh_n - 1 + ko + kr + (int)(rcv >> 16) + (int)(rcv & 0xFFFFu);
   }
-  // the rows' degrees, scanned in the tile, after the tile's first edge
+  __syncthreads();                                   // counters cleared
+#pragma unroll
+  for (int j = 0; j < PB_ROWS_PER; ++j)
+    if (j * TILE + tid < nreg) atomicAdd(&cur[rkey(x[j].x)], 1);
+  for (int e = lo + nreg + tid; e < hi; e += TILE) atomicAdd(&cur[rkey(d.pb_buf2[e].x)], 1);
+  __syncthreads();
+  // rows past a ragged tile's end have no slot a partner could draw: their counts are 0
+  const int co = cur[2 * tid], cr = cur[2 * tid + 1];
+  const int deg = live ? (int)sr.hh_n - 1 + ko + kr + co + cr : 0;
   int dinc = deg;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(dinc, o);
@@ -837,15 +734,16 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
     dtot += wsum[q];
   }
   if (b64 + dtot > d.ecap) {                         // the same for every lane
-    if (threadIdx.x == 0) atomicOr(d.flags, FLAG_CAPACITY);
+    if (tid == 0) atomicOr(d.flags, FLAG_CAPACITY);
     return;
   }
-  if (tix == d.ntiles - 1 && threadIdx.x == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
+  if (tix == d.ntiles - 1 && tid == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
   __syncthreads();                                   // wsum is free again
   const int base = (int)b64, end = base + dtot;
   const int rp0 = base + dwb + dinc - deg;           // this row's first edge
   if (live) d.row_ptr[i] = rp0;
   const bool staged = end - base <= cap;
+  int32_t* out = staged ? scol : d.col + base;       // the tile's edge range
   const int c = ko + kr;
   int inc = c;
   for (int o = 1; o < 64; o <<= 1) {
@@ -856,104 +754,98 @@ __global__ __launch_bounds__(TILE) void k_pb_assemble(Dev d) {
   __syncthreads();
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
-  // each row's lane writes its household part and, for every entry of its own and
-  // received lists, that entry's position in the tile (network in the top bits)
+  int ro0 = 0, rr0 = 0;                              // first positions of the two received runs
   if (live) {
-    const uint32_t r = rcv;
-    const int ro = (int)(r >> 16), rr = (int)(r & 0xFFFFu);
-    const int rs = d.pb_rstart[i] - g0;
-    int pos = rp0;
+    int pos = rp0 - base;
     for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
-      if (m != i) {
-        if (staged) scol[pos - base] = m;
-        else d.col[pos] = m;
-        ++pos;
-      }
+      if (m != i) out[pos++] = m;
     const int os = wb + inc - c;
     if (staged) {
-      for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q - base) | (1 << 14));
-      pos += ko;
-      for (int q = 0; q < ro; ++q) pos_of[oend + rs + q] = (uint16_t)((pos + q - base) | (1 << 14));
-      pos += ro;
-      for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q - base) | (2 << 14));
-      pos += kr;
-      for (int q = 0; q < rr; ++q) pos_of[oend + rs + ro + q] = (uint16_t)((pos + q - base) | (2 << 14));
-    } else {                                   // direct writes
-      for (int q = 0; q < ko; ++q) d.col[pos + q] = (int)col_word(ob[os + q], 1u);
-      pos += ko;
-      for (int q = 0; q < ro; ++q) d.col[pos + q] = (int)col_word(d.pb_rsrc[g0 + rs + q], 1u);
-      pos += ro;
-      for (int q = 0; q < kr; ++q) d.col[pos + q] = (int)col_word(ob[os + ko + q], 2u);
-      pos += kr;
-      for (int q = 0; q < rr; ++q) d.col[pos + q] = (int)col_word(d.pb_rsrc[g0 + rs + ro + q], 2u);
+      for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q) | (1 << 14));
+    } else {
+      for (int q = 0; q < ko; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + q] - dl), 1u);
+    }
+    pos += ko;
+    ro0 = pos;
+    pos += co;
+    if (staged) {
+      for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q) | (2 << 14));
+    } else {
+      for (int q = 0; q < kr; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + ko + q] - dl), 2u);
+    }
+    pos += kr;
+    rr0 = pos;
+    cur[2 * tid] = ro0;
+    cur[2 * tid + 1] = rr0;
+  }
+  __syncthreads();
+  if (staged) {                                      // own draws to their tabled positions
+    for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
+      if (kb > 0) {
+#pragma unroll
+        for (int u = 0; u < PB_UNROLL; ++u) {
+          const int k = kb + u * TILE + tid;
+          ov[u] = k < oend ? (int)ob[k] : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PB_UNROLL; ++u) {
+        const int k = kb + u * TILE + tid;
+        if (k < oend) {
+          const uint32_t p = pos_of[k];
+          scol[p & 0x1FFFu] = (ov[u] - dl) | (int)((p >> 14) << 30);
+        }
+      }
+    }
+  }
+  // received entries to the next position of their run
+  auto put = [&](const uint2& v) {
+    const int k = rkey(v.x);
+    out[atomicAdd(&cur[k], 1)] = (int)col_word(v.y, (uint32_t)(k & 1) + 1u);
+  };
+#pragma unroll
+  for (int j = 0; j < PB_ROWS_PER; ++j)
+    if (j * TILE + tid < nreg) put(x[j]);
+  for (int e = lo + nreg + tid; e < hi; e += TILE) put(d.pb_buf2[e]);
+  __syncthreads();
+  // each run sorted by initiator (the network bits are the same within a run)
+  if (live) {
+    const int runs[2][2] = {{ro0, ro0 + co}, {rr0, rr0 + cr}};
+    for (int r = 0; r < 2; ++r) {
+      const int a = runs[r][0], b = runs[r][1];
+      for (int y0 = a + 1; y0 < b; ++y0) {
+        const uint32_t v = (uint32_t)out[y0];
+        int y = y0 - 1;
+        while (y >= a && (uint32_t)out[y] > v) {
+          out[y + 1] = out[y];
+          --y;
+        }
+        out[y + 1] = (int)v;
+      }
     }
   }
   if (!staged) return;
   __syncthreads();
-  // both lists: consecutive lanes on consecutive entries, each placed by its position
-  const int nr = g1 - g0;
-  for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
-    if (kb > 0) {
-#pragma unroll
-      for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * TILE + (int)threadIdx.x;
-        ov[u] = k < oend ? (int)ob[k] : 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < PB_UNROLL; ++u) {
-      const int k = kb + u * TILE + (int)threadIdx.x;
-      if (k < oend) {
-        const uint32_t p = pos_of[k];
-        scol[p & 0x1FFFu] = ov[u] | (int)((p >> 14) << 30);
-      }
-    }
-  }
-  for (int kb = 0; kb < nr; kb += TILE * PB_UNROLL) {
-    if (kb > 0) {
-#pragma unroll
-      for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * TILE + (int)threadIdx.x;
-        rv[u] = k < nr ? (int)d.pb_rsrc[g0 + k] : 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < PB_UNROLL; ++u) {
-      const int k = kb + u * TILE + (int)threadIdx.x;
-      if (k < nr) {
-        const uint32_t p = pos_of[oend + k];
-        scol[p & 0x1FFFu] = rv[u] | (int)((p >> 14) << 30);
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < end - base; k += TILE) d.col[base + k] = scol[k];
+  for (int k = tid; k < end - base; k += TILE) d.col[base + k] = scol[k];
 }
 
 // Named steps of a day's graph build.  With the partitioned builder off (populations
 // too large for 1024 level-1 digits) the claim-based builder of k_graph.hip runs.
-int build_steps(const Dev& d) { return d.pb_on ? 8 : 5; }
+int build_steps(const Dev& d) { return d.pb_on ? 7 : 5; }
 
 const char* build_step_name(const Dev& d, int k) {
-  static const char* pb[8] = {"pb_gen", "pb_scan1", "pb_scatter1", "pb_hist2",
-                              "pb_scatter2", "pb_leaf", "pb_tiles", "pb_assemble"};
+  static const char* pb[7] = {"pb_gen", "pb_scan1", "pb_scatter1", "pb_hist2",
+                              "pb_scatter2", "pb_tiles", "pb_rows"};
   static const char* cl[5] = {"clear", "count", "scan", "fill", "canon"};
   return d.pb_on ? pb[k] : cl[k];
 }
 
-static size_t leaf_lds(const Dev& d) { return (size_t)(d.pb_leaf_cap + (2u << d.pb_lb) + 1) * 4; }
 static size_t gen_lds(const Dev& d) {
   return ((size_t)d.pb_bcap + (size_t)d.pb_bpw * ((d.pb_nb1 + 1) / 2)) * 4;
 }
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)k_pb_leaf<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)leaf_lds(d));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pb_leaf<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)leaf_lds(d));
-  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_pb_gen, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)gen_lds(d));
 }
@@ -984,16 +876,10 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       break;
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
     case 5:
-      if (d.pb_leaf_cap > 512 * PB_LEAF_PER * 5 / 4 + 512)   // mean leaf beyond 512 lanes' registers
-        hipLaunchKernelGGL(k_pb_leaf<1024>, dim3(d.pb_nleaf), dim3(1024), leaf_lds(d), s, d);
-      else
-        hipLaunchKernelGGL(k_pb_leaf<512>, dim3(d.pb_nleaf), dim3(512), leaf_lds(d), s, d);
-      break;
-    case 6:
       hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
       break;
-    default: hipLaunchKernelGGL(k_pb_assemble, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
+    default: hipLaunchKernelGGL(k_pb_rows, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
   }
 }
 

@@ -27,8 +27,9 @@ class Simulator:
     ``graph=False`` launches the day's kernels eagerly instead of replaying a HIP graph;
     ``claim_builder`` selects the per-edge atomic-claim graph builder; ``autotune`` times
     the force-of-infection kernel's tilings at create and keeps the fastest;
-    ``min_lds_room`` (a test aid) gives the graph builder's leaf sort and row assembly
-    their smallest LDS room, which exercises their multi-group and direct-write paths;
+    ``min_lds_room`` (a test aid) gives the graph builder's level-1 scatter and row pass
+    their smallest LDS and register room, which exercises their direct-write and re-read
+    paths;
     ``dense_message`` streams every edge through the force-of-infection kernel every day
     (by default, with 2^20 agents or more, a day with at most N/256 infectious agents sums
     only the rows that hold an infectious source; the result is bitwise the same);

@@ -2,6 +2,7 @@
 function include/abm.h declares, the ctypes structs have the C layout, and parameter,
 ABI and workspace errors are reported before any device work."""
 import ctypes as C
+import dataclasses
 import os
 import re
 import subprocess
@@ -75,6 +76,13 @@ def test_workspace_size_and_errors():
     assert rc == 0
     rc, *_ = _ws(dict(p, vacc_immunity=2, disease_model=1), pop)
     assert rc == -1
+    # replicates are separate populations: a workplace may not span two of them
+    p3, pop3 = workload(3, n=3000, n_rep=2)
+    assert _ws(p3, pop3)[0] == 0
+    cross = dataclasses.replace(pop3, wp_members=pop3.wp_members.copy())
+    first = int(pop3.wp_start[0])
+    cross.wp_members[first] = int(pop3.agent_offset[1]) + 5 if pop3.wp_members[first] < pop3.agent_offset[1] else 5
+    assert _ws(p3, cross)[0] == -1
 
 
 def test_high_contact_means_take_the_claim_builder():
