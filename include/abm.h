@@ -118,6 +118,10 @@ enum {
 #define ABM_FLAG_STRAIGHT_THROUGH 128 /* relaxed mode: the forward pass takes the hard
                                       infection draw (the relaxed sample's sign) and the
                                       adjoint the relaxed sample's derivative            */
+#define ABM_FLAG_TWO_TILE_LEAVES 256 /* test aid: give the graph builder's partition
+                                      leaves of two tiles (512 rows) at any population
+                                      size, as it does by itself beyond 2^25 agents; the
+                                      graph is bitwise the same                          */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's level-1 scatter
                                     and row pass their smallest LDS and register room,
                                     so that batches and tiles are written directly and

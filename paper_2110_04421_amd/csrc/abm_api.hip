@@ -109,7 +109,7 @@ struct Sizes {
   int64_t N = 0, R = 0, ntiles = 0, nscan = 0, M = 0, nseeds = 0, ecap = 0, T = 0;
   int64_t seg = 0, nckpt = 0;
   // partitioned builder
-  int64_t pb_on = 0, l2 = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
+  int64_t pb_on = 0, lb = 0, nlv = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
   int64_t asm_cap = 0, s1_cap = PB_S1_CAP, rper = 12;
   int64_t fseg = 1;
 };
@@ -360,14 +360,14 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   // room for the day's contacts: at least what the edge room leaves after the household
   // edges (each contact is two edges), so that a larger edge_capacity enlarges both
   z.ccap = (int64_t)std::ceil(std::max(cmean + 8.0 * std::sqrt(cmean), (ecap - hh_edges) / 2.0) + 4096.0);
-  // partitioned builder geometry: destinations numbered by tile slot, leaves of 256
-  // slots (one tile each), level-1 buckets of 2^(8 + l2) slots; l2 = 9 only where 256
-  // leaves a bucket would make more than 512 buckets
+  // partitioned builder geometry: destinations numbered by tile slot, leaves of 2^lb
+  // slots (one tile, or two where one-tile leaves would make more than 512 level-1
+  // buckets), level-1 buckets of 256 leaves
   const int64_t slots = z.ntiles * TILE;
-  auto nb1_of = [&](int l2) { return (slots + ((int64_t)1 << (l2 + 8)) - 1) >> (l2 + 8); };
-  const int l2 = nb1_of(8) > 512 ? 9 : 8;
-  z.l2 = l2;
-  z.nb1 = nb1_of(l2);
+  auto nb1_of = [&](int b) { return (slots + ((int64_t)1 << (b + 8)) - 1) >> (b + 8); };
+  z.lb = (nb1_of(8) > 512 || (p->flags & ABM_FLAG_TWO_TILE_LEAVES)) ? 9 : 8;
+  z.nb1 = nb1_of((int)z.lb);
+  z.nlv = (z.ntiles + ((int64_t)1 << (z.lb - 8)) - 1) >> (z.lb - 8);
   // room for a batch's own draws: 1.3x the largest per-agent Poisson means (+2048);
   // the generation pass stages a batch in LDS, so more than 24576 draws (high contact
   // means) take the claim builder
@@ -378,9 +378,10 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
             z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
             N < ((int64_t)1 << 27);   // initiators fit the 27 low bits of a partition word
-  // edges of a tile staged in LDS by the row assembly: 1.1x the mean (+512)
-  const double tile_mean = emean * (double)TILE / (double)N;
-  z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(8192, ((int64_t)(1.1 * tile_mean) + 512 + 255) / 256 * 256));
+  // edges of a leaf staged in LDS by the row pass: 1.1x the mean (+512); positions
+  // in the staged range take 14 bits
+  const double leaf_mean = emean * (double)((int64_t)1 << z.lb) / (double)N;
+  z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(16384, ((int64_t)(1.1 * leaf_mean) + 512 + 255) / 256 * 256));
   if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {
     z.asm_cap = 2048;
     z.s1_cap = 0;
@@ -394,7 +395,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.ngrid = (z.nbatch + z.bpw - 1) / z.bpw;
   z.s1_nparts = (z.nb1 * z.nbatch + SCAN_BLOCK - 1) / SCAN_BLOCK;
   z.maxch = (z.ccap + 8191) / 8192 + z.nb1;
-  z.nleaf = z.nb1 << z.l2;
+  z.nleaf = z.nb1 << 8;
   if (p->mode == ABM_SOFT) {
     z.seg = p->checkpoint_every;
     z.nckpt = (z.T + z.seg - 1) / z.seg + 1;
@@ -457,14 +458,14 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_bchunk = L.take<int32_t>(z.nb1 + 1);
     o.pb_nchunks = L.take<int32_t>(1);
     o.pb_chunks = L.take<int4>(z.maxch);
-    o.pb_hist2 = L.take<int32_t>(z.maxch << z.l2);
+    o.pb_hist2 = L.take<int32_t>(z.maxch * 256);
     o.pb_leaf = L.take<int32_t>(z.nleaf + 1);
     o.pb_b1h = L.take<uint16_t>(z.ccap);
     o.pb_b1w = L.take<uint32_t>(z.ccap);
     o.pb_buf2 = L.take<uint2>(z.ccap);
     o.pb_tdeg = L.take<int32_t>(z.ntiles);
-    o.pb_tstart = L.take<int32_t>(z.ntiles);
-    o.pb_tpart = L.take<int64_t>((z.ntiles + TILE - 1) / TILE + 1);
+    o.pb_tstart = L.take<int32_t>(z.nlv);
+    o.pb_tpart = L.take<int64_t>((z.nlv + TILE - 1) / TILE + 1);
   }
   if (p.mode == ABM_SOFT) {
     o.s = L.take<float>(z.N);
@@ -770,7 +771,8 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.msg_shape = 0;
   d.pb_on = (int32_t)z.pb_on;
   if (z.pb_on) {
-    d.pb_l2 = (int32_t)z.l2;
+    d.pb_lb = (int32_t)z.lb;
+    d.pb_nlv = (int32_t)z.nlv;
     d.pb_nb1 = (int32_t)z.nb1;
     d.pb_nbatch = (int32_t)z.nbatch;
     d.pb_bpw = (int32_t)z.bpw;
@@ -796,11 +798,11 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_b1h = (uint16_t*)(ws + o.pb_b1h);
     d.pb_b1w = (uint32_t*)(ws + o.pb_b1w);
     d.pb_buf2 = (uint2*)(ws + o.pb_buf2);
-    d.pb_sh = (int32_t)(z.l2 - 8);
+    d.pb_sh = (int32_t)(z.lb - 8);
     d.pb_tdeg = (int32_t*)(ws + o.pb_tdeg);
     d.pb_tstart = (int32_t*)(ws + o.pb_tstart);
     d.pb_tpart = (int64_t*)(ws + o.pb_tpart);
-    d.pb_ntgrp = (int32_t)((z.ntiles + TILE - 1) / TILE);
+    d.pb_ntgrp = (int32_t)((z.nlv + TILE - 1) / TILE);
   }
   name_kernels(s);
 

@@ -142,10 +142,10 @@ struct Dev {
                                               // shape 0: one tile a workgroup, masks in L2;
                                               // 1: one tile, mask in LDS; 2: four tiles, mask in LDS
   // The partitioned builder numbers destinations by tile slot, tile * 256 + row in the
-  // tile, so that a leaf of 256 slots is a tile.  Level-1 buckets hold 2^(8 + l2) slots
-  // and split into 2^l2 leaves (l2 = 8 or 9).
-  int32_t pb_on, pb_l2, pb_nb1, pb_nbatch, pb_bpw, pb_ngrid, pb_bcap, pb_s1_nparts, pb_maxch, pb_nleaf,
-      pb_asm_cap, pb_s1_cap, pb_rper;
+  // tile, so that a leaf of 2^lb slots (lb = 8 or 9) is one or two whole tiles.  Level-1
+  // buckets hold 2^(lb + 8) slots and split into 256 leaves; pb_nlv leaves hold tiles.
+  int32_t pb_on, pb_lb, pb_nb1, pb_nbatch, pb_bpw, pb_ngrid, pb_bcap, pb_s1_nparts, pb_maxch, pb_nleaf,
+      pb_nlv, pb_asm_cap, pb_s1_cap, pb_rper;
   int64_t pb_ccap;          // room for received entries (contacts) per day
   int32_t* pb_hist1;        // [nb1][nbatch] + 1: histograms, then run offsets
   uint32_t* pb_own;         // [nbatch][pb_bcap] each batch's own draws (slots), agent order
@@ -155,20 +155,20 @@ struct Dev {
   int32_t* pb_bchunk;       // [nb1 + 1] first chunk of each bucket
   int32_t* pb_nchunks;      // [1]
   int4* pb_chunks;          // [maxch] {bucket, begin, end, 0}
-  int32_t* pb_hist2;        // [maxch][2^l2] histogram, then run offsets
-  int32_t* pb_leaf;         // [nb1 * 2^l2 + 1] leaf (= tile) starts
+  int32_t* pb_hist2;        // [maxch][256] histogram, then run offsets
+  int32_t* pb_leaf;         // [nb1 * 256 + 1] leaf starts
   // level-1 partition, 6 bytes an entry: with dib = slot within its level-1 bucket
-  // (8 + l2 bits) and sh = l2 - 8: b1h = dib >> sh,
+  // (lb + 8 bits) and sh = lb - 8: b1h = dib >> sh,
   // b1w = initiator | (dib & (2^sh - 1)) << 27 | network << 31
   uint16_t* pb_b1h;         // [ccap]
   uint32_t* pb_b1w;         // [ccap]
-  // leaves: (row within the tile | network << 15, initiator)
+  // leaves: (row within the leaf (lb bits) | network << 15, initiator)
   uint2* pb_buf2;           // [ccap]
   int32_t pb_sh;
   int32_t* pb_tdeg;         // [ntiles] household and own edges of a tile's rows
-  int32_t* pb_tstart;       // [ntiles] a tile's first edge within its group of 256 tiles
-  int64_t* pb_tpart;        // [ntiles / 256 + 1] first edge of each group; [last] = total
-  int32_t pb_ntgrp;         // groups of 256 tiles
+  int32_t* pb_tstart;       // [nlv] a leaf's first edge within its group of 256 leaves
+  int64_t* pb_tpart;        // [nlv / 256 + 1] first edge of each group; [last] = total
+  int32_t pb_ntgrp;         // groups of 256 leaves
 
   // soft mode
   float* s;            // susceptible mass [N]

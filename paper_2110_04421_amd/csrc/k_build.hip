@@ -2,25 +2,25 @@
 // claim-based builder in k_graph.hip (section 3, "Interaction Networks"), built without
 // global atomics and without random 4-byte scatters.  Destinations are numbered by tile
 // slot (tile * 256 + row in the tile), so that the last level of the partition, a leaf
-// of 256 slots, is one tile of rows:
+// of 2^LB slots (LB = 8 or 9), is one or two whole tiles of rows:
 //
 //   P1  gen         per batch of 4 tiles: draw every agent's contacts once (Philox, and
 //                   the workplace-member loads), store the partners' slots in agent
 //                   order in the batch's own list, keep the agent's counts and each
 //                   tile's household + own edge count, histogram the partners by
-//                   level-1 digit (slot >> (8 + l2)).
+//                   level-1 digit (slot >> (LB + 8)).
 //   S1  scan        digit-major exclusive scan of the histograms -> each (digit, batch)
 //                   run's offset; level-1 bucket bounds; chunk table.
 //   P2  scatter-1   read the batch's own list, counting-sort its entries
 //                   (slot, src | net) by digit in LDS, write each run contiguously
 //                   as 6-byte entries (16-bit slot part, 32-bit source word).
-//   P3  hist-2      per chunk of a level-1 bucket: histogram by leaf digit (l2 bits).
-//   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf (= tile) bounds.
+//   P3  hist-2      per chunk of a level-1 bucket: histogram by leaf digit.
+//   S2  scan-2      per bucket, digit-major scan -> run offsets; leaf bounds.
 //   P4  scatter-2   entries into leaves.
-//   S3  tiles       each tile's first edge: a scan of the tiles' edge totals.
-//   P5  rows        per tile: count the leaf per (row, network), row pointers, then each
-//                   row: household, own occupation draws, received occupation, own
-//                   random draws, received random, the received runs sorted by
+//   S3  leaves      each leaf's first edge: a scan of the leaves' edge totals.
+//   P5  rows        per leaf: count its entries per (row, network), row pointers, then
+//                   each row: household, own occupation draws, received occupation,
+//                   own random draws, received random, the received runs sorted by
 //                   initiator in LDS.
 // Every run written in P2/P4 leaves as consecutive lanes on consecutive addresses, and
 // every random access of a per-edge scatter becomes an LDS access.
@@ -114,7 +114,7 @@ __device__ __forceinline__ StaticRec load_srec_nt(const StaticRec* p) {
 
 // Level-1 partition entry of (destination slot p, initiator | network << 31).
 __device__ __forceinline__ void put_b1(const Dev& d, int pos, uint32_t p, uint32_t w) {
-  const uint32_t dib = p & ((1u << (d.pb_l2 + 8)) - 1u);
+  const uint32_t dib = p & ((1u << (d.pb_lb + 8)) - 1u);
   d.pb_b1h[pos] = (uint16_t)(dib >> d.pb_sh);
   d.pb_b1w[pos] = w | ((dib & ((1u << d.pb_sh) - 1u)) << 27);
 }
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   for (int k = threadIdx.x; k < d.pb_bpw * nh2; k += PB_THREADS) hist[k] = 0u;
   __syncthreads();
   const uint32_t t = (uint32_t)(*d.day);
-  const int s1 = d.pb_l2 + 8;
+  const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = 0; j < d.pb_bpw; ++j) {
     const int bt = blockIdx.x * d.pb_bpw + j;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
   __shared__ int nstage;
   if (*d.flags) return;
-  const int s1 = d.pb_l2 + 8;
+  const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
   const int bt0 = blockIdx.x * d.pb_bpw;
@@ -500,14 +500,12 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
 }
 
 // ---- P3: level-2 histograms per chunk -----------------------------------------------
-constexpr int PB_L2_MAX = 512;         // leaves per level-1 bucket (2^l2)
 __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
-  __shared__ int hist[PB_L2_MAX];
+  __shared__ int hist[256];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
-  const int nd = 1 << d.pb_l2, d2s = 8 - d.pb_sh;    // leaf digit = b1h >> d2s
-  for (int k = threadIdx.x; k < nd; k += TILE) hist[k] = 0;
+  hist[threadIdx.x] = 0;
   __syncthreads();
   const int4 ch = d.pb_chunks[c];
   for (int eb = ch.y; eb < ch.z; eb += TILE * PB_UNROLL) {
@@ -519,10 +517,10 @@ __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
     }
 #pragma unroll
     for (int u = 0; u < PB_UNROLL; ++u)
-      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> d2s) & (nd - 1)], 1);
+      if (eb + u * TILE + (int)threadIdx.x < ch.z) atomicAdd(&hist[(x[u] >> (d.pb_lb - d.pb_sh)) & 255u], 1);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nd; k += TILE) d.pb_hist2[((size_t)c << d.pb_l2) + k] = hist[k];
+  d.pb_hist2[(size_t)c * 256 + threadIdx.x] = hist[threadIdx.x];
 }
 
 // ---- S2: per bucket, digit-major exclusive scan of its chunks' histograms ------------
@@ -533,15 +531,14 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
   const int b = blockIdx.x;
   const int c0 = d.pb_bchunk[b], nc = d.pb_bchunk[b + 1] - c0;
   const int base = d.pb_bstart[b];
-  const int l2 = d.pb_l2, nd = 1 << l2;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  const int n = nd * nc;
+  const int n = 256 * nc;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int q0 = 0; q0 < n; q0 += TILE) {
     const int q = q0 + threadIdx.x;
     const int dg = nc ? q / nc : 0, cc = nc ? q % nc : 0;
-    const int v = q < n ? d.pb_hist2[((size_t)(c0 + cc) << l2) + dg] : 0;
+    const int v = q < n ? d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] : 0;
     int inc = v;
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(inc, o);
@@ -553,19 +550,19 @@ __global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
     for (int k = 0; k < wv; ++k) wb += wsum[k];
     const int ex = carry + wb + inc - v;
     if (q < n) {
-      d.pb_hist2[((size_t)(c0 + cc) << l2) + dg] = base + ex;
-      if (cc == 0) d.pb_leaf[((size_t)b << l2) + dg] = base + ex;
+      d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] = base + ex;
+      if (cc == 0) d.pb_leaf[(size_t)b * 256 + dg] = base + ex;
     }
     __syncthreads();
     if (threadIdx.x == TILE - 1) carry += wb + inc;
     __syncthreads();
   }
   if (nc == 0)
-    for (int dg = threadIdx.x; dg < nd; dg += TILE) d.pb_leaf[((size_t)b << l2) + dg] = base;
-  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 << l2] = d.pb_bstart[d.pb_nb1];
+    for (int dg = threadIdx.x; dg < 256; dg += TILE) d.pb_leaf[(size_t)b * 256 + dg] = base;
+  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 * 256] = d.pb_bstart[d.pb_nb1];
 }
 
-// ---- P4: scatter into leaves (tiles) -------------------------------------------------
+// ---- P4: scatter into leaves ---------------------------------------------------------
 // The chunk is read once into registers (PB_S2_PER entries a lane), counting-sorted by
 // leaf digit in LDS, and each leaf's part of the chunk leaves as one contiguous run of
 // consecutive lanes.  The order inside a run is immaterial: the row pass orders fully.
@@ -573,17 +570,17 @@ constexpr int PB_S2_THREADS = 1024;
 constexpr int PB_S2_PER = PB_CHUNK / PB_S2_THREADS;
 __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
   __shared__ uint2 sorted[PB_CHUNK];
-  __shared__ int cnt[PB_L2_MAX], first[PB_L2_MAX];
-  __shared__ int wsum[PB_L2_MAX / 64];
+  __shared__ int cnt[256], first[256];
+  __shared__ int wsum[4];
   if (*d.flags) return;
   const int c = blockIdx.x;
   if (c >= *d.pb_nchunks) return;
   const int4 ch = d.pb_chunks[c];
   const int n = ch.z - ch.y;
   const int tid = threadIdx.x;
-  const int nd = 1 << d.pb_l2, d2s = 8 - d.pb_sh;   // leaf digit = b1h >> d2s
-  if (tid < nd) cnt[tid] = 0;
+  if (tid < 256) cnt[tid] = 0;
   __syncthreads();
+  const int d2s = d.pb_lb - d.pb_sh;          // level-2 digit = (b1h >> d2s) & 255
   uint2 x[PB_S2_PER];                         // (b1h, b1w)
   int rank[PB_S2_PER];
 #pragma unroll
@@ -594,18 +591,18 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d2s) & (nd - 1)], 1) : 0;
+    rank[j] = k < n ? atomicAdd(&cnt[(x[j].x >> d2s) & 255u], 1) : 0;
   }
   __syncthreads();
-  const int v = tid < nd ? cnt[tid] : 0;
+  const int v = tid < 256 ? cnt[tid] : 0;
   int inc = v;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(inc, o);
     if ((tid & 63) >= o) inc += y;
   }
-  if (tid < nd && (tid & 63) == 63) wsum[tid >> 6] = inc;
+  if (tid < 256 && (tid & 63) == 63) wsum[tid >> 6] = inc;
   __syncthreads();
-  if (tid < nd) {
+  if (tid < 256) {
     int wb = 0;
     for (int q = 0; q < (tid >> 6); ++q) wb += wsum[q];
     first[tid] = wb + inc - v;
@@ -614,30 +611,35 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 #pragma unroll
   for (int j = 0; j < PB_S2_PER; ++j) {
     const int k = j * PB_S2_THREADS + tid;
-    if (k < n) sorted[first[(x[j].x >> d2s) & (nd - 1)] + rank[j]] = x[j];
+    if (k < n) sorted[first[(x[j].x >> d2s) & 255u] + rank[j]] = x[j];
   }
   __syncthreads();
-  const int* off = d.pb_hist2 + ((size_t)c << d.pb_l2);
-  const uint32_t lmask = (1u << d.pb_sh) - 1u;
+  const int* off = d.pb_hist2 + (size_t)c * 256;
+  const uint32_t lmask = (1u << d.pb_sh) - 1u, dmask = (1u << d.pb_lb) - 1u;
   for (int k = tid; k < n; k += PB_S2_THREADS) {
     const uint2 y = sorted[k];
-    const int dg = (y.x >> d2s) & (nd - 1);
+    const int dg = (y.x >> d2s) & 255u;
     const int pos = off[dg] + (k - first[dg]);
     const uint32_t dib = (y.x << d.pb_sh) | ((y.y >> 27) & lmask);
-    d.pb_buf2[pos] = make_uint2((dib & 255u) | ((y.y >> 31) << 15), y.y & 0x07FFFFFFu);
+    d.pb_buf2[pos] = make_uint2((dib & dmask) | ((y.y >> 31) << 15), y.y & 0x07FFFFFFu);
   }
 }
 
-// ---- S3: each tile's first edge --------------------------------------------------
-// A tile's edges are its rows' household and own edges (summed by P1) and its received
-// entries (its leaf); k_pb_tsum scans them within groups of 256 tiles and k_pb_parts
+// ---- S3: each leaf's first edge --------------------------------------------------
+// A leaf's edges are its tiles' household and own edges (summed by P1) and its
+// received entries; k_pb_tsum scans them within groups of 256 leaves and k_pb_parts
 // scans the groups, so the row pointers come from about N/256 values, not N degrees.
 __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   __shared__ int wsum[TILE / 64];
   if (*d.flags) return;
-  const int t = blockIdx.x * TILE + (int)threadIdx.x;
+  const int L = blockIdx.x * TILE + (int)threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int v = t < d.ntiles ? d.pb_tdeg[t] + d.pb_leaf[t + 1] - d.pb_leaf[t] : 0;
+  const int nt = 1 << (d.pb_lb - 8);
+  int v = 0;
+  if (L < d.pb_nlv) {
+    v = d.pb_leaf[L + 1] - d.pb_leaf[L];
+    for (int t = L * nt; t < min(L * nt + nt, d.ntiles); ++t) v += d.pb_tdeg[t];
+  }
   int inc = v;
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(inc, o);
@@ -647,76 +649,88 @@ __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   __syncthreads();
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
-  if (t < d.ntiles) d.pb_tstart[t] = wb + inc - v;
+  if (L < d.pb_nlv) d.pb_tstart[L] = wb + inc - v;
   if (threadIdx.x == TILE - 1) d.pb_tpart[blockIdx.x] = (int64_t)(wb + inc);
 }
 
-// ---- P5: the rows of a tile ------------------------------------------------------
-// One workgroup per tile, one lane per row.  The tile's leaf (its received entries, in
-// no particular order) is read once into registers (pb_rper entries a lane, the rest
-// read again from memory) and counted per (row, network) in LDS; with the household
-// size and own counts these give the rows' degrees, whose scan after the tile's first
-// edge gives the row pointers.  Each lane lays out its row (household, own workplace
-// draws, received workplace, own random draws, received random), writes its
-// household part into the LDS copy of the tile's edge range, a 16-bit LDS table entry
-// with the position of each of its own draws, and the first position of each of its
-// two received runs.  The tile's own draws (one contiguous range of its batch's own
-// list) are read with consecutive lanes on consecutive entries and dropped at their
-// tabled positions; each received entry takes the next position of its (row,
-// network) run.  Each lane then sorts its two runs by initiator (they are short), and
-// the tile's edge range leaves with consecutive lanes on consecutive addresses.  A
-// column word is the source id with the network in its top two bits.  A tile with more
-// edges than the LDS room is laid out in the column array itself.
+// ---- P5: the rows of a leaf ------------------------------------------------------
+// One workgroup per leaf of NT tiles (NT * 256 rows, one lane each; the tiles are
+// consecutive rows of the CSR and consecutive ranges of one batch's own list).  The
+// leaf's received entries (in no particular order) are read once into registers
+// (pb_rper entries a lane, the rest read again from memory) and counted per (row,
+// network) in LDS; with the household sizes and own counts these give the rows'
+// degrees, whose scan after the leaf's first edge gives the row pointers.  Each lane
+// lays out its row (household, own workplace draws, received workplace, own random
+// draws, received random), writes its household part into the LDS copy of the leaf's
+// edge range, a 16-bit LDS table entry with the position of each of its own draws, and
+// the first position of each of its two received runs.  The own draws are read with
+// consecutive lanes on consecutive entries and dropped at their tabled positions; each
+// received entry takes the next position of its (row, network) run.  Each lane then
+// sorts its two runs by initiator (they are short), and the edge range leaves with
+// consecutive lanes on consecutive addresses.  A column word is the source id with the
+// network in its top two bits.  A leaf with more edges than the LDS room is laid out
+// in the column array itself.
 constexpr int PB_ROWS_PER = 12;        // received entries a lane keeps in registers
-__device__ __forceinline__ int rkey(uint32_t x) { return (int)(((x & 255u) << 1) | (x >> 15)); }
+__device__ __forceinline__ int slot_delta(const Dev& d, int tix) {   // slot - agent id
+  const RepInfo& ri = d.rep[d.tiles[tix].x];
+  return (ri.tile0 << 8) - ri.start;
+}
 
-__global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
+template <int NT>
+__global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
+  constexpr int NR = NT * TILE;
   extern __shared__ int32_t scol[];                  // [cap] staged edges, then [cap] u16 positions
-  __shared__ int cur[2 * TILE];                      // (row, network): received count, then next position
-  __shared__ int wsum[TILE / 64];
+  __shared__ int cur[2 * NR];                        // (row, network): received count, then next position
+  __shared__ int wsum[NR / 64];
   if (*d.flags) return;
   const int cap = d.pb_asm_cap;
   uint16_t* pos_of = reinterpret_cast<uint16_t*>(scol + cap);
-  const int tix = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int L = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   cur[tid] = 0;
-  cur[tid + TILE] = 0;
-  const int4 tl = d.tiles[tix];
-  const RepInfo& ri = d.rep[tl.x];
-  const int dl = (ri.tile0 << 8) - ri.start;        // slot - agent id in this replicate
-  const int2 tb = d.pb_tbase[tix];
-  const int oend = tb.y;
-  const uint32_t* ob = d.pb_own + (size_t)(tix >> 2) * d.pb_bcap + tb.x;
-  const int lo = d.pb_leaf[tix], hi = d.pb_leaf[tix + 1];
-  const int nreg = min(hi - lo, d.pb_rper * TILE);
-  const int64_t b64 = d.pb_tpart[tix >> 8] + d.pb_tstart[tix];
+  cur[tid + NR] = 0;
+  const int t0 = L * NT, tix = t0 + tid / TILE;      // the leaf's first tile, this lane's tile
+  const bool two = NT == 2 && t0 + 1 < d.ntiles;
+  const int2 tb0 = d.pb_tbase[t0];
+  const int oend0 = tb0.y, oend = tb0.y + (two ? d.pb_tbase[t0 + 1].y : 0);
+  const uint32_t* ob = d.pb_own + (size_t)(t0 >> 2) * d.pb_bcap + tb0.x;
+  const int dl0 = slot_delta(d, t0), dl1 = two ? slot_delta(d, t0 + 1) : dl0;
+  const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
+  const int nreg = min(hi - lo, d.pb_rper * NR);
+  const int64_t b64 = d.pb_tpart[L >> 8] + d.pb_tstart[L];
   // the first round of own draws and the leaf, loaded with the rows' own data
   int ov[PB_UNROLL];
 #pragma unroll
   for (int u = 0; u < PB_UNROLL; ++u) {
-    const int k = u * TILE + tid;
+    const int k = u * NR + tid;
     ov[u] = k < oend ? (int)ob[k] : 0;
   }
   uint2 x[PB_ROWS_PER];
 #pragma unroll
   for (int j = 0; j < PB_ROWS_PER; ++j) {
-    const int k = j * TILE + tid;
+    const int k = j * NR + tid;
     x[j] = k < nreg ? d.pb_buf2[lo + k] : make_uint2(0u, 0u);
   }
-  const int i = tl.y + tid;
-  const bool live = i < tl.z;
-  int ko = 0, kr = 0;
+  int i = 0, ko = 0, kr = 0;
+  bool live = false;
   StaticRec sr{};
-  if (live) {
-    const uint32_t o = d.own[i];
-    ko = (int)(o & 0xFFu);
-    kr = (int)(o >> 8);
-    sr = d.srec[i];
+  if (tix < d.ntiles) {
+    const int4 tl = d.tiles[tix];
+    i = tl.y + (tid & (TILE - 1));
+    live = i < tl.z;
+    if (live) {
+      const uint32_t o = d.own[i];
+      ko = (int)(o & 0xFFu);
+      kr = (int)(o >> 8);
+      sr = d.srec[i];
+    }
   }
+  const int dl = tid < TILE ? dl0 : dl1;
+  auto rkey = [](uint32_t v) { return (int)(((v & (NR - 1)) << 1) | (v >> 15)); };
   __syncthreads();                                   // counters cleared
 #pragma unroll
   for (int j = 0; j < PB_ROWS_PER; ++j)
-    if (j * TILE + tid < nreg) atomicAdd(&cur[rkey(x[j].x)], 1);
-  for (int e = lo + nreg + tid; e < hi; e += TILE) atomicAdd(&cur[rkey(d.pb_buf2[e].x)], 1);
+    if (j * NR + tid < nreg) atomicAdd(&cur[rkey(x[j].x)], 1);
+  for (int e = lo + nreg + tid; e < hi; e += NR) atomicAdd(&cur[rkey(d.pb_buf2[e].x)], 1);
   __syncthreads();
   // rows past a ragged tile's end have no slot a partner could draw: their counts are 0
   const int co = cur[2 * tid], cr = cur[2 * tid + 1];
@@ -729,7 +743,7 @@ __global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
   if (lane == 63) wsum[wv] = dinc;
   __syncthreads();
   int dwb = 0, dtot = 0;
-  for (int q = 0; q < TILE / 64; ++q) {
+  for (int q = 0; q < NR / 64; ++q) {
     if (q < wv) dwb += wsum[q];
     dtot += wsum[q];
   }
@@ -737,13 +751,13 @@ __global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
     if (tid == 0) atomicOr(d.flags, FLAG_CAPACITY);
     return;
   }
-  if (tix == d.ntiles - 1 && tid == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
+  if (L == d.pb_nlv - 1 && tid == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
   __syncthreads();                                   // wsum is free again
   const int base = (int)b64, end = base + dtot;
   const int rp0 = base + dwb + dinc - deg;           // this row's first edge
   if (live) d.row_ptr[i] = rp0;
   const bool staged = end - base <= cap;
-  int32_t* out = staged ? scol : d.col + base;       // the tile's edge range
+  int32_t* out = staged ? scol : d.col + base;       // the leaf's edge range
   const int c = ko + kr;
   int inc = c;
   for (int o = 1; o < 64; o <<= 1) {
@@ -780,20 +794,20 @@ __global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
   }
   __syncthreads();
   if (staged) {                                      // own draws to their tabled positions
-    for (int kb = 0; kb < oend; kb += TILE * PB_UNROLL) {
+    for (int kb = 0; kb < oend; kb += NR * PB_UNROLL) {
       if (kb > 0) {
 #pragma unroll
         for (int u = 0; u < PB_UNROLL; ++u) {
-          const int k = kb + u * TILE + tid;
+          const int k = kb + u * NR + tid;
           ov[u] = k < oend ? (int)ob[k] : 0;
         }
       }
 #pragma unroll
       for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * TILE + tid;
+        const int k = kb + u * NR + tid;
         if (k < oend) {
           const uint32_t p = pos_of[k];
-          scol[p & 0x1FFFu] = (ov[u] - dl) | (int)((p >> 14) << 30);
+          scol[p & 0x3FFFu] = (ov[u] - (k < oend0 ? dl0 : dl1)) | (int)((p >> 14) << 30);
         }
       }
     }
@@ -805,8 +819,8 @@ __global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
   };
 #pragma unroll
   for (int j = 0; j < PB_ROWS_PER; ++j)
-    if (j * TILE + tid < nreg) put(x[j]);
-  for (int e = lo + nreg + tid; e < hi; e += TILE) put(d.pb_buf2[e]);
+    if (j * NR + tid < nreg) put(x[j]);
+  for (int e = lo + nreg + tid; e < hi; e += NR) put(d.pb_buf2[e]);
   __syncthreads();
   // each run sorted by initiator (the network bits are the same within a run)
   if (live) {
@@ -826,7 +840,7 @@ __global__ __launch_bounds__(TILE) void k_pb_rows(Dev d) {
   }
   if (!staged) return;
   __syncthreads();
-  for (int k = tid; k < end - base; k += TILE) d.col[base + k] = scol[k];
+  for (int k = tid; k < end - base; k += NR) d.col[base + k] = scol[k];
 }
 
 // Named steps of a day's graph build.  With the partitioned builder off (populations
@@ -835,7 +849,7 @@ int build_steps(const Dev& d) { return d.pb_on ? 7 : 5; }
 
 const char* build_step_name(const Dev& d, int k) {
   static const char* pb[7] = {"pb_gen", "pb_scan1", "pb_scatter1", "pb_hist2",
-                              "pb_scatter2", "pb_tiles", "pb_rows"};
+                              "pb_scatter2", "pb_leaves", "pb_rows"};
   static const char* cl[5] = {"clear", "count", "scan", "fill", "canon"};
   return d.pb_on ? pb[k] : cl[k];
 }
@@ -843,9 +857,16 @@ const char* build_step_name(const Dev& d, int k) {
 static size_t gen_lds(const Dev& d) {
   return ((size_t)d.pb_bcap + (size_t)d.pb_bpw * ((d.pb_nb1 + 1) / 2)) * 4;
 }
+static size_t rows_lds(const Dev& d) { return (size_t)d.pb_asm_cap * 6; }
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_pb_rows<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)rows_lds(d));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_pb_rows<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)rows_lds(d));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_pb_gen, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)gen_lds(d));
 }
@@ -879,7 +900,12 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
       break;
-    default: hipLaunchKernelGGL(k_pb_rows, dim3(d.ntiles), dim3(TILE), (size_t)d.pb_asm_cap * 6, s, d); break;
+    default:
+      if (d.pb_lb == 9)
+        hipLaunchKernelGGL(k_pb_rows<2>, dim3(d.pb_nlv), dim3(2 * TILE), rows_lds(d), s, d);
+      else
+        hipLaunchKernelGGL(k_pb_rows<1>, dim3(d.pb_nlv), dim3(TILE), rows_lds(d), s, d);
+      break;
   }
 }
 

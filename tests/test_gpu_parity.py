@@ -53,10 +53,13 @@ def test_tables_match_oracle():
             assert list(pt[23 + a]) == poisson_thresholds(p["mu_random"][a] / 2.0)
 
 
+@pytest.mark.parametrize("two", [False, True])
 @pytest.mark.parametrize("k,n,nrep", [(0, None, None), (1, 20000, None), (3, 30000, 7)])
-def test_csr_bit_exact(k, n, nrep):
+def test_csr_bit_exact(k, n, nrep, two):
+    """Leaves of one tile (below 2^25 agents) and of two (beyond; forced here): two
+    tiles of a leaf may belong to different replicates and one may be ragged."""
     p, pop = workload(k, n=n, n_rep=nrep, n_steps=8)
-    with _sim(p, pop) as s:
+    with _sim(p, pop, two_tile_leaves=two) as s:
         for t in range(3):
             s.run(1)
             rp, col, w = s.csr()
@@ -67,12 +70,14 @@ def test_csr_bit_exact(k, n, nrep):
 
 
 @pytest.mark.parametrize("mu", [15.0, 40.0])
-def test_csr_bit_exact_at_high_contact_means(mu):
-    """At mean 15 a batch's draws pass the level-1 scatter's and the assembly's LDS
-    room (their direct paths run); at the validator's largest mean, 40 per network, the
-    claim builder takes over.  Either way the graph is the oracle's."""
+@pytest.mark.parametrize("two", [False, True])
+def test_csr_bit_exact_at_high_contact_means(mu, two):
+    """At mean 15 a batch's draws pass the level-1 scatter's and the row pass's LDS
+    and register room (their direct and re-read paths run); at the validator's largest
+    mean, 40 per network, the claim builder takes over.  Either way the graph is the
+    oracle's."""
     p, pop = workload(1, n=3000, n_steps=4, mu_random=[mu] * 9, mu_occupation=[mu] * 23)
-    with _sim(p, pop) as s:
+    with _sim(p, pop, two_tile_leaves=two) as s:
         for t in range(2):
             s.run(1)
             rp, col, w = s.csr()
@@ -183,10 +188,12 @@ def test_claim_builder_builds_the_same_graph():
     assert np.array_equal(outs[0][2], outs[1][2])
 
 
-def test_csr_bit_exact_several_level1_buckets():
-    # 600k agents: the partitioned builder splits destinations over 3 level-1 buckets
+@pytest.mark.parametrize("two", [False, True])
+def test_csr_bit_exact_several_level1_buckets(two):
+    # 600k agents: the partitioned builder splits destinations over 10 level-1 buckets
+    # of 65,536 slots (5 of 131,072 with two-tile leaves)
     p, pop = workload(1, n=600_000, n_steps=2)
-    with _sim(p, pop) as s:
+    with _sim(p, pop, two_tile_leaves=two) as s:
         s.run(1)
         rp, col, w = s.csr()
     rp_o, col_o, w_o, _ = og.build_graph(pop, p, 0)
@@ -195,12 +202,13 @@ def test_csr_bit_exact_several_level1_buckets():
     assert np.array_equal(w, w_o.astype(np.float32))
 
 
-def test_builder_small_lds_room_builds_the_same_graph():
-    # leaves sorted in several groups and tiles assembled by direct writes
+@pytest.mark.parametrize("two", [False, True])
+def test_builder_small_lds_room_builds_the_same_graph(two):
+    # batches scattered and leaves laid out by direct writes, received entries re-read
     p, pop = workload(3, n=60000, n_rep=5, n_steps=4)
     outs = []
     for small in (False, True):
-        with _sim(p, pop, min_lds_room=small) as s:
+        with _sim(p, pop, min_lds_room=small, two_tile_leaves=two) as s:
             c = s.run(3)
             outs.append((c, s.csr(), s.state()))
     assert np.array_equal(outs[0][0], outs[1][0])
