@@ -43,7 +43,7 @@ def household_edges(pop) -> int:
 
 def level1_buckets(N: int) -> int:
     """Level-1 buckets of the partitioned builder (same rule as the library, one
-    replicate): destinations are numbered by tile slot, leaves are tiles of 256."""
+    replicate): destinations are numbered by tile slot, leaves are one or two tiles."""
     slots = -(-N // 256) * 256
     nb1 = lambda l2: -(-slots // (1 << (l2 + 8)))
     return nb1(9) if nb1(8) > 512 else nb1(8)
@@ -66,7 +66,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
         "pb_scatter1": 2.0 * N + 10.0 * C,         # counts and own list in, 6-byte entries out
         "pb_hist2": 2.0 * C,                       # the 16-bit destination parts
         "pb_scatter2": 14.0 * C,                   # 6-byte entries in, 8-byte leaf entries out
-        "pb_tiles": 16.0 * nbt * 4,                # per tile: degree and leaf bounds in, start out
+        "pb_leaves": 16.0 * nbt * 4,               # per tile: degree and leaf bounds in, start out
         # leaf entries, own list, counts and static records in; col and row_ptr out
         "pb_rows": 4.0 * E + 12.0 * C + 22.0 * N,
         # claim-based builder
@@ -81,7 +81,7 @@ def kernel_bytes(name: str, N: int, E: float, C: float, vacc: bool, Einf: float 
 
 
 KERNEL_SOURCES = {"message": "k_step.hip", "fused": "k_step.hip", "pre": "k_step.hip",
-                  "mask": "k_step.hip", "pb_rows": "k_build.hip", "pb_tiles": "k_build.hip",
+                  "mask": "k_step.hip", "pb_rows": "k_build.hip", "pb_leaves": "k_build.hip",
                   "pb_gen": "k_build.hip", "pb_scatter1": "k_build.hip",
                   "pb_hist2": "k_build.hip", "pb_scatter2": "k_build.hip",
                   "pb_scan1": "k_build.hip"}

@@ -111,7 +111,7 @@ struct Sizes {
   // partitioned builder
   int64_t pb_on = 0, lb = 0, nlv = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
   int64_t asm_cap = 0, s1_cap = PB_S1_CAP, rper = 12;
-  int64_t fseg = 1;
+  int64_t fseg = 1, fin_one = 0;
 };
 
 // element strides of the notification ring's slots, rounded to 64 elements so that
@@ -319,6 +319,8 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   }
   // end-of-day count reduction: each replicate's tile rows in fseg parts of 256 lanes
   z.fseg = std::max<int64_t>(1, std::min<int64_t>(256, (max_rep_tiles + 255) / 256));
+  // up to 2048 tiles a replicate, one launch reduces and closes the day
+  z.fin_one = max_rep_tiles <= 2048;
   z.nscan = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
   // Edge room: mean directed edges + 8 standard deviations of the Poisson contact count.
   double hh_edges = 0;
@@ -436,7 +438,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.fin_part = L.take<unsigned long long>(z.R * z.fseg * TILE_NC);
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
   o.traj = L.take<long long>(z.T * z.R * ABM_NC);
-  o.day = L.take<int32_t>(1);
+  o.day = L.take<int32_t>(2);                  // the day, and the count of replicates done with it
   o.rmask = L.take<uint32_t>((z.N + 31) / 32 + 1);
   o.ninf = L.take<int32_t>(1);
   o.work = L.take<int32_t>((int64_t)FRONT_NB * front_cap(z));
@@ -719,9 +721,11 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.tile_counts = (uint32_t*)(ws + o.tile_counts);
   d.fin_part = (unsigned long long*)(ws + o.fin_part);
   d.fseg = (int32_t)z.fseg;
+  d.fin_one = (int32_t)z.fin_one;
   d.prev_counts = (long long*)(ws + o.prev_counts);
   d.traj = (long long*)(ws + o.traj);
   d.day = (int32_t*)(ws + o.day);
+  d.fin_done = d.day + 1;
   d.rmask = (uint32_t*)(ws + o.rmask);
   d.ninf = (int32_t*)(ws + o.ninf);
   d.work = (int32_t*)(ws + o.work);
@@ -893,7 +897,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   if (z.nseeds > 0)
     HIPCHK(s, hipMemcpyAsync(ws + o.seeds, pop->initial_infected, z.nseeds * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemsetAsync(ws + o.latch, 0, R, st));
-  HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 4, st));
+  HIPCHK(s, hipMemsetAsync(ws + o.day, 0, 8, st));
   HIPCHK(s, hipMemsetAsync(ws + o.ninf, 0, 4, st));
   if (d.den_on) {                          // no graphs before day 0: empty rows
     HIPCHK(s, hipMemsetAsync(ws + o.ring_rp, 0, (size_t)p->den_window * d.ring_rstride * 4, st));

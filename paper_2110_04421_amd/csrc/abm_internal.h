@@ -123,10 +123,11 @@ struct Dev {
 
   uint32_t* tile_counts;            // [ntiles][TILE_NC] each day's per-tile counts
   unsigned long long* fin_part;     // [R][fseg][TILE_NC] partial sums of the tile rows
-  int32_t fseg;
+  int32_t fseg, fin_one;     // fin_one: one launch per day reduces the counts (k_fin_one)
   long long* prev_counts;           // [R][ABM_NC]
   long long* traj;                  // [T][R][ABM_NC]
   int32_t* day;
+  int32_t* fin_done;        // replicates whose counts k_fin_one has closed this day
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)

@@ -307,10 +307,9 @@ __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
 }
 
 // Bucket bounds and the level-2 chunk table (one workgroup; nb1 <= 1024).
-__global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
+__device__ void buckets_body(const Dev& d, int64_t total) {
   __shared__ int nch[PB_NB1_MAX + 1];
   __shared__ int ok;
-  const int64_t total = d.pb_part[d.pb_s1_nparts];
   const int b = threadIdx.x;
   int start = 0, size = 0;
   if (b < d.pb_nb1) {
@@ -345,6 +344,43 @@ __global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) {
     d.pb_bchunk[b] = nch[b];
   }
   if (b == 0) d.pb_bchunk[d.pb_nb1] = nch[d.pb_nb1];
+}
+
+__global__ __launch_bounds__(1024) void k_pb_buckets(Dev d) { buckets_body(d, d.pb_part[d.pb_s1_nparts]); }
+
+// The whole level-1 scan and the bucket table in one workgroup, where the histograms
+// are few (small populations, whose day is bound by launches): each lane scans a
+// contiguous run of at most PB_S1_ONE entries in place.
+constexpr int PB_S1_ONE = 32;
+__global__ __launch_bounds__(1024) void k_pb_s1_one(Dev d) {
+  __shared__ int wsum[16];
+  __shared__ int64_t tot;
+  const int n = d.pb_nb1 * d.pb_nbatch;
+  const int per = (n + 1023) / 1024;
+  const int q0 = (int)threadIdx.x * per;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int s = 0;
+  for (int k = 0; k < per; ++k)
+    if (q0 + k < n) s += d.pb_hist1[q0 + k];
+  int inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int q = 0; q < wv; ++q) wb += wsum[q];
+  if (threadIdx.x == 1023) tot = (int64_t)(wb + inc);
+  int run = wb + inc - s;
+  for (int k = 0; k < per; ++k)
+    if (q0 + k < n) {
+      const int v = d.pb_hist1[q0 + k];
+      d.pb_hist1[q0 + k] = run;
+      run += v;
+    }
+  __syncthreads();                                   // the offsets are written
+  buckets_body(d, tot);
 }
 
 // ---- P2: scatter into level-1 runs ---------------------------------------------------
@@ -650,7 +686,14 @@ __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
   if (L < d.pb_nlv) d.pb_tstart[L] = wb + inc - v;
-  if (threadIdx.x == TILE - 1) d.pb_tpart[blockIdx.x] = (int64_t)(wb + inc);
+  if (threadIdx.x == TILE - 1) {
+    if (gridDim.x == 1) {                            // one group: its parts scanned here
+      d.pb_tpart[0] = 0;
+      d.pb_tpart[1] = (int64_t)(wb + inc);
+    } else {
+      d.pb_tpart[blockIdx.x] = (int64_t)(wb + inc);
+    }
+  }
 }
 
 // ---- P5: the rows of a leaf ------------------------------------------------------
@@ -885,6 +928,10 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
   switch (k) {
     case 0: hipLaunchKernelGGL(k_pb_gen, dim3(d.pb_ngrid), dim3(PB_THREADS), gen_lds(d), s, d); break;
     case 1:
+      if ((int64_t)d.pb_nb1 * d.pb_nbatch <= 1024 * PB_S1_ONE) {
+        hipLaunchKernelGGL(k_pb_s1_one, dim3(1), dim3(1024), 0, s, d);
+        break;
+      }
       hipLaunchKernelGGL(k_pb_s1a, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
       hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_part, d.pb_s1_nparts);
       hipLaunchKernelGGL(k_pb_s1c, dim3(d.pb_s1_nparts), dim3(TILE), 0, s, d);
@@ -898,7 +945,7 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
     case 5:
       hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(TILE), 0, s, d);
-      hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
+      if (d.pb_ntgrp > 1) hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
       break;
     default:
       if (d.pb_lb == 9)

@@ -919,6 +919,47 @@ __global__ __launch_bounds__(64) void k_finalize(Dev d) {
 
 __global__ void k_advance_day(Dev d) { *d.day = *d.day + 1; }
 
+// Small replicates (at most 2048 tiles): one workgroup per replicate adds its tile rows
+// in one part, writes the day's counts as k_finalize does, and the last workgroup to
+// finish advances the day (every workgroup has read it by then).
+__global__ __launch_bounds__(TILE) void k_fin_one(Dev d) {
+  __shared__ unsigned long long part[TILE / 64][ABM_NC];
+  const int r = blockIdx.x;
+  const RepInfo& ri = d.rep[r];
+  const int t = *d.day;
+  const bool ok = *d.flags == 0;
+  unsigned long long acc[ABM_NC];
+#pragma unroll
+  for (int c = 0; c < ABM_NC; ++c) acc[c] = 0ull;
+  for (int k = threadIdx.x; k < ri.ntiles; k += TILE) {
+    const uint4* row = (const uint4*)(d.tile_counts + (size_t)(ri.tile0 + k) * TILE_NC);
+    const uint4 a = row[0], b = row[1], c = row[2], e = row[3];
+    const uint32_t v[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int q = 0; q < ABM_NC; ++q) acc[q] += v[q];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < ABM_NC; ++c) {
+    unsigned long long v = acc[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) part[wv][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < ABM_NC) {
+    const int c = threadIdx.x;
+    long long v = (long long)(part[0][c] + part[1][c] + part[2][c] + part[3][c]);
+    if (c == ABM_C_EDGES) v = ok ? (long long)d.row_ptr[ri.start + ri.n] - d.row_ptr[ri.start] : 0;
+    if (c == ABM_C_INF_EDGES && !ok) v = 0;
+    if (t < d.T) d.traj[((size_t)t * d.R + r) * ABM_NC + c] = v;
+    d.prev_counts[(size_t)r * ABM_NC + c] = v;
+  }
+  if (threadIdx.x == 0 && atomicAdd(d.fin_done, 1) == (int)gridDim.x - 1) {
+    *d.fin_done = 0;
+    *d.day = t + 1;
+  }
+}
+
 // ---- initial state: everyone susceptible, seeds exposed on day -1 --------------------
 __global__ __launch_bounds__(TILE) void k_init_state(Dev d) {
   const int i = blockIdx.x * TILE + threadIdx.x;
@@ -1073,6 +1114,10 @@ void launch_fused(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_fused, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
 void launch_finalize(const Dev& d, hipStream_t s) {
+  if (d.fin_one) {
+    hipLaunchKernelGGL(k_fin_one, dim3(d.R), dim3(TILE), 0, s, d);
+    return;
+  }
   hipLaunchKernelGGL(k_fin_part, dim3(d.fseg, d.R), dim3(TILE), 0, s, d);
   hipLaunchKernelGGL(k_finalize, dim3(d.R), dim3(64), 0, s, d);
   hipLaunchKernelGGL(k_advance_day, dim3(1), dim3(1), 0, s, d);
