@@ -467,7 +467,7 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
     o.pb_buf2 = L.take<uint2>(z.ccap);
     o.pb_tdeg = L.take<int32_t>(z.ntiles);
     o.pb_tstart = L.take<int32_t>(z.nlv);
-    o.pb_tpart = L.take<int64_t>((z.nlv + TILE - 1) / TILE + 1);
+    o.pb_tpart = L.take<int64_t>((z.nlv + 1023) / 1024 + 1);
   }
   if (p.mode == ABM_SOFT) {
     o.s = L.take<float>(z.N);
@@ -806,7 +806,7 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
     d.pb_tdeg = (int32_t*)(ws + o.pb_tdeg);
     d.pb_tstart = (int32_t*)(ws + o.pb_tstart);
     d.pb_tpart = (int64_t*)(ws + o.pb_tpart);
-    d.pb_ntgrp = (int32_t)((z.nlv + TILE - 1) / TILE);
+    d.pb_ntgrp = (int32_t)((z.nlv + 1023) / 1024);
   }
   name_kernels(s);
 

@@ -167,9 +167,9 @@ struct Dev {
   uint2* pb_buf2;           // [ccap]
   int32_t pb_sh;
   int32_t* pb_tdeg;         // [ntiles] household and own edges of a tile's rows
-  int32_t* pb_tstart;       // [nlv] a leaf's first edge within its group of 256 leaves
-  int64_t* pb_tpart;        // [nlv / 256 + 1] first edge of each group; [last] = total
-  int32_t pb_ntgrp;         // groups of 256 leaves
+  int32_t* pb_tstart;       // [nlv] a leaf's first edge within its group of 1024 leaves
+  int64_t* pb_tpart;        // [nlv / 1024 + 1] first edge of each group; [last] = total
+  int32_t pb_ntgrp;         // groups of 1024 leaves
 
   // soft mode
   float* s;            // susceptible mass [N]

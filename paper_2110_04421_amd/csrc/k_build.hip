@@ -560,42 +560,41 @@ __global__ __launch_bounds__(TILE) void k_pb_hist2(Dev d) {
 }
 
 // ---- S2: per bucket, digit-major exclusive scan of its chunks' histograms ------------
-__global__ __launch_bounds__(TILE) void k_pb_s2(Dev d) {
-  __shared__ int wsum[TILE / 64];
-  __shared__ int carry;
+// Four lanes per digit, each taking a quarter of the digit's chunks: the lanes' runs
+// follow the digit-major order, and at each step a wave reads 16 consecutive digits of
+// 4 chunk rows.  Run sums, a workgroup scan of them, then the runs' offsets (two
+// barriers; the histograms are read twice, the second time from cache).
+constexpr int PB_S2_SCAN = 1024;
+__global__ __launch_bounds__(PB_S2_SCAN) void k_pb_s2(Dev d) {
+  __shared__ int wsum[PB_S2_SCAN / 64];
   if (*d.flags) return;
   const int b = blockIdx.x;
   const int c0 = d.pb_bchunk[b], nc = d.pb_bchunk[b + 1] - c0;
   const int base = d.pb_bstart[b];
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int n = 256 * nc;
+  const int dg = threadIdx.x >> 2, part = threadIdx.x & 3;
+  const int per = (nc + 3) >> 2;
+  const int ca = min(nc, part * per), cb = min(nc, ca + per);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q0 = 0; q0 < n; q0 += TILE) {
-    const int q = q0 + threadIdx.x;
-    const int dg = nc ? q / nc : 0, cc = nc ? q % nc : 0;
-    const int v = q < n ? d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] : 0;
-    int inc = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    int wb = 0;
-    for (int k = 0; k < wv; ++k) wb += wsum[k];
-    const int ex = carry + wb + inc - v;
-    if (q < n) {
-      d.pb_hist2[(size_t)(c0 + cc) * 256 + dg] = base + ex;
-      if (cc == 0) d.pb_leaf[(size_t)b * 256 + dg] = base + ex;
-    }
-    __syncthreads();
-    if (threadIdx.x == TILE - 1) carry += wb + inc;
-    __syncthreads();
+  int* h = d.pb_hist2 + ((size_t)c0 << 8) + dg;
+  int s = 0;
+  for (int cc = ca; cc < cb; ++cc) s += h[(size_t)cc << 8];
+  int inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
-  if (nc == 0)
-    for (int dg = threadIdx.x; dg < 256; dg += TILE) d.pb_leaf[(size_t)b * 256 + dg] = base;
-  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 * 256] = d.pb_bstart[d.pb_nb1];
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int k = 0; k < wv; ++k) wb += wsum[k];
+  int run = base + wb + inc - s;
+  if (part == 0) d.pb_leaf[((size_t)b << 8) + dg] = run;   // the digit's first chunk (or its empty run)
+  for (int cc = ca; cc < cb; ++cc) {
+    const int v = h[(size_t)cc << 8];
+    h[(size_t)cc << 8] = run;
+    run += v;
+  }
+  if (b == d.pb_nb1 - 1 && threadIdx.x == 0) d.pb_leaf[(size_t)d.pb_nb1 << 8] = d.pb_bstart[d.pb_nb1];
 }
 
 // ---- P4: scatter into leaves ---------------------------------------------------------
@@ -663,12 +662,14 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
 
 // ---- S3: each leaf's first edge --------------------------------------------------
 // A leaf's edges are its tiles' household and own edges (summed by P1) and its
-// received entries; k_pb_tsum scans them within groups of 256 leaves and k_pb_parts
-// scans the groups, so the row pointers come from about N/256 values, not N degrees.
-__global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
-  __shared__ int wsum[TILE / 64];
+// received entries; k_pb_tsum scans them within groups of PB_TGRP leaves and
+// k_pb_parts scans the groups (not launched for a single group), so the row pointers
+// come from about N/256 values, not N degrees.
+constexpr int PB_TGRP = 1024;
+__global__ __launch_bounds__(PB_TGRP) void k_pb_tsum(Dev d) {
+  __shared__ int wsum[PB_TGRP / 64];
   if (*d.flags) return;
-  const int L = blockIdx.x * TILE + (int)threadIdx.x;
+  const int L = blockIdx.x * PB_TGRP + (int)threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nt = 1 << (d.pb_lb - 8);
   int v = 0;
@@ -686,7 +687,7 @@ __global__ __launch_bounds__(TILE) void k_pb_tsum(Dev d) {
   int wb = 0;
   for (int q = 0; q < wv; ++q) wb += wsum[q];
   if (L < d.pb_nlv) d.pb_tstart[L] = wb + inc - v;
-  if (threadIdx.x == TILE - 1) {
+  if (threadIdx.x == PB_TGRP - 1) {
     if (gridDim.x == 1) {                            // one group: its parts scanned here
       d.pb_tpart[0] = 0;
       d.pb_tpart[1] = (int64_t)(wb + inc);
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   constexpr int NR = NT * TILE;
   extern __shared__ int32_t scol[];                  // [cap] staged edges, then [cap] u16 positions
   __shared__ int cur[2 * NR];                        // (row, network): received count, then next position
-  __shared__ int wsum[NR / 64];
+  __shared__ int wsum[NR / 64], wsum2[NR / 64];
   if (*d.flags) return;
   const int cap = d.pb_asm_cap;
   uint16_t* pos_of = reinterpret_cast<uint16_t*>(scol + cap);
@@ -739,7 +740,7 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   const int dl0 = slot_delta(d, t0), dl1 = two ? slot_delta(d, t0 + 1) : dl0;
   const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
   const int nreg = min(hi - lo, d.pb_rper * NR);
-  const int64_t b64 = d.pb_tpart[L >> 8] + d.pb_tstart[L];
+  const int64_t b64 = d.pb_tpart[L / PB_TGRP] + d.pb_tstart[L];
   // the first round of own draws and the leaf, loaded with the rows' own data
   int ov[PB_UNROLL];
 #pragma unroll
@@ -776,18 +777,29 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   for (int e = lo + nreg + tid; e < hi; e += NR) atomicAdd(&cur[rkey(d.pb_buf2[e].x)], 1);
   __syncthreads();
   // rows past a ragged tile's end have no slot a partner could draw: their counts are 0
+  // the rows' degrees and own-draw counts, scanned together
   const int co = cur[2 * tid], cr = cur[2 * tid + 1];
-  const int deg = live ? (int)sr.hh_n - 1 + ko + kr + co + cr : 0;
-  int dinc = deg;
+  const int c = ko + kr;
+  const int deg = live ? (int)sr.hh_n - 1 + c + co + cr : 0;
+  int dinc = deg, inc = c;
   for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(dinc, o);
-    if (lane >= o) dinc += y;
+    const int y = __shfl_up(dinc, o), y2 = __shfl_up(inc, o);
+    if (lane >= o) {
+      dinc += y;
+      inc += y2;
+    }
   }
-  if (lane == 63) wsum[wv] = dinc;
+  if (lane == 63) {
+    wsum[wv] = dinc;
+    wsum2[wv] = inc;
+  }
   __syncthreads();
-  int dwb = 0, dtot = 0;
+  int dwb = 0, dtot = 0, wb = 0;
   for (int q = 0; q < NR / 64; ++q) {
-    if (q < wv) dwb += wsum[q];
+    if (q < wv) {
+      dwb += wsum[q];
+      wb += wsum2[q];
+    }
     dtot += wsum[q];
   }
   if (b64 + dtot > d.ecap) {                         // the same for every lane
@@ -795,22 +807,11 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
     return;
   }
   if (L == d.pb_nlv - 1 && tid == 0) d.row_ptr[d.N] = (int)(b64 + dtot);
-  __syncthreads();                                   // wsum is free again
   const int base = (int)b64, end = base + dtot;
   const int rp0 = base + dwb + dinc - deg;           // this row's first edge
   if (live) d.row_ptr[i] = rp0;
   const bool staged = end - base <= cap;
   int32_t* out = staged ? scol : d.col + base;       // the leaf's edge range
-  const int c = ko + kr;
-  int inc = c;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  if (lane == 63) wsum[wv] = inc;
-  __syncthreads();
-  int wb = 0;
-  for (int q = 0; q < wv; ++q) wb += wsum[q];
   int ro0 = 0, rr0 = 0;                              // first positions of the two received runs
   if (live) {
     int pos = rp0 - base;
@@ -940,11 +941,11 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
     case 2: hipLaunchKernelGGL(k_pb_scatter1, dim3(d.pb_ngrid), dim3(PB_THREADS), 0, s, d); break;
     case 3:
       hipLaunchKernelGGL(k_pb_hist2, dim3(d.pb_maxch), dim3(TILE), 0, s, d);
-      hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(PB_S2_SCAN), 0, s, d);
       break;
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
     case 5:
-      hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(TILE), 0, s, d);
+      hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(PB_TGRP), 0, s, d);
       if (d.pb_ntgrp > 1) hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
       break;
     default:

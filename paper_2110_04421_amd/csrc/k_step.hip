@@ -220,51 +220,68 @@ __global__ __launch_bounds__(TILE) void k_pre(Dev d) {
 // agent).  Coarse: bit g = some agent of the group [8g, 8g+8) infectious (1/64 byte per
 // agent, small enough to stay in L2).  The message kernel tests the coarse bit, then the
 // fine bit, before it reads an edge's weight and the source's code byte.
-__global__ __launch_bounds__(TILE) void k_mask(Dev d) {
-  const int w = blockIdx.x * TILE + threadIdx.x;       // coarse word: agents [256w, 256w+256)
-  const int ncw = (d.N + 255) >> 8;
-  uint32_t coarse = 0;
-  int ninf = 0;
-  if (w < ncw) {
-    for (int f = 0; f < 8; ++f) {
-      const int i0 = (w << 8) + (f << 5);
-      uint32_t m = 0;
-      if (i0 + 32 <= d.N) {
-        const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
-        const uint4 a = c4[0], b = c4[1];
-        const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+// One lane per fine word (32 agents); a workgroup of MASK_T lanes covers one
+// super-coarse word (64 coarse words of 256 agents).
+constexpr int MASK_T = 512;
+__global__ __launch_bounds__(MASK_T) void k_mask(Dev d) {
+  __shared__ int wsum[MASK_T / 64];
+  __shared__ uint32_t wbyte[MASK_T / 64];
+  const int fw = blockIdx.x * MASK_T + (int)threadIdx.x;
+  const int i0 = fw << 5;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t m = 0;
+  if (i0 + 32 <= d.N) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(d.code + i0);
+    const uint4 a = c4[0], b = c4[1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
-      } else {
-        for (int k = 0; i0 + k < d.N && k < 32; ++k)
-          if (d.code[i0 + k]) m |= 1u << k;
-      }
-      if (i0 < d.N) {
-        d.imask[i0 >> 5] = m;
-        d.rmask[i0 >> 5] = 0u;
-      }
-      ninf += __builtin_popcount(m);
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-        if ((m >> (8 * g)) & 0xFFu) coarse |= 1u << (4 * f + g);
-    }
-    d.cmask[w] = coarse;
+      for (int k = 0; k < 4; ++k)
+        if ((v[q] >> (8 * k)) & 0xFFu) m |= 1u << (4 * q + k);
+  } else {
+    for (int k = 0; i0 + k < d.N && k < 32; ++k)
+      if (d.code[i0 + k]) m |= 1u << k;
   }
+  if (i0 < d.N) {
+    d.imask[fw] = m;
+    d.rmask[fw] = 0u;
+  }
+  // coarse word fw >> 3: four bits (one per 8 agents) from each of its 8 fine words
+  uint32_t cb = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    if ((m >> (8 * g)) & 0xFFu) cb |= 1u << g;
+  uint32_t coarse = cb << (4 * (fw & 7));
+  coarse |= __shfl_xor(coarse, 1);
+  coarse |= __shfl_xor(coarse, 2);
+  coarse |= __shfl_xor(coarse, 4);
+  const int w = fw >> 3;
+  if ((fw & 7) == 0 && w < ((d.N + 255) >> 8)) d.cmask[w] = coarse;
+  // super-coarse: bit (w & 63) of word w >> 6 = some agent of coarse word w infectious;
+  // a wave holds 8 coarse words, a workgroup one super-coarse word
+  const unsigned long long bl = __ballot((fw & 7) == 0 && coarse != 0u);
+  uint32_t byte = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) byte |= (uint32_t)((bl >> (8 * k)) & 1ull) << k;
   // one atomic per workgroup (a single counter: the fewer the better)
-  __shared__ int wsum[TILE / 64];
+  int ninf = __builtin_popcount(m);
   for (int o = 32; o > 0; o >>= 1) ninf += __shfl_xor(ninf, o);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = ninf;
+  if (lane == 0) {
+    wsum[wv] = ninf;
+    wbyte[wv] = byte;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    int t = 0;
+    unsigned long long sc = 0ull;
+    for (int q = 0; q < MASK_T / 64; ++q) {
+      t += wsum[q];
+      sc |= (unsigned long long)wbyte[q] << (8 * q);
+    }
     if (t) atomicAdd(d.ninf, t);
+    if ((int)blockIdx.x < d.nsc) d.scmask[blockIdx.x] = sc;
   }
-  // super-coarse: bit w = some agent of [256w, 256w+256) infectious (one word per wave)
-  const unsigned long long b = __ballot(coarse != 0u);
-  if ((threadIdx.x & 63) == 0 && (w >> 6) < d.nsc) d.scmask[w >> 6] = b;
 }
 
 // A frontier day: few enough agents infectious (k_mask's count) that the force of
@@ -1038,8 +1055,8 @@ void launch_pre(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_pre, dim3(d.ntiles), dim3(TILE), 0, s, d);
 }
 void launch_mask(const Dev& d, hipStream_t s) {
-  const int ncw = (d.N + 255) >> 8;
-  hipLaunchKernelGGL(k_mask, dim3((ncw + TILE - 1) / TILE), dim3(TILE), 0, s, d);
+  const int nfw = (d.N + 31) >> 5;
+  hipLaunchKernelGGL(k_mask, dim3((nfw + MASK_T - 1) / MASK_T), dim3(MASK_T), 0, s, d);
 }
 void launch_vplan(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
