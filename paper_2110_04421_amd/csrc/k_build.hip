@@ -811,78 +811,85 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   const int rp0 = base + dwb + dinc - deg;           // this row's first edge
   if (live) d.row_ptr[i] = rp0;
   const bool staged = end - base <= cap;
-  int32_t* out = staged ? scol : d.col + base;       // the leaf's edge range
-  int ro0 = 0, rr0 = 0;                              // first positions of the two received runs
-  if (live) {
-    int pos = rp0 - base;
-    for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
-      if (m != i) out[pos++] = m;
-    const int os = wb + inc - c;
-    if (staged) {
-      for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q) | (1 << 14));
-    } else {
-      for (int q = 0; q < ko; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + q] - dl), 1u);
+  // The layout, written once for each target so that the staged one addresses LDS
+  // directly (a pointer that may be either would take the slower generic path).
+  auto lay_out = [&](auto* out, bool stg) {
+    int ro0 = 0, rr0 = 0;                            // first positions of the two received runs
+    if (live) {
+      int pos = rp0 - base;
+      for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
+        if (m != i) out[pos++] = m;
+      const int os = wb + inc - c;
+      if (stg) {
+        for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q) | (1 << 14));
+      } else {
+        for (int q = 0; q < ko; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + q] - dl), 1u);
+      }
+      pos += ko;
+      ro0 = pos;
+      pos += co;
+      if (stg) {
+        for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q) | (2 << 14));
+      } else {
+        for (int q = 0; q < kr; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + ko + q] - dl), 2u);
+      }
+      pos += kr;
+      rr0 = pos;
+      cur[2 * tid] = ro0;
+      cur[2 * tid + 1] = rr0;
     }
-    pos += ko;
-    ro0 = pos;
-    pos += co;
-    if (staged) {
-      for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q) | (2 << 14));
-    } else {
-      for (int q = 0; q < kr; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + ko + q] - dl), 2u);
-    }
-    pos += kr;
-    rr0 = pos;
-    cur[2 * tid] = ro0;
-    cur[2 * tid + 1] = rr0;
-  }
-  __syncthreads();
-  if (staged) {                                      // own draws to their tabled positions
-    for (int kb = 0; kb < oend; kb += NR * PB_UNROLL) {
-      if (kb > 0) {
+    __syncthreads();
+    if (stg) {                                       // own draws to their tabled positions
+      for (int kb = 0; kb < oend; kb += NR * PB_UNROLL) {
+        if (kb > 0) {
+#pragma unroll
+          for (int u = 0; u < PB_UNROLL; ++u) {
+            const int k = kb + u * NR + tid;
+            ov[u] = k < oend ? (int)ob[k] : 0;
+          }
+        }
 #pragma unroll
         for (int u = 0; u < PB_UNROLL; ++u) {
           const int k = kb + u * NR + tid;
-          ov[u] = k < oend ? (int)ob[k] : 0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < PB_UNROLL; ++u) {
-        const int k = kb + u * NR + tid;
-        if (k < oend) {
-          const uint32_t p = pos_of[k];
-          scol[p & 0x3FFFu] = (ov[u] - (k < oend0 ? dl0 : dl1)) | (int)((p >> 14) << 30);
+          if (k < oend) {
+            const uint32_t p = pos_of[k];
+            out[p & 0x3FFFu] = (ov[u] - (k < oend0 ? dl0 : dl1)) | (int)((p >> 14) << 30);
+          }
         }
       }
     }
-  }
-  // received entries to the next position of their run
-  auto put = [&](const uint2& v) {
-    const int k = rkey(v.x);
-    out[atomicAdd(&cur[k], 1)] = (int)col_word(v.y, (uint32_t)(k & 1) + 1u);
+    // received entries to the next position of their run
+    auto put = [&](const uint2& v) {
+      const int k = rkey(v.x);
+      out[atomicAdd(&cur[k], 1)] = (int)col_word(v.y, (uint32_t)(k & 1) + 1u);
+    };
+#pragma unroll
+    for (int j = 0; j < PB_ROWS_PER; ++j)
+      if (j * NR + tid < nreg) put(x[j]);
+    for (int e = lo + nreg + tid; e < hi; e += NR) put(d.pb_buf2[e]);
+    __syncthreads();
+    // each run sorted by initiator (the network bits are the same within a run)
+    if (live) {
+      const int runs[2][2] = {{ro0, ro0 + co}, {rr0, rr0 + cr}};
+      for (int r = 0; r < 2; ++r) {
+        const int a = runs[r][0], b = runs[r][1];
+        for (int y0 = a + 1; y0 < b; ++y0) {
+          const uint32_t v = (uint32_t)out[y0];
+          int y = y0 - 1;
+          while (y >= a && (uint32_t)out[y] > v) {
+            out[y + 1] = out[y];
+            --y;
+          }
+          out[y + 1] = (int)v;
+        }
+      }
+    }
   };
-#pragma unroll
-  for (int j = 0; j < PB_ROWS_PER; ++j)
-    if (j * NR + tid < nreg) put(x[j]);
-  for (int e = lo + nreg + tid; e < hi; e += NR) put(d.pb_buf2[e]);
-  __syncthreads();
-  // each run sorted by initiator (the network bits are the same within a run)
-  if (live) {
-    const int runs[2][2] = {{ro0, ro0 + co}, {rr0, rr0 + cr}};
-    for (int r = 0; r < 2; ++r) {
-      const int a = runs[r][0], b = runs[r][1];
-      for (int y0 = a + 1; y0 < b; ++y0) {
-        const uint32_t v = (uint32_t)out[y0];
-        int y = y0 - 1;
-        while (y >= a && (uint32_t)out[y] > v) {
-          out[y + 1] = out[y];
-          --y;
-        }
-        out[y + 1] = (int)v;
-      }
-    }
+  if (!staged) {
+    lay_out(d.col + base, false);
+    return;
   }
-  if (!staged) return;
+  lay_out(scol, true);
   __syncthreads();
   for (int k = tid; k < end - base; k += NR) d.col[base + k] = scol[k];
 }
