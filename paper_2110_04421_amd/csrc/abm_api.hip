@@ -380,8 +380,7 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.pb_on = !(p->flags & ABM_FLAG_CLAIM_BUILDER) && z.nb1 <= 1024 &&
             z.ccap < ((int64_t)1 << 31) && z.bcap <= 24576 &&
             N < ((int64_t)1 << 27);   // initiators fit the 27 low bits of a partition word
-  // edges of a leaf staged in LDS by the row pass: 1.1x the mean (+512); positions
-  // in the staged range take 14 bits
+  // edges of a leaf staged in LDS by the row pass: 1.1x the mean (+512), at most 64 KB
   const double leaf_mean = emean * (double)((int64_t)1 << z.lb) / (double)N;
   z.asm_cap = std::max<int64_t>(2048, std::min<int64_t>(16384, ((int64_t)(1.1 * leaf_mean) + 512 + 255) / 256 * 256));
   if (p->flags & ABM_FLAG_MIN_LDS_ROOM) {

@@ -705,15 +705,14 @@ __global__ __launch_bounds__(PB_TGRP) void k_pb_tsum(Dev d) {
 // network) in LDS; with the household sizes and own counts these give the rows'
 // degrees, whose scan after the leaf's first edge gives the row pointers.  Each lane
 // lays out its row (household, own workplace draws, received workplace, own random
-// draws, received random), writes its household part into the LDS copy of the leaf's
-// edge range, a 16-bit LDS table entry with the position of each of its own draws, and
-// the first position of each of its two received runs.  The own draws are read with
-// consecutive lanes on consecutive entries and dropped at their tabled positions; each
-// received entry takes the next position of its (row, network) run.  Each lane then
-// sorts its two runs by initiator (they are short), and the edge range leaves with
-// consecutive lanes on consecutive addresses.  A column word is the source id with the
-// network in its top two bits.  A leaf with more edges than the LDS room is laid out
-// in the column array itself.
+// draws, received random) in the LDS copy of the leaf's edge range: its household part
+// and its own draws (read from the own list, where the rows' draws follow one another,
+// so a wave reads one contiguous stretch), and the first position of each of its two
+// received runs.  Each received entry takes the next position of its (row, network)
+// run; each lane then sorts its two runs by initiator (they are short), and the edge
+// range leaves with consecutive lanes on consecutive addresses.  A column word is the
+// source id with the network in its top two bits.  A leaf with more edges than the LDS
+// room is laid out in the column array itself.
 constexpr int PB_ROWS_PER = 12;        // received entries a lane keeps in registers
 __device__ __forceinline__ int slot_delta(const Dev& d, int tix) {   // slot - agent id
   const RepInfo& ri = d.rep[d.tiles[tix].x];
@@ -723,31 +722,21 @@ __device__ __forceinline__ int slot_delta(const Dev& d, int tix) {   // slot - a
 template <int NT>
 __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   constexpr int NR = NT * TILE;
-  extern __shared__ int32_t scol[];                  // [cap] staged edges, then [cap] u16 positions
+  extern __shared__ int32_t scol[];                  // [cap] staged edges
   __shared__ int cur[2 * NR];                        // (row, network): received count, then next position
   __shared__ int wsum[NR / 64], wsum2[NR / 64];
   if (*d.flags) return;
   const int cap = d.pb_asm_cap;
-  uint16_t* pos_of = reinterpret_cast<uint16_t*>(scol + cap);
   const int L = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   cur[tid] = 0;
   cur[tid + NR] = 0;
   const int t0 = L * NT, tix = t0 + tid / TILE;      // the leaf's first tile, this lane's tile
-  const bool two = NT == 2 && t0 + 1 < d.ntiles;
   const int2 tb0 = d.pb_tbase[t0];
-  const int oend0 = tb0.y, oend = tb0.y + (two ? d.pb_tbase[t0 + 1].y : 0);
-  const uint32_t* ob = d.pb_own + (size_t)(t0 >> 2) * d.pb_bcap + tb0.x;
-  const int dl0 = slot_delta(d, t0), dl1 = two ? slot_delta(d, t0 + 1) : dl0;
+  const uint32_t* ob = d.pb_own + (size_t)(t0 >> 2) * d.pb_bcap + tb0.x;   // the leaf's own range
   const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
   const int nreg = min(hi - lo, d.pb_rper * NR);
   const int64_t b64 = d.pb_tpart[L / PB_TGRP] + d.pb_tstart[L];
-  // the first round of own draws and the leaf, loaded with the rows' own data
-  int ov[PB_UNROLL];
-#pragma unroll
-  for (int u = 0; u < PB_UNROLL; ++u) {
-    const int k = u * NR + tid;
-    ov[u] = k < oend ? (int)ob[k] : 0;
-  }
+  // the leaf's received entries, loaded with the rows' own data
   uint2 x[PB_ROWS_PER];
 #pragma unroll
   for (int j = 0; j < PB_ROWS_PER; ++j) {
@@ -768,7 +757,7 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
       sr = d.srec[i];
     }
   }
-  const int dl = tid < TILE ? dl0 : dl1;
+  const int dl = tix < d.ntiles ? slot_delta(d, tix) : 0;   // this row's replicate
   auto rkey = [](uint32_t v) { return (int)(((v & (NR - 1)) << 1) | (v >> 15)); };
   __syncthreads();                                   // counters cleared
 #pragma unroll
@@ -813,51 +802,26 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   const bool staged = end - base <= cap;
   // The layout, written once for each target so that the staged one addresses LDS
   // directly (a pointer that may be either would take the slower generic path).
-  auto lay_out = [&](auto* out, bool stg) {
+  auto lay_out = [&](auto* out) {
     int ro0 = 0, rr0 = 0;                            // first positions of the two received runs
     if (live) {
       int pos = rp0 - base;
       for (int m = sr.hh_lo; m < sr.hh_lo + (int)sr.hh_n; ++m)
         if (m != i) out[pos++] = m;
-      const int os = wb + inc - c;
-      if (stg) {
-        for (int q = 0; q < ko; ++q) pos_of[os + q] = (uint16_t)((pos + q) | (1 << 14));
-      } else {
-        for (int q = 0; q < ko; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + q] - dl), 1u);
-      }
+      // the row's own draws: consecutive entries of the leaf's own range (the lanes
+      // of a wave read one contiguous stretch of it)
+      const uint32_t* own = ob + (wb + inc - c);
+      for (int q = 0; q < ko; ++q) out[pos + q] = (int)col_word((uint32_t)((int)own[q] - dl), 1u);
       pos += ko;
       ro0 = pos;
       pos += co;
-      if (stg) {
-        for (int q = 0; q < kr; ++q) pos_of[os + ko + q] = (uint16_t)((pos + q) | (2 << 14));
-      } else {
-        for (int q = 0; q < kr; ++q) out[pos + q] = (int)col_word((uint32_t)((int)ob[os + ko + q] - dl), 2u);
-      }
+      for (int q = 0; q < kr; ++q) out[pos + q] = (int)col_word((uint32_t)((int)own[ko + q] - dl), 2u);
       pos += kr;
       rr0 = pos;
       cur[2 * tid] = ro0;
       cur[2 * tid + 1] = rr0;
     }
     __syncthreads();
-    if (stg) {                                       // own draws to their tabled positions
-      for (int kb = 0; kb < oend; kb += NR * PB_UNROLL) {
-        if (kb > 0) {
-#pragma unroll
-          for (int u = 0; u < PB_UNROLL; ++u) {
-            const int k = kb + u * NR + tid;
-            ov[u] = k < oend ? (int)ob[k] : 0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < PB_UNROLL; ++u) {
-          const int k = kb + u * NR + tid;
-          if (k < oend) {
-            const uint32_t p = pos_of[k];
-            out[p & 0x3FFFu] = (ov[u] - (k < oend0 ? dl0 : dl1)) | (int)((p >> 14) << 30);
-          }
-        }
-      }
-    }
     // received entries to the next position of their run
     auto put = [&](const uint2& v) {
       const int k = rkey(v.x);
@@ -886,10 +850,10 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
     }
   };
   if (!staged) {
-    lay_out(d.col + base, false);
+    lay_out(d.col + base);
     return;
   }
-  lay_out(scol, true);
+  lay_out(scol);
   __syncthreads();
   for (int k = tid; k < end - base; k += NR) d.col[base + k] = scol[k];
 }
@@ -908,7 +872,7 @@ const char* build_step_name(const Dev& d, int k) {
 static size_t gen_lds(const Dev& d) {
   return ((size_t)d.pb_bcap + (size_t)d.pb_bpw * ((d.pb_nb1 + 1) / 2)) * 4;
 }
-static size_t rows_lds(const Dev& d) { return (size_t)d.pb_asm_cap * 6; }
+static size_t rows_lds(const Dev& d) { return (size_t)d.pb_asm_cap * 4; }
 
 hipError_t prepare_build(const Dev& d) {
   if (!d.pb_on) return hipSuccess;
