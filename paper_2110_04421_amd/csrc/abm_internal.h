@@ -127,7 +127,7 @@ struct Dev {
   long long* prev_counts;           // [R][ABM_NC]
   long long* traj;                  // [T][R][ABM_NC]
   int32_t* day;
-  int32_t* fin_done;        // replicates whose counts k_fin_one has closed this day
+  int32_t* fin_done;        // replicates whose day k_fin_one (k_soft_finalize) has closed
   int32_t* flags;
 
   // partitioned graph builder (k_build.hip)

@@ -140,16 +140,46 @@ __global__ __launch_bounds__(TILE) void k_soft_update(Dev d, int32_t seg_slot) {
 }
 
 // Daily relaxed incidence per replicate: its tiles' partial sums in tile order.
-__global__ void k_soft_finalize(Dev d) {
-  const int t = *d.day;
-  for (int r = threadIdx.x; r < d.R; r += blockDim.x) {
-    const RepInfo& ri = d.rep[r];
-    float c = 0.f;
-    for (int k = 0; k < ri.ntiles; ++k) c += d.gpart[(size_t)(ri.tile0 + k) * ABM_N_THETA];
-    if (t < d.T) d.soft_inc[(size_t)r * d.T + t] = c;
+// Per replicate, the sums of its tiles' partials in slots [0, NQ): lane l adds tiles l,
+// l + 256, ... in order, then the lanes are added in a fixed tree (the order, and so
+// the rounding, depends only on the replicate's tile count).  out[q] on lane 0.
+template <int NQ>
+__device__ __forceinline__ void rep_sums(const Dev& d, const RepInfo& ri, float (*red)[NQ], float* out) {
+  float acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
+  for (int m = threadIdx.x; m < ri.ntiles; m += TILE) {
+    const float* g = d.gpart + (size_t)(ri.tile0 + m) * ABM_N_THETA;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += g[q];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+    if (lane == 0) red[wv][q] = acc[q];
   }
   __syncthreads();
-  if (threadIdx.x == 0) *d.day = t + 1;
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+// One workgroup per replicate; the last to finish advances the day (every workgroup
+// has read it by then).
+__global__ __launch_bounds__(TILE) void k_soft_finalize(Dev d) {
+  __shared__ float red[TILE / 64][1];
+  const int r = blockIdx.x;
+  const int t = *d.day;
+  float c;
+  rep_sums<1>(d, d.rep[r], red, &c);
+  if (threadIdx.x == 0) {
+    if (t < d.T) d.soft_inc[(size_t)r * d.T + t] = c;
+    if (atomicAdd(d.fin_done, 1) == (int)gridDim.x - 1) {
+      *d.fin_done = 0;
+      *d.day = t + 1;
+    }
+  }
 }
 
 // Checkpoint slot k = susceptible mass + the exposure ring.
@@ -216,14 +246,15 @@ __global__ __launch_bounds__(TILE) void k_adj_day(Dev d, int32_t t, int32_t seg_
   }
 }
 
-__global__ void k_adj_theta(Dev d) {
-  for (int k = threadIdx.x; k < d.R * ABM_N_THETA; k += blockDim.x) {
-    const int r = k / ABM_N_THETA, q = k % ABM_N_THETA;
-    const RepInfo& ri = d.rep[r];
-    float g = 0.f;
-    for (int m = 0; m < ri.ntiles; ++m) g += d.gpart[(size_t)(ri.tile0 + m) * ABM_N_THETA + q];
-    d.gtheta[k] += g;
-  }
+// One workgroup per replicate: the day's gradient partials of its tiles, added to dθ.
+__global__ __launch_bounds__(TILE) void k_adj_theta(Dev d) {
+  __shared__ float red[TILE / 64][ABM_N_THETA];
+  const int r = blockIdx.x;
+  float g[ABM_N_THETA];
+  rep_sums<ABM_N_THETA>(d, d.rep[r], red, g);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < ABM_N_THETA; ++q) d.gtheta[(size_t)r * ABM_N_THETA + q] += g[q];
 }
 
 static unsigned grid_for(int64_t n) {
@@ -246,7 +277,7 @@ void launch_soft_update(const Dev& d, int32_t seg_slot, hipStream_t s) {
   hipLaunchKernelGGL(k_soft_update, dim3(d.ntiles), dim3(TILE), 0, s, d, seg_slot);
 }
 void launch_soft_finalize(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_soft_finalize, dim3(1), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_soft_finalize, dim3(d.R), dim3(TILE), 0, s, d);
 }
 void launch_soft_ckpt_save(const Dev& d, int32_t k, hipStream_t s) {
   hipLaunchKernelGGL(k_soft_ckpt, dim3(grid_for((int64_t)(WIN + 1) * d.N)), dim3(TILE), 0, s, d, k, 0);
@@ -262,7 +293,7 @@ void launch_adj_day(const Dev& d, int32_t t, int32_t seg_slot, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_day, dim3(d.ntiles), dim3(TILE), 0, s, d, t, seg_slot);
 }
 void launch_adj_theta(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_adj_theta, dim3(d.R), dim3(TILE), 0, s, d);
 }
 void launch_adj_ibar(const Dev& d, int32_t t, hipStream_t s) {
   const int slot = ((t % WIN) + WIN) % WIN;
