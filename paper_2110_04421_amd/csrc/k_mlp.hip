@@ -124,12 +124,19 @@ __global__ void k_copy_f32(const float* x, float* y, int64_t n) {
 }
 
 // Column sums of an FP32 [rows][cols] matrix, rows in order.
-__global__ void k_colsum(const float* x, int rows, int cols, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// Column sums (bias gradients): a workgroup takes 64 columns; wave w adds rows w,
+// w + 4, ... of its lane's column (each load a coalesced 256-byte row piece), and the
+// four wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(const float* x, int rows, int cols, float* out) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += x[(int64_t)r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int r = wv; r < rows; r += 4) s += x[(int64_t)r * cols + c];
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && c < cols) out[c] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // dY = 2 (y - t) / (B n_out) on the first n_out outputs, 0 elsewhere; loss = mean
@@ -358,7 +365,7 @@ int abm_mlp_backward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float
   g = plain(256, 256, B);
   g.sam = 1; g.sak = 256; g.sbn = 1; g.sbk = 256; g.C = G + OW2;
   gemm(g, (const float*)w.dh2, (const uint16_t*)w.h1, s);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, (const float*)w.dh2, B, 256, G + OB2);
+  hipLaunchKernelGGL(k_colsum, dim3(4), dim3(256), 0, s, (const float*)w.dh2, B, 256, G + OB2);
   // dH1 = (dH2 W2) * [H1 > 0]
   g = plain(B, 256, 256);
   g.sam = 256; g.sak = 1; g.sbn = 1; g.sbk = 256; g.mask = w.h1; g.C = w.dh1;
@@ -367,7 +374,7 @@ int abm_mlp_backward(void* d_ws, size_t ws_bytes, const uint16_t* P, const float
   g = plain(256, 192, B);
   g.sam = 1; g.sak = 256; g.sbn = 1; g.sbk = 192; g.C = G + OW1;
   gemm(g, (const float*)w.dh1, (const uint16_t*)w.xb, s);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, (const float*)w.dh1, B, 256, G + OB1);
+  hipLaunchKernelGGL(k_colsum, dim3(4), dim3(256), 0, s, (const float*)w.dh1, B, 256, G + OB1);
   return hipGetLastError() == hipSuccess ? ABM_OK : ABM_E_HIP;
 }
 
