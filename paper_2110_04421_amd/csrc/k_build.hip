@@ -84,23 +84,6 @@ __device__ __forceinline__ Gen gen_rand(const Dev& d, const RepInfo& ri, uint32_
   return g;
 }
 
-// For u < U: a[u] = the last j < n with s[j] <= g0 + u * gs, where s is nondecreasing
-// over [0, n), s[0] <= every query and n <= NMAX (a power of two).  The U searches go
-// in lockstep, so each step's U LDS reads are independent of one another.
-template <int U, int NMAX>
-__device__ __forceinline__ void last_le(const int* s, int n, int g0, int gs, int* a) {
-#pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = 0;
-#pragma unroll
-  for (int h = NMAX / 2; h > 0; h >>= 1) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int m = a[u] + h;
-      if (m < n && s[m] <= g0 + u * gs) a[u] = m;
-    }
-  }
-}
-
 // The generation pass streams the static records in and its own lists out with
 // nontemporal accesses, so that they do not displace the workplace member lists that
 // its partner draws read at random.
