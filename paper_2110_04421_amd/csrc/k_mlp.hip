@@ -30,6 +30,31 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 __device__ __forceinline__ uint16_t load_bf16(const float* p, int64_t o) { return to_bf16(p[o]); }
 __device__ __forceinline__ uint16_t load_bf16(const uint16_t* p, int64_t o) { return p[o]; }
 
+// Eight consecutive elements p[o .. o + 8) (o a multiple of 8) as BF16, or zeros.
+__device__ __forceinline__ uint4 load8(const uint16_t* p, int64_t o, bool ok) {
+  return ok ? *reinterpret_cast<const uint4*>(p + o) : make_uint4(0u, 0u, 0u, 0u);
+}
+__device__ __forceinline__ uint4 load8(const float* p, int64_t o, bool ok) {
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+  if (ok) {
+    a = *reinterpret_cast<const float4*>(p + o);
+    b = *reinterpret_cast<const float4*>(p + o + 4);
+  }
+  return make_uint4((uint32_t)to_bf16(a.x) | ((uint32_t)to_bf16(a.y) << 16),
+                    (uint32_t)to_bf16(a.z) | ((uint32_t)to_bf16(a.w) << 16),
+                    (uint32_t)to_bf16(b.x) | ((uint32_t)to_bf16(b.y) << 16),
+                    (uint32_t)to_bf16(b.z) | ((uint32_t)to_bf16(b.w) << 16));
+}
+// The eight values down a column of an LDS tile: dst[q * GK] = value q.
+__device__ __forceinline__ void store_col(uint16_t* dst, const uint4& v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    dst[(2 * q) * GK] = (uint16_t)(w[q] & 0xFFFFu);
+    dst[(2 * q + 1) * GK] = (uint16_t)(w[q] >> 16);
+  }
+}
+
 struct Gemm {
   int M, N, K;
   int64_t sam, sak;          // A(m, k) = A[m * sam + k * sak]
@@ -40,6 +65,8 @@ struct Gemm {
   const uint16_t* mask;      // bf16 [M][N] (row stride N): multiply by (mask > 0)
   float* C;                  // fp32 out [M][N] (row stride N) or null
   uint16_t* Cb;              // bf16 out [M][N] or null
+  int avec, bvec;            // staging form of A, B: 1 rows contiguous in k, 2 contiguous
+                             // along the rows, 0 element by element (set by gemm())
 };
 
 template <typename TA, typename TB>
@@ -54,21 +81,39 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g, const TA* A, const TB* B) 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // staging: thread -> (row r = tid / 4, k chunk c = (tid % 4) * 8)
+  // staging: thread -> (row r = tid / 4, k chunk c = (tid % 4) * 8).  An operand whose
+  // rows are contiguous in k (vec 1) is loaded 8 elements at a time along a row; one
+  // contiguous along the rows (vec 2: 8 rows of one k) is loaded 8 rows at a time with
+  // thread -> (k = tid / 8, row chunk (tid % 8) * 8) and stored down the tile's column.
   const int sr = threadIdx.x >> 2, sc = (threadIdx.x & 3) * 8;
+  const int tk = threadIdx.x >> 3, tc = (threadIdx.x & 7) * 8;
   for (int k0 = 0; k0 < g.K; k0 += GK) {
     {
-      const int m = m0 + sr;
+      if (g.avec == 1) {
+        const int m = m0 + sr, k = k0 + sc;
+        *reinterpret_cast<uint4*>(&As[sr][sc]) = load8(A, (int64_t)m * g.sam + k, m < g.M && k < g.K);
+      } else if (g.avec == 2) {
+        const int m = m0 + tc, k = k0 + tk;
+        store_col(&As[tc][tk], load8(A, (int64_t)m + (int64_t)k * g.sak, m < g.M && k < g.K));
+      } else {
+        const int m = m0 + sr, k = k0 + sc;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + sc + q;
-        As[sr][sc + q] = (m < g.M && k < g.K) ? load_bf16(A, (int64_t)m * g.sam + (int64_t)k * g.sak) : (uint16_t)0;
+        for (int q = 0; q < 8; ++q)
+          As[sr][sc + q] = (m < g.M && k + q < g.K) ? load_bf16(A, (int64_t)m * g.sam + (int64_t)(k + q) * g.sak)
+                                                     : (uint16_t)0;
       }
-      const int n = n0 + sr;
+      if (g.bvec == 1) {
+        const int n = n0 + sr, k = k0 + sc;
+        *reinterpret_cast<uint4*>(&Bs[sr][sc]) = load8(B, (int64_t)n * g.sbn + k, n < g.N && k < g.K);
+      } else if (g.bvec == 2) {
+        const int n = n0 + tc, k = k0 + tk;
+        store_col(&Bs[tc][tk], load8(B, (int64_t)n + (int64_t)k * g.sbk, n < g.N && k < g.K));
+      } else {
+        const int n = n0 + sr, k = k0 + sc;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + sc + q;
-        Bs[sr][sc + q] = (n < g.N && k < g.K) ? load_bf16(B, (int64_t)n * g.sbn + (int64_t)k * g.sbk) : (uint16_t)0;
+        for (int q = 0; q < 8; ++q)
+          Bs[sr][sc + q] = (n < g.N && k + q < g.K) ? load_bf16(B, (int64_t)n * g.sbn + (int64_t)(k + q) * g.sbk)
+                                                     : (uint16_t)0;
       }
     }
     __syncthreads();
@@ -106,7 +151,13 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g, const TA* A, const TB* B) 
 }
 
 template <typename TA, typename TB>
-void gemm(const Gemm& g, const TA* A, const TB* B, hipStream_t s) {
+void gemm(const Gemm& g0, const TA* A, const TB* B, hipStream_t s) {
+  Gemm g = g0;
+  const auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  g.avec = !al(A) ? 0 : (g.sak == 1 && g.sam % 8 == 0 && g.K % 8 == 0) ? 1
+           : (g.sam == 1 && g.sak % 8 == 0 && g.M % 8 == 0) ? 2 : 0;
+  g.bvec = !al(B) ? 0 : (g.sbk == 1 && g.sbn % 8 == 0 && g.K % 8 == 0) ? 1
+           : (g.sbn == 1 && g.sbk % 8 == 0 && g.N % 8 == 0) ? 2 : 0;
   dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
   hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, g, A, B);
 }
@@ -116,11 +167,11 @@ __global__ void k_to_bf16(const float* x, uint16_t* y, int64_t n) {
   if (i < n) y[i] = to_bf16(x[i]);
 }
 
-__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
-
-__global__ void k_copy_f32(const float* x, float* y, int64_t n) {
+// y = x, and the batch size recorded in the workspace header (one lane)
+__global__ void k_copy_f32(const float* x, float* y, int64_t n, int32_t* hdr, int32_t B) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
+  if (i == 0) *hdr = B;
 }
 
 // Column sums of an FP32 [rows][cols] matrix, rows in order.
@@ -282,8 +333,7 @@ hipError_t enqueue_forward(const MlpWs& w, const uint16_t* P, const float* d_x, 
   g.bias = P + OB3; g.C = w.y;
   gemm(g, (const uint16_t*)w.h2, P + OW3, s);
   hipLaunchKernelGGL(k_copy_f32, dim3(blocks((int64_t)B * 16)), dim3(256), 0, s, (const float*)w.y, d_y,
-                     (int64_t)B * 16);
-  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, w.hdr, B);
+                     (int64_t)B * 16, w.hdr, B);
   return hipGetLastError();
 }
 
