@@ -29,7 +29,7 @@
 namespace abm {
 
 constexpr int PB_THREADS = 1024;       // P1/P2 workgroup: one batch of 4 tiles at a time
-constexpr int PB_UNROLL = 8;           // loads a lane issues before using them (P2, P6)
+constexpr int PB_UNROLL = 8;           // loads a lane issues before using them (P2, P3)
 constexpr int PB_CHUNK = 8192;         // entries per level-2 chunk (sorted in LDS)
 constexpr int PB_NB1_MAX = 1024;       // level-1 digits
 

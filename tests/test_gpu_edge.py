@@ -1,7 +1,7 @@
 """Degenerate and ragged inputs on the GPU against the FP64 oracle: replicates of 1 to
 1,000 agents that straddle tile boundaries (single-agent replicates and workplaces
 draw no partners), households of the largest size (255 members: tiles far beyond the
-assembly's LDS room), and no initial infections."""
+row pass's LDS room), and no initial infections."""
 import dataclasses
 
 import numpy as np
