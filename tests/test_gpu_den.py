@@ -4,7 +4,7 @@ the uninterrupted run; graph replay and eager launches agree."""
 import numpy as np
 import pytest
 
-from helpers import require_gpu
+from helpers import require_gpu, lockstep
 from oracle import step as ostep
 from synthpop import workload
 from synthpop.configs import TEST_TYPES
@@ -29,9 +29,11 @@ def test_notification_lockstep_with_interventions():
     assert traj[:, 0, ostep.C_NOTIFIED].sum() > 50
 
 
-def test_notification_batched_and_course_lockstep():
+@pytest.mark.parametrize("two", [False, True])
+def test_notification_batched_and_course_lockstep(two):
+    """Two-tile leaves build the day's graph into the ring slot as one-tile leaves do."""
     p, pop = workload(3, n=30000, n_rep=4, n_steps=30, disease_model=1, **DEN)
-    _lockstep(p, pop, 30)
+    lockstep(lambda p_, pop_, **kw: _sim(p_, pop_, two_tile_leaves=two, **kw), p, pop, 30)
 
 
 def test_resume_with_notification_equals_uninterrupted():

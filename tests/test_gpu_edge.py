@@ -7,26 +7,30 @@ import dataclasses
 import numpy as np
 import pytest
 
-from helpers import require_gpu, lam_close
+from helpers import require_gpu, lam_close, lockstep
 from oracle import graph as og
 from oracle import step as ostep
 from synthpop import make_population
 from synthpop.configs import params_for
-from test_gpu_parity import _lockstep
+from test_gpu_parity import _sim
 
 pytestmark = pytest.mark.gpu
 
 
-def test_ragged_replicates_with_interventions_in_lockstep():
+@pytest.mark.parametrize("two", [False, True])
+def test_ragged_replicates_with_interventions_in_lockstep(two):
+    """With two-tile leaves, most leaves hold the ragged tiles of two replicates."""
     require_gpu()
     sizes = [1, 2, 3, 63, 64, 65, 255, 256, 257, 1000]
     pop = make_population(sizes, workplaces=True, n_seeds=[min(2, n) for n in sizes], pop_seed=5)
     p = params_for(1, n_steps=12, vacc_trigger=0.0, vacc_rate=0.05)
-    near, worst = _lockstep(p, pop, 12, check_csr_every=1)
+    near, worst, _ = lockstep(lambda p_, pop_, **kw: _sim(p_, pop_, two_tile_leaves=two, **kw), p, pop, 12,
+                              check_csr_every=1)
     assert worst < 1e-5
 
 
-def test_largest_households_overflow_a_tile_room():
+@pytest.mark.parametrize("two", [False, True])
+def test_largest_households_overflow_a_tile_room(two):
     require_gpu()
     from paper_2110_04421_amd.sim import Simulator
     from paper_2110_04421_amd._lib import AbmError
@@ -36,7 +40,7 @@ def test_largest_households_overflow_a_tile_room():
     hs = np.union1d(hs[(hs <= big[0]) | (hs >= big[-1])], big)
     pop = dataclasses.replace(base, hh_start=hs.astype(np.int32))
     p = params_for(1, n_steps=3)
-    with Simulator(p, pop) as s:
+    with Simulator(p, pop, two_tile_leaves=two) as s:
         s.run(1)
         rp, col, w = s.csr()
         lam = s.lam()
