@@ -111,7 +111,7 @@ __device__ __forceinline__ void put_b1(const Dev& d, int pos, uint32_t p, uint32
 // level-1 histograms (16-bit counters in LDS for all the workgroup's batches) are
 // stored digit-major (digit * nbatch + batch) for the scan.
 __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_pb_gen(Dev d) {
-  extern __shared__ uint32_t stage[];        // [pb_bcap] draws, then [pb_bpw][nh2] histograms
+  extern __shared__ __attribute__((aligned(16))) uint32_t stage[];   // [pb_bcap] draws, then [pb_bpw][nh2] histograms
   __shared__ uint32_t T[NPT * 64];
   __shared__ int wsum[PB_THREADS / 64], wdeg[PB_THREADS / 64];
   __shared__ int ntot;
@@ -207,8 +207,13 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       });
     }
     __syncthreads();
+    // the batch's own list (it starts on a 16-byte boundary) in 16-byte stores
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
     uint32_t* dst = d.pb_own + (size_t)bt * d.pb_bcap;
-    for (int k = tid; k < n; k += PB_THREADS) __builtin_nontemporal_store(stage[k], dst + k);
+    const int nv = n >> 2;
+    for (int v = tid; v < nv; v += PB_THREADS)
+      __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(stage + 4 * v), reinterpret_cast<v4u*>(dst) + v);
+    for (int k = 4 * nv + tid; k < n; k += PB_THREADS) __builtin_nontemporal_store(stage[k], dst + k);
     __syncthreads();
   }
   // the workgroup's histograms, digit-major: each digit's batches are consecutive
@@ -838,7 +843,15 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   }
   lay_out(scol);
   __syncthreads();
-  for (int k = tid; k < end - base; k += NR) d.col[base + k] = scol[k];
+  // the staged range leaves in 16-byte stores between its first and last 16-byte
+  // boundaries in the column array (the array itself starts on one)
+  const int n = end - base, head = min(n, (4 - (base & 3)) & 3), nv = (n - head) >> 2;
+  if (tid < head) d.col[base + tid] = scol[tid];
+  for (int v = tid; v < nv; v += NR) {
+    const int k = head + 4 * v;
+    *reinterpret_cast<int4*>(d.col + base + k) = make_int4(scol[k], scol[k + 1], scol[k + 2], scol[k + 3]);
+  }
+  for (int k = head + 4 * nv + tid; k < n; k += NR) d.col[base + k] = scol[k];
 }
 
 // Named steps of a day's graph build.  With the partitioned builder off (populations
