@@ -243,28 +243,35 @@ __global__ __launch_bounds__(TILE) void k_pb_s1a(Dev d) {
 }
 
 // Exclusive scan of nparts block sums in place (one workgroup); total to parts[nparts].
+// Each lane takes a contiguous run of ceil(nparts / 1024) sums; the run totals are
+// scanned with wave shuffles and one barrier.
 __global__ __launch_bounds__(1024) void k_pb_parts(int64_t* parts, int nparts) {
-  __shared__ int64_t buf[1024];
-  __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int b0 = 0; b0 < nparts; b0 += 1024) {
-    const int b = b0 + threadIdx.x;
-    const int64_t v = b < nparts ? parts[b] : 0;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-      __syncthreads();
-      buf[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (b < nparts) parts[b] = carry + buf[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += buf[1023];
-    __syncthreads();
+  __shared__ int64_t wsum[1024 / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per = (nparts + 1023) / 1024, q0 = (int)threadIdx.x * per;
+  int64_t s = 0;
+  for (int k = 0; k < per; ++k)
+    if (q0 + k < nparts) s += parts[q0 + k];
+  int64_t inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
-  if (threadIdx.x == 0) parts[nparts] = carry;
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int64_t run = 0, tot = 0;
+  for (int q = 0; q < 1024 / 64; ++q) {
+    if (q < wv) run += wsum[q];
+    tot += wsum[q];
+  }
+  run += inc - s;
+  for (int k = 0; k < per; ++k)
+    if (q0 + k < nparts) {
+      const int64_t v = parts[q0 + k];
+      parts[q0 + k] = run;
+      run += v;
+    }
+  if (threadIdx.x == 0) parts[nparts] = tot;
 }
 
 __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
@@ -297,24 +304,32 @@ __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
 // Bucket bounds and the level-2 chunk table (one workgroup; nb1 <= 1024).
 __device__ void buckets_body(const Dev& d, int64_t total) {
   __shared__ int nch[PB_NB1_MAX + 1];
+  __shared__ int wsum[1024 / 64];
   __shared__ int ok;
-  const int b = threadIdx.x;
-  int start = 0, size = 0;
+  const int b = threadIdx.x, lane = b & 63, wv = b >> 6;
+  int start = 0, size = 0, n = 0;
   if (b < d.pb_nb1) {
     start = d.pb_hist1[(size_t)b * d.pb_nbatch];
     const int64_t end = b + 1 < d.pb_nb1 ? (int64_t)d.pb_hist1[(size_t)(b + 1) * d.pb_nbatch] : total;
     size = (int)(end - start);
     d.pb_bstart[b] = start;
-    nch[b] = (size + PB_CHUNK - 1) / PB_CHUNK;
+    n = (size + PB_CHUNK - 1) / PB_CHUNK;
   }
+  // each bucket's first chunk: a workgroup scan of the chunk counts
+  int inc = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
+  int wb = 0, c = 0;
+  for (int q = 0; q < 1024 / 64; ++q) {
+    if (q < wv) wb += wsum[q];
+    c += wsum[q];
+  }
+  if (b < d.pb_nb1) nch[b] = wb + inc - n;
   if (threadIdx.x == 0) {
-    int c = 0;
-    for (int k = 0; k < d.pb_nb1; ++k) {
-      const int n = nch[k];
-      nch[k] = c;
-      c += n;
-    }
     nch[d.pb_nb1] = c;
     *d.pb_nchunks = c;
     d.pb_hist1[(size_t)d.pb_nb1 * d.pb_nbatch] = (int)total;   // end of the last run
