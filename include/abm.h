@@ -122,6 +122,11 @@ enum {
                                       leaves of two tiles (512 rows) at any population
                                       size, as it does by itself beyond 2^25 agents; the
                                       graph is bitwise the same                          */
+#define ABM_FLAG_SEGMENT_VPLAN 512 /* test aid: plan the day's vaccination doses by
+                                      segments of 256 tiles, each summed and ranked by
+                                      its own workgroup, at any replicate size, as it is
+                                      done by itself above 2048 tiles (2^19 agents) a
+                                      replicate; the doses are the same                  */
 #define ABM_FLAG_MIN_LDS_ROOM 16 /* test aid: give the graph builder's level-1 scatter
                                     and row pass their smallest LDS and register room,
                                     so that batches and tiles are written directly and

@@ -17,6 +17,7 @@ N_AGE, N_OCC, N_THETA, N_DUR = 9, 23, 10, 9
 NEVER = -32768
 FLAG_PROFILE, FLAG_NO_GRAPH, FLAG_CLAIM_BUILDER, FLAG_AUTOTUNE, FLAG_MIN_LDS_ROOM = 1, 2, 4, 8, 16
 FLAG_DENSE_MESSAGE, FLAG_FRONTIER_ANY_SIZE, FLAG_STRAIGHT_THROUGH, FLAG_TWO_TILE_LEAVES = 32, 64, 128, 256
+FLAG_SEGMENT_VPLAN = 512
 (C_S, C_E, C_I, C_R, C_M, C_NEW, C_TESTS, C_POS, C_DOSE1, C_DOSE2, C_EDGES, C_NEAR,
  C_INF_EDGES, C_HOSP, C_ICU, C_NOTIFIED) = range(NC)
 (GET_STATE, GET_LAMBDA, GET_CODE, GET_ROWPTR, GET_COL, GET_W, GET_ATAB, GET_POISSON, GET_DAY,

@@ -97,7 +97,7 @@ struct Layout {
 
 struct Offsets {
   size_t rep, tiles, srec, age, hhn, wpm, atab, ptab, dtab, state, code, imask, cmask, scmask, lambda, own, recv, row_ptr,
-      cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, tile_counts, fin_part, prev_counts,
+      cur_occ, cur_rand, col, scan_part, vhist, vplan, vtile, latch, vpart, vsegbase, tile_counts, fin_part, prev_counts,
       traj, day, flags, seeds, ring_rp, ring_col, den_mask, rmask, ninf, work, nwork;
   size_t pb_hist1, pb_own, pb_tbase, pb_part, pb_bstart, pb_bchunk, pb_nchunks, pb_chunks, pb_hist2, pb_leaf, pb_b1h,
       pb_b1w, pb_buf2, pb_tdeg, pb_tstart, pb_tpart;
@@ -111,7 +111,7 @@ struct Sizes {
   // partitioned builder
   int64_t pb_on = 0, lb = 0, nlv = 0, nb1 = 0, nbatch = 0, bpw = 1, ngrid = 0, bcap = 0, s1_nparts = 0, maxch = 0, nleaf = 0, ccap = 0;
   int64_t asm_cap = 0, s1_cap = PB_S1_CAP, rper = 12;
-  int64_t fseg = 1, fin_one = 0;
+  int64_t fseg = 1, fin_one = 0, vseg = 0;
 };
 
 // element strides of the notification ring's slots, rounded to 64 elements so that
@@ -321,6 +321,9 @@ int validate(const abm_params* p, const abm_population* pop, Sizes& z, std::stri
   z.fseg = std::max<int64_t>(1, std::min<int64_t>(256, (max_rep_tiles + 255) / 256));
   // up to 2048 tiles a replicate, one launch reduces and closes the day
   z.fin_one = max_rep_tiles <= 2048;
+  // vaccination plan: above 2048 tiles a replicate, its tiles are summed and ranked in
+  // segments of 256 by their own workgroups
+  z.vseg = (max_rep_tiles <= 2048 && !(p->flags & ABM_FLAG_SEGMENT_VPLAN)) ? 0 : (max_rep_tiles + 255) / 256;
   z.nscan = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
   // Edge room: mean directed edges + 8 standard deviations of the Poisson contact count.
   double hh_edges = 0;
@@ -433,6 +436,10 @@ void layout(const Sizes& z, const abm_params& p, Offsets& o, size_t& total) {
   o.vplan = L.take<int32_t>(2 * z.R);
   o.vtile = L.take<int32_t>(z.ntiles);
   o.latch = L.take<uint8_t>(z.R);
+  if (z.vseg) {
+    o.vpart = L.take<int32_t>(z.R * z.vseg * NBUCKET);
+    o.vsegbase = L.take<int32_t>(z.R * z.vseg);
+  }
   o.tile_counts = L.take<uint32_t>(z.ntiles * TILE_NC);
   o.fin_part = L.take<unsigned long long>(z.R * z.fseg * TILE_NC);
   o.prev_counts = L.take<long long>(z.R * ABM_NC);
@@ -717,6 +724,9 @@ int abm_create(const abm_params* p, const abm_population* pop, void* d_workspace
   d.vplan = (int32_t*)(ws + o.vplan);
   d.vtile_base = (int32_t*)(ws + o.vtile);
   d.latch = (uint8_t*)(ws + o.latch);
+  d.vseg = (int32_t)z.vseg;
+  d.vpart = z.vseg ? (int32_t*)(ws + o.vpart) : nullptr;
+  d.vsegbase = z.vseg ? (int32_t*)(ws + o.vsegbase) : nullptr;
   d.tile_counts = (uint32_t*)(ws + o.tile_counts);
   d.fin_part = (unsigned long long*)(ws + o.fin_part);
   d.fseg = (int32_t)z.fseg;

@@ -120,6 +120,9 @@ struct Dev {
   int32_t* vplan;               // [R][2] partial class, quota in it
   int32_t* vtile_base;          // [ntiles]
   uint8_t* latch;               // [R]
+  int32_t vseg;                 // segments of 256 tiles per replicate; 0: one workgroup plans a replicate
+  int32_t* vpart;               // [R][vseg][NBUCKET] class totals per segment
+  int32_t* vsegbase;            // [R][vseg] first rank of each segment in the partial class
 
   uint32_t* tile_counts;            // [ntiles][TILE_NC] each day's per-tile counts
   unsigned long long* fin_part;     // [R][fseg][TILE_NC] partial sums of the tile rows

@@ -294,6 +294,41 @@ __device__ __forceinline__ bool sparse_day(const Dev& d) {
 // Latch on prevalence, then give the day's capacity to the priority classes in order;
 // the first class that does not fit entirely gets a quota filled by ascending agent id
 // (exclusive prefix of its members over the replicate's tiles).
+// The day's vaccination plan of replicate r: from the day the prevalence latch fires,
+// the capacity goes to the priority classes in order; bstar is the class where it runs
+// out and quota the doses left for it, and each tile's first rank inside bstar is the
+// number of bstar agents in the replicate's earlier tiles.  Replicates of at most
+// VPLAN_ONE tiles take one workgroup (k_vplan); larger ones are summed per segment of
+// 256 tiles (k_vsum), planned (k_vplan_seg) and ranked per segment (k_vtile), so that
+// no workgroup walks a replicate's tiles one round after another.
+// Latched today: the latch fired before, or yesterday's prevalence reaches the trigger.
+__device__ __forceinline__ bool latched_today(const Dev& d, int r) {
+  if (d.latch[r]) return true;
+  const long long* pc = d.prev_counts + (size_t)r * ABM_NC;
+  const long long ei = pc[ABM_C_E] + pc[ABM_C_I] + pc[ABM_C_HOSP] + pc[ABM_C_ICU];
+  return (double)ei >= d.vacc_trigger * (double)d.rep[r].n;
+}
+
+// bstar and quota from the class totals (thread 0); writes the plan and the latch.
+__device__ __forceinline__ void make_plan(const Dev& d, int r, const long long* tot, int* plan) {
+  const RepInfo& ri = d.rep[r];
+  long long rem = ri.cap;
+  int bstar = NBUCKET, quota = 0;
+  for (int b = 0; b < NBUCKET; ++b) {
+    if (tot[b] > rem) {
+      bstar = b;
+      quota = (int)rem;
+      break;
+    }
+    rem -= tot[b];
+  }
+  plan[0] = bstar;
+  plan[1] = quota;
+  d.vplan[2 * r] = bstar;
+  d.vplan[2 * r + 1] = quota;
+  d.latch[r] = 1;
+}
+
 __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
   __shared__ int tot[TILE / 64][NBUCKET];
   __shared__ int plan[2];
@@ -301,20 +336,7 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
   __shared__ int carry;
   const int r = blockIdx.x;
   const RepInfo& ri = d.rep[r];
-  if (threadIdx.x == 0) {
-    int latched = d.latch[r];
-    if (!latched) {
-      const long long* pc = d.prev_counts + (size_t)r * ABM_NC;
-      const long long ei = pc[ABM_C_E] + pc[ABM_C_I] + pc[ABM_C_HOSP] + pc[ABM_C_ICU];
-      if ((double)ei >= d.vacc_trigger * (double)ri.n) {
-        latched = 1;
-        d.latch[r] = 1;
-      }
-    }
-    plan[0] = latched ? 0 : -1;
-  }
-  __syncthreads();
-  if (plan[0] < 0) {
+  if (!latched_today(d, r)) {
     if (threadIdx.x == 0) {
       d.vplan[2 * r] = -1;
       d.vplan[2 * r + 1] = 0;
@@ -330,22 +352,12 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long rem = ri.cap;
-    int bstar = NBUCKET, quota = 0;
+    long long t[NBUCKET];
     for (int b = 0; b < NBUCKET; ++b) {
-      long long c = 0;
-      for (int q = 0; q < TILE / 64; ++q) c += tot[q][b];
-      if (c > rem) {
-        bstar = b;
-        quota = (int)rem;
-        break;
-      }
-      rem -= c;
+      t[b] = 0;
+      for (int q = 0; q < TILE / 64; ++q) t[b] += tot[q][b];
     }
-    plan[0] = bstar;
-    plan[1] = quota;
-    d.vplan[2 * r] = bstar;
-    d.vplan[2 * r + 1] = quota;
+    make_plan(d, r, t, plan);
     carry = 0;
   }
   __syncthreads();
@@ -368,6 +380,107 @@ __global__ __launch_bounds__(TILE) void k_vplan(Dev d) {
     if (threadIdx.x == TILE - 1) carry += wb + inc;
     __syncthreads();
   }
+}
+
+// Segment s (tiles 256 s ..) of replicate r: its class totals, one lane per tile.
+__global__ __launch_bounds__(TILE) void k_vsum(Dev d) {
+  __shared__ int tot[TILE / 64][NBUCKET];
+  const int s = blockIdx.x, r = blockIdx.y;
+  const RepInfo& ri = d.rep[r];
+  if (256 * s >= ri.ntiles || !latched_today(d, r)) return;
+  const int k = 256 * s + (int)threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int* h = d.vhist + (size_t)(ri.tile0 + k) * NBUCKET;
+#pragma unroll
+  for (int b = 0; b < NBUCKET; ++b) {
+    int v = k < ri.ntiles ? h[b] : 0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) tot[wv][b] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET) {
+    const int b = threadIdx.x;
+    d.vpart[((size_t)r * d.vseg + s) * NBUCKET + b] = (tot[0][b] + tot[1][b]) + (tot[2][b] + tot[3][b]);
+  }
+}
+
+// The plan of replicate r from its segments' totals, and each segment's first rank in
+// bstar (a scan over the segments, 1024 at a time).
+__global__ __launch_bounds__(1024) void k_vplan_seg(Dev d) {
+  __shared__ long long tot[1024 / 64][NBUCKET];
+  __shared__ int plan[2];
+  __shared__ int wsum[1024 / 64];
+  __shared__ int carry;
+  const int r = blockIdx.x;
+  const RepInfo& ri = d.rep[r];
+  if (!latched_today(d, r)) {
+    if (threadIdx.x == 0) {
+      d.vplan[2 * r] = -1;
+      d.vplan[2 * r + 1] = 0;
+    }
+    return;
+  }
+  const int nseg = (ri.ntiles + 255) / 256;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int* vp = d.vpart + (size_t)r * d.vseg * NBUCKET;
+  for (int b = 0; b < NBUCKET; ++b) {
+    long long v = 0;
+    for (int s = threadIdx.x; s < nseg; s += 1024) v += vp[(size_t)s * NBUCKET + b];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) tot[wv][b] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t[NBUCKET];
+    for (int b = 0; b < NBUCKET; ++b) {
+      t[b] = 0;
+      for (int q = 0; q < 1024 / 64; ++q) t[b] += tot[q][b];
+    }
+    make_plan(d, r, t, plan);
+    carry = 0;
+  }
+  __syncthreads();
+  const int bstar = plan[0];
+  if (bstar >= NBUCKET) return;
+  for (int s0 = 0; s0 < nseg; s0 += 1024) {
+    const int s = s0 + (int)threadIdx.x;
+    const int v = s < nseg ? vp[(size_t)s * NBUCKET + bstar] : 0;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int q = 0; q < wv; ++q) wb += wsum[q];
+    if (s < nseg) d.vsegbase[(size_t)r * d.vseg + s] = carry + wb + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += wb + inc;
+    __syncthreads();
+  }
+}
+
+// Each tile's first rank in bstar: its segment's base plus a scan inside the segment.
+__global__ __launch_bounds__(TILE) void k_vtile(Dev d) {
+  __shared__ int wsum[TILE / 64];
+  const int s = blockIdx.x, r = blockIdx.y;
+  const RepInfo& ri = d.rep[r];
+  const int bstar = d.vplan[2 * r];
+  if (256 * s >= ri.ntiles || bstar < 0 || bstar >= NBUCKET) return;
+  const int k = 256 * s + (int)threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int v = k < ri.ntiles ? d.vhist[(size_t)(ri.tile0 + k) * NBUCKET + bstar] : 0;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int q = 0; q < wv; ++q) wb += wsum[q];
+  if (k < ri.ntiles) d.vtile_base[ri.tile0 + k] = d.vsegbase[(size_t)r * d.vseg + s] + wb + inc - v;
 }
 
 // ---- force of infection: lambda_j = coef[a_j] * sum_{e in row j} w_e * Atab[code[src_e]]
@@ -1059,7 +1172,13 @@ void launch_mask(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_mask, dim3((nfw + MASK_T - 1) / MASK_T), dim3(MASK_T), 0, s, d);
 }
 void launch_vplan(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
+  if (d.vseg == 0) {
+    hipLaunchKernelGGL(k_vplan, dim3(d.R), dim3(TILE), 0, s, d);
+    return;
+  }
+  hipLaunchKernelGGL(k_vsum, dim3(d.vseg, d.R), dim3(TILE), 0, s, d);
+  hipLaunchKernelGGL(k_vplan_seg, dim3(d.R), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_vtile, dim3(d.vseg, d.R), dim3(TILE), 0, s, d);
 }
 // Message-kernel variants the autotuner chooses from: LDS chunk x grid shape x where
 // the first mask level lives (L2, or LDS for persistent grids when it fits) x tiles per

@@ -36,13 +36,16 @@ class Simulator:
     ``frontier_any_size`` (a test aid) allows that path at any population size;
     ``straight_through`` (relaxed mode) takes the hard infection draw forward and the
     relaxed sample's derivative in the adjoint; ``two_tile_leaves`` (a test aid) gives
-    the graph builder the two-tile leaves it takes by itself beyond 2^25 agents.
+    the graph builder the two-tile leaves it takes by itself beyond 2^25 agents;
+    ``segment_vplan`` (a test aid) plans the vaccination doses by segments of 256 tiles,
+    as is done by itself above 2^19 agents a replicate.
     """
 
     def __init__(self, params: dict, pop, *, profile: bool = False, graph: bool = True,
                  claim_builder: bool = False, autotune: bool = False, min_lds_room: bool = False,
                  dense_message: bool = False, frontier_any_size: bool = False,
-                 straight_through: bool = False, two_tile_leaves: bool = False, stream=None):
+                 straight_through: bool = False, two_tile_leaves: bool = False,
+                 segment_vplan: bool = False, stream=None):
         torch = _torch()
         self._lib = L.lib()
         flags = ((L.FLAG_PROFILE if profile else 0) | (0 if graph else L.FLAG_NO_GRAPH)
@@ -52,7 +55,8 @@ class Simulator:
                  | (L.FLAG_DENSE_MESSAGE if dense_message else 0)
                  | (L.FLAG_FRONTIER_ANY_SIZE if frontier_any_size else 0)
                  | (L.FLAG_STRAIGHT_THROUGH if straight_through else 0)
-                 | (L.FLAG_TWO_TILE_LEAVES if two_tile_leaves else 0))
+                 | (L.FLAG_TWO_TILE_LEAVES if two_tile_leaves else 0)
+                 | (L.FLAG_SEGMENT_VPLAN if segment_vplan else 0))
         self.params = dict(params)
         self._p = L.make_params(params, flags)
         self._pop, self._keep = L.make_population(pop)

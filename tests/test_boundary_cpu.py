@@ -147,7 +147,8 @@ def test_header_constants_match_the_binding(tmp_path):
              "ABM_FLAG_CLAIM_BUILDER": L.FLAG_CLAIM_BUILDER, "ABM_FLAG_AUTOTUNE": L.FLAG_AUTOTUNE,
              "ABM_FLAG_MIN_LDS_ROOM": L.FLAG_MIN_LDS_ROOM, "ABM_FLAG_DENSE_MESSAGE": L.FLAG_DENSE_MESSAGE,
              "ABM_FLAG_FRONTIER_ANY_SIZE": L.FLAG_FRONTIER_ANY_SIZE,
-             "ABM_FLAG_TWO_TILE_LEAVES": L.FLAG_TWO_TILE_LEAVES, "ABM_DISEASE_COURSE": L.COURSE,
+             "ABM_FLAG_TWO_TILE_LEAVES": L.FLAG_TWO_TILE_LEAVES,
+             "ABM_FLAG_SEGMENT_VPLAN": L.FLAG_SEGMENT_VPLAN, "ABM_DISEASE_COURSE": L.COURSE,
              "ABM_IMMUNITY_ASYMPTOMATIC": 1}
     src = tmp_path / "k.c"
     body = "".join(f'printf("%ld\\n", (long)({n}));' for n in names)

@@ -126,6 +126,34 @@ def test_lockstep_strategies_and_dropout():
         _lockstep(p, pop, 40, graph=False)
 
 
+def test_lockstep_segmented_vaccination_plan():
+    """The plan the path takes above 2048 tiles a replicate (forced here): replicates of
+    several 256-tile segments, one ragged, with the capacity running out inside a
+    priority class on most days."""
+    p, pop = workload(3, n=150000, n_rep=2, n_steps=15, vacc_trigger=0.0, vacc_rate=0.02,
+                      strategy=1)
+    p["dose_lag"] = 3
+    nt = np.diff(np.asarray(pop.agent_offset)) // 256
+    assert nt.max() > 256
+    _, _, doses = lockstep(lambda p_, pop_, **kw: _sim(p_, pop_, segment_vplan=True, **kw),
+                           p, pop, 15)
+    assert (doses[..., 0] > 0).all()
+
+
+@pytest.mark.parametrize("strat", [0, 1, 2])
+def test_segmented_vaccination_plan_equals_one_workgroup(strat):
+    p, pop = workload(3, n=400000, n_rep=3, n_steps=20, vacc_trigger=0.001, vacc_rate=0.01,
+                      strategy=strat)
+    out = []
+    for seg in (False, True):
+        with _sim(p, pop, segment_vplan=seg) as s:
+            out.append((s.run(20), s.state(), s.latch()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+    assert out[0][0][..., ostep.C_DOSE1].sum() > 0
+
+
 def test_batched_equals_sequential():
     p, pop = workload(3, n=60000, n_rep=6, n_steps=40, vacc_trigger=0.002)
     with _sim(p, pop) as s:
