@@ -240,6 +240,16 @@ __device__ __forceinline__ float u01(uint32_t x) {
 // Inverse-CDF Poisson count from a 32-bit word: #{k < 63 : T_k <= x}.
 // #{k < 63 : T[k] <= x} for nondecreasing thresholds: the first k with T[k] > x, capped
 // at 63, found in six uniform steps.
+// Logical index of workgroup b in a grid of G workgroups, such that the workgroups the
+// dispatcher places on one XCD (it deals them out b mod 8) take consecutive indices.
+// Kernels whose neighbouring workgroups write into the same cache lines (the ends of
+// short runs) use it, so that those lines are completed in one XCD's L2 instead of
+// leaving two partial copies to be written back from two.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, q = b >> 3, base = G >> 3, rem = G & 7;
+  return x * base + min(x, rem) + q;
+}
+
 __device__ __forceinline__ int poisson_k(const uint32_t* T, uint32_t x) {
   int lo = 0;
 #pragma unroll

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = 0; j < d.pb_bpw; ++j) {
-    const int bt = blockIdx.x * d.pb_bpw + j;
+    const int bt = xcd_block(blockIdx.x, gridDim.x) * d.pb_bpw + j;
     if (bt >= d.pb_nbatch) break;
     uint32_t* h = hist + j * nh2;
     const int tix = bt * 4 + (tid >> 8);
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     __syncthreads();
   }
   // the workgroup's histograms, digit-major: each digit's batches are consecutive
-  const int bt0 = blockIdx.x * d.pb_bpw;
+  const int bt0 = xcd_block(blockIdx.x, gridDim.x) * d.pb_bpw;
   const int nb = min(d.pb_bpw, d.pb_nbatch - bt0);
   for (int k = threadIdx.x; k < d.pb_nb1 * nb; k += PB_THREADS) {
     const int dg = k / nb, j = k - dg * nb;
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
-  const int bt0 = blockIdx.x * d.pb_bpw;
+  const int bt0 = xcd_block(blockIdx.x, gridDim.x) * d.pb_bpw;
   const int nb = min(d.pb_bpw, nbt - bt0), nb1w = nb + 1;
   // a batch's agent counts and the first PB_S1_PF rounds of its own list are loaded
   // one batch ahead, while the previous batch is sorted and written
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(PB_S2_THREADS) void k_pb_scatter2(Dev d) {
   __shared__ int cnt[256], first[256];
   __shared__ int wsum[4];
   if (*d.flags) return;
-  const int c = blockIdx.x;
+  const int c = xcd_block(blockIdx.x, gridDim.x);
   if (c >= *d.pb_nchunks) return;
   const int4 ch = d.pb_chunks[c];
   const int n = ch.z - ch.y;
