@@ -399,7 +399,6 @@ constexpr int PB_S1_PF = 10;           // own-list entries a lane loads for the 
 __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   __shared__ uint2 stage[PB_S1_CAP];
   __shared__ uint16_t tag[PB_S1_CAP];          // own-list entry -> initiator lane | network << 15
-  __shared__ int hs[PB_HS_MAX];                // run offsets: [digit][batch of the workgroup + 1]
   __shared__ int gofs[PB_NB1_MAX], lst[PB_NB1_MAX], lcur[PB_NB1_MAX];
   __shared__ int aid[PB_THREADS];
   __shared__ int wsum[PB_THREADS / 64], wsum2[PB_THREADS / 64];
@@ -408,11 +407,20 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int s1 = d.pb_lb + 8;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
-  const int bt0 = xcd_block(blockIdx.x, gridDim.x) * d.pb_bpw;
-  const int nb = min(d.pb_bpw, nbt - bt0), nb1w = nb + 1;
-  // a batch's agent counts and the first PB_S1_PF rounds of its own list are loaded
-  // one batch ahead, while the previous batch is sorted and written
-  auto fetch = [&](int bt, int& i, uint32_t& o, uint32_t* pv) {
+  // The batches of the workgroups that the dispatcher places on one XCD (it deals them
+  // out blockIdx mod 8) form one range, and its w-th workgroup takes batches w, w + cx,
+  // w + 2 cx, ... of it.  The workgroups running together on an XCD then place
+  // neighbouring batches at the same time, so the line where one batch's run for a
+  // digit ends and the next batch's begins is completed in that XCD's L2 while both
+  // are written, instead of staying open there until the next batch of the same
+  // workgroup.
+  const int G = (int)gridDim.x, x = (int)(blockIdx.x & 7), w = (int)(blockIdx.x >> 3);
+  const int cx = (G >> 3) + (x < (G & 7) ? 1 : 0), px = x * (G >> 3) + min(x, G & 7);
+  const int b0 = px * d.pb_bpw, bx = min(nbt, (px + cx) * d.pb_bpw) - b0;
+  const int nb = bx > w ? (bx - w + cx - 1) / cx : 0;
+  // a batch's agent counts, its runs' offsets and the first PB_S1_PF rounds of its own
+  // list are loaded one batch ahead, while the previous batch is sorted and written
+  auto fetch = [&](int bt, int& i, uint32_t& o, uint32_t* pv, int& g, int& e) {
     const int tix = bt * 4 + (tid >> 8);
     i = -1;
     o = 0u;
@@ -424,6 +432,10 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
         o = d.own[a];
       }
     }
+    if (tid < d.pb_nb1) {              // run (digit, bt) ends where (digit, bt + 1) starts
+      g = d.pb_hist1[(size_t)tid * nbt + bt];
+      e = d.pb_hist1[(size_t)tid * nbt + bt + 1];
+    }
     const uint32_t* src = d.pb_own + (size_t)bt * d.pb_bcap;
 #pragma unroll
     for (int u = 0; u < PB_S1_PF; ++u) {
@@ -431,16 +443,11 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       pv[u] = k < d.pb_bcap ? src[k] : 0u;
     }
   };
-  int inx;
+  int inx, gnx = 0, enx = 0;
   uint32_t onx, pvn[PB_S1_PF];
-  fetch(bt0, inx, onx, pvn);
-  for (int k = tid; k < d.pb_nb1 * nb1w; k += PB_THREADS) {
-    const int dg = k / nb1w, j = k - dg * nb1w;
-    hs[k] = d.pb_hist1[(size_t)dg * nbt + bt0 + j];
-  }
-  __syncthreads();
+  if (nb > 0) fetch(b0 + w, inx, onx, pvn, gnx, enx);
   for (int j = 0; j < nb; ++j) {
-    const int bt = bt0 + j;
+    const int bt = b0 + w + j * cx;
     const int i = inx;
     const uint32_t o = onx;
     uint32_t pv[PB_S1_PF];
@@ -448,9 +455,8 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
     for (int u = 0; u < PB_S1_PF; ++u) pv[u] = pvn[u];
     int cntv = 0;
     if (tid < d.pb_nb1) {
-      const int g = hs[tid * nb1w + j];
-      gofs[tid] = g;
-      cntv = hs[tid * nb1w + j + 1] - g;
+      gofs[tid] = gnx;
+      cntv = enx - gnx;
     }
     const int ko = i >= 0 ? (int)(o & 0xFFu) : 0;
     const int c = i >= 0 ? ko + (int)(o >> 8) : 0;
@@ -487,7 +493,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       for (int q = 0; q < c; ++q) tag[ao + q] = (uint16_t)(tid | (q >= ko ? 0x8000 : 0));
     }
     __syncthreads();
-    if (j + 1 < nb) fetch(bt + 1, inx, onx, pvn);
+    if (j + 1 < nb) fetch(bt + cx, inx, onx, pvn, gnx, enx);
     auto place = [&](int k, uint32_t p) {
       const uint32_t tg = tag[k];
       const uint32_t net = (tg & 0x8000u) << 16;
