@@ -245,9 +245,24 @@ __device__ __forceinline__ float u01(uint32_t x) {
 // Kernels whose neighbouring workgroups write into the same cache lines (the ends of
 // short runs) use it, so that those lines are completed in one XCD's L2 instead of
 // leaving two partial copies to be written back from two.
-__device__ __forceinline__ int xcd_block(int b, int G) {
+__host__ __device__ inline int xcd_block(int b, int G) {
   const int x = b & 7, q = b >> 3, base = G >> 3, rem = G & 7;
-  return x * base + min(x, rem) + q;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
+// The batches of workgroup b of a grid of G (groups of bpw batches, nbt batches in all)
+// when one XCD's workgroups share its groups' batch range interleaved: the w-th of its
+// c workgroups takes the range's batches w, w + c, w + 2c, ...  Returns the first
+// batch, the stride and the count.
+struct Interleave {
+  int first, stride, count;
+};
+__host__ __device__ inline Interleave xcd_interleave(int b, int G, int bpw, int nbt) {
+  const int x = b & 7, w = b >> 3, base = G >> 3, rem = G & 7;
+  const int c = base + (x < rem ? 1 : 0), p = x * base + (x < rem ? x : rem);
+  const int b0 = p * bpw, end = (p + c) * bpw < nbt ? (p + c) * bpw : nbt;
+  const int n = end - b0 > w ? (end - b0 - w + c - 1) / c : 0;
+  return Interleave{b0 + w, c, n};
 }
 
 __device__ __forceinline__ int poisson_k(const uint32_t* T, uint32_t x) {

@@ -408,16 +408,14 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbt = d.pb_nbatch;
   // The batches of the workgroups that the dispatcher places on one XCD (it deals them
-  // out blockIdx mod 8) form one range, and its w-th workgroup takes batches w, w + cx,
-  // w + 2 cx, ... of it.  The workgroups running together on an XCD then place
+  // out blockIdx mod 8) form one range, and the w-th of its c workgroups takes batches
+  // w, w + c, w + 2c, ... of it (xcd_interleave).  The workgroups running together on an XCD then place
   // neighbouring batches at the same time, so the line where one batch's run for a
   // digit ends and the next batch's begins is completed in that XCD's L2 while both
   // are written, instead of staying open there until the next batch of the same
   // workgroup.
-  const int G = (int)gridDim.x, x = (int)(blockIdx.x & 7), w = (int)(blockIdx.x >> 3);
-  const int cx = (G >> 3) + (x < (G & 7) ? 1 : 0), px = x * (G >> 3) + min(x, G & 7);
-  const int b0 = px * d.pb_bpw, bx = min(nbt, (px + cx) * d.pb_bpw) - b0;
-  const int nb = bx > w ? (bx - w + cx - 1) / cx : 0;
+  const Interleave il = xcd_interleave((int)blockIdx.x, (int)gridDim.x, d.pb_bpw, nbt);
+  const int nb = il.count;
   // a batch's agent counts, its runs' offsets and the first PB_S1_PF rounds of its own
   // list are loaded one batch ahead, while the previous batch is sorted and written
   auto fetch = [&](int bt, int& i, uint32_t& o, uint32_t* pv, int& g, int& e) {
@@ -445,9 +443,9 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   };
   int inx, gnx = 0, enx = 0;
   uint32_t onx, pvn[PB_S1_PF];
-  if (nb > 0) fetch(b0 + w, inx, onx, pvn, gnx, enx);
+  if (nb > 0) fetch(il.first, inx, onx, pvn, gnx, enx);
   for (int j = 0; j < nb; ++j) {
-    const int bt = b0 + w + j * cx;
+    const int bt = il.first + j * il.stride;
     const int i = inx;
     const uint32_t o = onx;
     uint32_t pv[PB_S1_PF];
@@ -493,7 +491,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
       for (int q = 0; q < c; ++q) tag[ao + q] = (uint16_t)(tid | (q >= ko ? 0x8000 : 0));
     }
     __syncthreads();
-    if (j + 1 < nb) fetch(bt + cx, inx, onx, pvn, gnx, enx);
+    if (j + 1 < nb) fetch(bt + il.stride, inx, onx, pvn, gnx, enx);
     auto place = [&](int k, uint32_t p) {
       const uint32_t tg = tag[k];
       const uint32_t net = (tg & 0x8000u) << 16;
