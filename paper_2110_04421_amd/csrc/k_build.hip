@@ -731,7 +731,7 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   constexpr int NR = NT * TILE;
   extern __shared__ int32_t scol[];                  // [cap] staged edges
   __shared__ int cur[2 * NR];                        // (row, network): received count, then next position
-  __shared__ int wsum[NR / 64], wsum2[NR / 64];
+  __shared__ int wsum[NR / 64], wsum2[NR / 64], lsum[NR / 64];
   if (*d.flags) return;
   const int cap = d.pb_asm_cap;
   const int L = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -742,7 +742,6 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   const uint32_t* ob = d.pb_own + (size_t)(t0 >> 2) * d.pb_bcap + tb0.x;   // the leaf's own range
   const int lo = d.pb_leaf[L], hi = d.pb_leaf[L + 1];
   const int nreg = min(hi - lo, d.pb_rper * NR);
-  const int64_t b64 = d.pb_tpart[L / PB_TGRP] + d.pb_tstart[L];
   // the leaf's received entries, loaded with the rows' own data
   uint2 x[PB_ROWS_PER];
 #pragma unroll
@@ -766,7 +765,26 @@ __global__ __launch_bounds__(NT * TILE) void k_pb_rows(Dev d) {
   }
   const int dl = tix < d.ntiles ? slot_delta(d, tix) : 0;   // this row's replicate
   auto rkey = [](uint32_t v) { return (int)(((v & (NR - 1)) << 1) | (v >> 15)); };
-  __syncthreads();                                   // counters cleared
+  // The leaf's first edge: from the leaf scan, or, with one group of leaves (where that
+  // scan is not launched), the sum of the earlier leaves' edges, added up here.
+  const bool own_sum = d.pb_ntgrp == 1;
+  if (own_sum) {
+    const int nt = 1 << (d.pb_lb - 8);
+    int acc = 0;
+    for (int l2 = tid; l2 < L; l2 += NR) {
+      acc += d.pb_leaf[l2 + 1] - d.pb_leaf[l2];
+      for (int t = l2 * nt; t < min(l2 * nt + nt, d.ntiles); ++t) acc += d.pb_tdeg[t];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) lsum[wv] = acc;
+  }
+  __syncthreads();                                   // counters cleared, leaf sums written
+  int64_t b64 = 0;
+  if (own_sum) {
+    for (int q = 0; q < NR / 64; ++q) b64 += lsum[q];
+  } else {
+    b64 = d.pb_tpart[L / PB_TGRP] + d.pb_tstart[L];
+  }
 #pragma unroll
   for (int j = 0; j < PB_ROWS_PER; ++j)
     if (j * NR + tid < nreg) atomicAdd(&cur[rkey(x[j].x)], 1);
@@ -930,9 +948,11 @@ void launch_build_step(const Dev& d, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_pb_s2, dim3(d.pb_nb1), dim3(PB_S2_SCAN), 0, s, d);
       break;
     case 4: hipLaunchKernelGGL(k_pb_scatter2, dim3(d.pb_maxch), dim3(PB_S2_THREADS), 0, s, d); break;
-    case 5:
-      hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(PB_TGRP), 0, s, d);
-      if (d.pb_ntgrp > 1) hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
+    case 5:                                  // one group of leaves: the row pass sums
+      if (d.pb_ntgrp > 1) {
+        hipLaunchKernelGGL(k_pb_tsum, dim3(d.pb_ntgrp), dim3(PB_TGRP), 0, s, d);
+        hipLaunchKernelGGL(k_pb_parts, dim3(1), dim3(1024), 0, s, d.pb_tpart, d.pb_ntgrp);
+      }
       break;
     default:
       if (d.pb_lb == 9)
