@@ -1058,6 +1058,9 @@ __global__ __launch_bounds__(TILE) void k_fin_one(Dev d) {
   const RepInfo& ri = d.rep[r];
   const int t = *d.day;
   const bool ok = *d.flags == 0;
+  // the day's edge count, loaded before the tile rows so that its latency overlaps theirs
+  long long edges = 0;
+  if (threadIdx.x == ABM_C_EDGES) edges = (long long)d.row_ptr[ri.start + ri.n] - d.row_ptr[ri.start];
   unsigned long long acc[ABM_NC];
 #pragma unroll
   for (int c = 0; c < ABM_NC; ++c) acc[c] = 0ull;
@@ -1079,7 +1082,7 @@ __global__ __launch_bounds__(TILE) void k_fin_one(Dev d) {
   if (threadIdx.x < ABM_NC) {
     const int c = threadIdx.x;
     long long v = (long long)(part[0][c] + part[1][c] + part[2][c] + part[3][c]);
-    if (c == ABM_C_EDGES) v = ok ? (long long)d.row_ptr[ri.start + ri.n] - d.row_ptr[ri.start] : 0;
+    if (c == ABM_C_EDGES) v = ok ? edges : 0;
     if (c == ABM_C_INF_EDGES && !ok) v = 0;
     if (t < d.T) d.traj[((size_t)t * d.R + r) * ABM_NC + c] = v;
     d.prev_counts[(size_t)r * ABM_NC + c] = v;
