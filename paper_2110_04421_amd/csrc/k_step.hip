@@ -290,17 +290,16 @@ __device__ __forceinline__ bool sparse_day(const Dev& d) {
   return d.sparse_div > 0 && (int64_t)*d.ninf * d.sparse_div <= (int64_t)d.N;
 }
 
-// ---- vaccination plan: one workgroup per replicate ------------------------------------
-// Latch on prevalence, then give the day's capacity to the priority classes in order;
-// the first class that does not fit entirely gets a quota filled by ascending agent id
-// (exclusive prefix of its members over the replicate's tiles).
-// The day's vaccination plan of replicate r: from the day the prevalence latch fires,
-// the capacity goes to the priority classes in order; bstar is the class where it runs
-// out and quota the doses left for it, and each tile's first rank inside bstar is the
-// number of bstar agents in the replicate's earlier tiles.  Replicates of at most
-// VPLAN_ONE tiles take one workgroup (k_vplan); larger ones are summed per segment of
-// 256 tiles (k_vsum), planned (k_vplan_seg) and ranked per segment (k_vtile), so that
-// no workgroup walks a replicate's tiles one round after another.
+// ---- vaccination plan ----------------------------------------------------------------
+// The day's plan of replicate r: from the day the prevalence latch fires, the capacity
+// goes to the priority classes in order; bstar is the first class that does not fit
+// entirely and quota the doses left for it, filled by ascending agent id: each tile's
+// first rank inside bstar is the number of bstar agents in the replicate's earlier
+// tiles.  Replicates of at most 2048 tiles take one workgroup (k_vplan); larger ones
+// are summed per segment of 256 tiles (k_vsum), planned (k_vplan_seg) and ranked per
+// segment (k_vtile), so that no workgroup walks a replicate's tiles one round after
+// another.
+
 // Latched today: the latch fired before, or yesterday's prevalence reaches the trigger.
 __device__ __forceinline__ bool latched_today(const Dev& d, int r) {
   if (d.latch[r]) return true;
