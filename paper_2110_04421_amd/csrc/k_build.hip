@@ -229,13 +229,20 @@ __global__ __launch_bounds__(PB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
 // Level-1 order: q = digit * nbatch + batch, the storage order of hist1.
 __device__ __forceinline__ int* h1_at(const Dev& d, int64_t q) { return d.pb_hist1 + q; }
 
+static_assert(SCAN_ITEMS == 8, "the level-1 scan moves a lane's items as two 16-byte vectors");
 __global__ __launch_bounds__(TILE) void k_pb_s1a(Dev d) {
   __shared__ int red[TILE / 64];
   const int64_t n = (int64_t)d.pb_nb1 * d.pb_nbatch;
   const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
   int s = 0;
-  for (int k = 0; k < SCAN_ITEMS; ++k)
-    if (q0 + k < n) s += *h1_at(d, q0 + k);
+  if (q0 + SCAN_ITEMS <= n) {                // whole: two 16-byte loads (q0 is a multiple of 8)
+    const int4* p = reinterpret_cast<const int4*>(h1_at(d, q0));
+    const int4 a = p[0], b = p[1];
+    s = (a.x + a.y) + (a.z + a.w) + (b.x + b.y) + (b.z + b.w);
+  } else {
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+      if (q0 + k < n) s += *h1_at(d, q0 + k);
+  }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -280,10 +287,16 @@ __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
   const int64_t q0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
   int s = 0;
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = q0 + k < n ? *h1_at(d, q0 + k) : 0;
-    s += v[k];
+  const bool whole = q0 + SCAN_ITEMS <= n;   // two 16-byte loads and stores (q0 is a multiple of 8)
+  if (whole) {
+    const int4* p = reinterpret_cast<const int4*>(h1_at(d, q0));
+    const int4 a = p[0], b = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = q0 + k < n ? *h1_at(d, q0 + k) : 0;
   }
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int inc = s;
   for (int o = 1; o < 64; o <<= 1) {
@@ -295,9 +308,18 @@ __global__ __launch_bounds__(TILE) void k_pb_s1c(Dev d) {
   int wb = 0;
   for (int k = 0; k < wv; ++k) wb += wsum[k];
   int64_t run = d.pb_part[blockIdx.x] + wb + inc - s;
+  int ex[SCAN_ITEMS];
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (q0 + k < n) *h1_at(d, q0 + k) = (int)run;
+    ex[k] = (int)run;
     run += v[k];
+  }
+  if (whole) {
+    int4* p = reinterpret_cast<int4*>(h1_at(d, q0));
+    p[0] = make_int4(ex[0], ex[1], ex[2], ex[3]);
+    p[1] = make_int4(ex[4], ex[5], ex[6], ex[7]);
+  } else {
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+      if (q0 + k < n) *h1_at(d, q0 + k) = ex[k];
   }
 }
 
