@@ -20,7 +20,7 @@ constexpr int TILE_NC = 16;       // per-tile count row (ABM_NC slots, padded)
 static_assert(ABM_NC <= TILE_NC, "count slots fit a tile row");
 constexpr size_t SCMASK_LDS_MAX = 48 * 1024;   // largest LDS copy of the super-coarse mask
 constexpr int PB_S1_CAP = 12288;  // entries of a batch staged in LDS by the level-1 scatter
-constexpr int PB_HS_MAX = 4608;   // level-1 run offsets a P2 workgroup keeps in LDS (digits x (batches + 1))
+constexpr int PB_HS_MAX = 4608;   // bound on digits x (batches a workgroup + 1): sizes the P1 LDS histograms
 constexpr int SPARSE_DIV = 256;
 constexpr int64_t FRONT_MIN_N = 1 << 20;   // smallest population that takes the frontier path
 constexpr int FRONT_NB = 1024;     // lists of flagged rows (256-agent group mod FRONT_NB): spread counters    // frontier force of infection with <= N/256 infectious agents

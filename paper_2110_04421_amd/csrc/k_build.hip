@@ -431,11 +431,11 @@ __global__ __launch_bounds__(PB_THREADS) void k_pb_scatter1(Dev d) {
   const int nbt = d.pb_nbatch;
   // The batches of the workgroups that the dispatcher places on one XCD (it deals them
   // out blockIdx mod 8) form one range, and the w-th of its c workgroups takes batches
-  // w, w + c, w + 2c, ... of it (xcd_interleave).  The workgroups running together on an XCD then place
-  // neighbouring batches at the same time, so the line where one batch's run for a
-  // digit ends and the next batch's begins is completed in that XCD's L2 while both
-  // are written, instead of staying open there until the next batch of the same
-  // workgroup.
+  // w, w + c, w + 2c, ... of it (xcd_interleave).  The workgroups running together on
+  // an XCD then place neighbouring batches at the same time, so the line where one
+  // batch's run for a digit ends and the next batch's begins is completed in that
+  // XCD's L2 while both are written, instead of staying open there until the next
+  // batch of the same workgroup.
   const Interleave il = xcd_interleave((int)blockIdx.x, (int)gridDim.x, d.pb_bpw, nbt);
   const int nb = il.count;
   // a batch's agent counts, its runs' offsets and the first PB_S1_PF rounds of its own
